@@ -1,0 +1,401 @@
+/*
+ * cuesim_oracle.c -- FP64 CPU oracle of one time step of the cue-diffusion axon-guidance
+ * simulation (Mihut, Morgan & Kaiser 2014, "GPU Simulation of Axon Growth and Guidance
+ * through Cue Diffusion").
+ *
+ * TEST INFRASTRUCTURE ONLY: the plain, slow reference that the GPU library is checked
+ * against.  Tests, the smoke check and the CPU-baseline leg of the benchmark load it; the
+ * product path never does.  It shares no code with the GPU library.
+ *
+ * A time step has two parts, in this order (Sec. 1: growth per neuron each time step as an
+ * independent process; Sec. 3.5: the cue environment drives the steering):
+ *   F1  explicit finite-difference diffusion of every cue species with first-order decay,
+ *       zero-flux walls (a neighbour outside the grid is replaced by the cell itself);
+ *   F2  point sources add their per-step amount q / dx^dim to their cell;
+ *   C1  each active growth cone samples the cue gradient at its tip: central differences at
+ *       cell centres, interpolated multilinearly to the tip, summed over species with sign;
+ *   C2  deterministic turn toward the direction of (heading + gain * gradient) -- the
+ *       vector-addition steering of Sec. 3.5, Eqs. 6-7, where the turn angle follows from
+ *       the dot product (cosine) and cross product (sine) -- capped at pi/30 per step, the
+ *       turn magnitude Sec. 3.5 fixes;
+ *   C3  angular noise from a counter-based, stateless Philox stream keyed by
+ *       (cone, step, tag, simulation), the per-thread generator style Sec. 5.1 recommends;
+ *   C4  advance a fixed distance per step along the heading (Sec. 3.5 steering);
+ *   C5  a cone that leaves the simulation bounds stops (Sec. 3.4);
+ *   C6  contact: squared distance strictly below the squared radius (Sec. 3.3 sphere test),
+ *       nearest target wins, lowest index on an exact tie; the cone stops there (Sec. 3.4).
+ *
+ * Readings where the paper is silent (grid centring, decay discretisation, source units,
+ * gain, noise law, exit-before-contact, no contact test at t = 0) are the ones documented
+ * with the design; every rule above is executed literally, in FP64, with no blocking or
+ * reordering.
+ */
+#include "cuesim_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy as      */
+/* 1, 2, 3", SC'11).  Round: two 32x32->64 multiplies of counter words 0 and 2 by the    */
+/* published multipliers; the high halves are xored with the other two words and the    */
+/* key.  The key is bumped by the published Weyl constants between rounds.               */
+/* ------------------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t mul0 = 0xD2511F53u, mul1 = 0xCD9E8D57u;
+    const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)mul0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)mul1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += weyl0;
+        k1 += weyl1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform in (0,1) from the top 24 bits, centred in its bin: exactly representable in
+ * both FP32 and FP64, so every implementation sees the same uniform. */
+static double uniform24(uint32_t x)
+{
+    return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+}
+
+void oracle_normals4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                     double z[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    oracle_philox4x32_10(ctr, key, x);
+    /* Box-Muller: radius from the first uniform of a pair, angle from the second. */
+    for (int pair = 0; pair < 2; ++pair) {
+        double u_r = uniform24(x[2 * pair]);
+        double u_a = uniform24(x[2 * pair + 1]);
+        double radius = sqrt(-2.0 * log(u_r));
+        z[2 * pair] = radius * cos(2.0 * ORACLE_PI * u_a);
+        z[2 * pair + 1] = radius * sin(2.0 * ORACLE_PI * u_a);
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Grid helpers.                                                                          */
+/* ------------------------------------------------------------------------------------ */
+static int64_t n_cells(const oracle_params* p)
+{
+    return (int64_t)p->nx * p->ny * (p->dim == 3 ? p->nz : 1);
+}
+
+static int axis_size(const oracle_params* p, int a)
+{
+    return a == 0 ? p->nx : (a == 1 ? p->ny : p->nz);
+}
+
+static int64_t cell_index(const oracle_params* p, const int idx[3])
+{
+    int64_t l = p->dim == 3 ? idx[2] : 0;
+    return (l * p->ny + idx[1]) * p->nx + idx[0];
+}
+
+/* Value of the neighbour of cell idx one step along axis a in direction d (+1/-1); a
+ * neighbour outside the grid is the cell itself (zero-flux wall). */
+static double neighbour(const oracle_params* p, const double* c, const int idx[3], int a, int d)
+{
+    int nb[3] = {idx[0], idx[1], idx[2]};
+    nb[a] += d;
+    if (nb[a] < 0 || nb[a] >= axis_size(p, a))
+        return c[cell_index(p, idx)];
+    return c[cell_index(p, nb)];
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* F1 + F2: field update.                                                                 */
+/* ------------------------------------------------------------------------------------ */
+void oracle_field_step(const oracle_params* p, const double* const in[2], double* const out[2])
+{
+    const int nz = p->dim == 3 ? p->nz : 1;
+    const double cell_volume = pow(p->dx, p->dim);
+    for (int s = 0; s < p->n_species; ++s) {
+        const double r = p->D[s] * p->dt / (p->dx * p->dx);
+        const double kdt = p->k[s] * p->dt;
+        const double* c = in[s];
+        double* c_new = out[s];
+        /* F1: c' = c + r * sum_axes (c[+e] + c[-e] - 2c) - k dt c */
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int l = 0; l < nz; ++l) {
+            for (int j = 0; j < p->ny; ++j) {
+                for (int i = 0; i < p->nx; ++i) {
+                    int idx[3] = {i, j, l};
+                    double centre = c[cell_index(p, idx)];
+                    double laplacian_sum = 0.0;
+                    for (int a = 0; a < p->dim; ++a)
+                        laplacian_sum += neighbour(p, c, idx, a, +1) + neighbour(p, c, idx, a, -1)
+                                         - 2.0 * centre;
+                    c_new[cell_index(p, idx)] = centre + r * laplacian_sum - kdt * centre;
+                }
+            }
+        }
+        /* F2: each source adds its per-step amount, spread over its cell's volume. */
+        for (int m = 0; m < p->n_sources[s]; ++m)
+            c_new[p->source_cell[s][m]] += p->source_q[s][m] / cell_volume;
+    }
+}
+
+double oracle_mass(const oracle_params* p, const double* field)
+{
+    double total = 0.0;
+    int64_t n = n_cells(p);
+    for (int64_t x = 0; x < n; ++x)
+        total += field[x];
+    return total * pow(p->dx, p->dim);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* C1: gradient sampling.                                                                 */
+/* ------------------------------------------------------------------------------------ */
+
+/* Central-difference gradient component along axis a at the centre of cell idx. */
+static double centre_gradient(const oracle_params* p, const double* c, const int idx[3], int a)
+{
+    return (neighbour(p, c, idx, a, +1) - neighbour(p, c, idx, a, -1)) / (2.0 * p->dx);
+}
+
+void oracle_sample_gradient(const oracle_params* p, const double* field, const double* point,
+                            double g[3])
+{
+    int base[3] = {0, 0, 0};
+    double frac[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < p->dim; ++a) {
+        /* Cell centres sit at (i + 1/2) dx: u is the tip in units of cell-centre spacing. */
+        int n = axis_size(p, a);
+        double u = point[a] / p->dx - 0.5;
+        if (u < 0.0) u = 0.0;
+        if (u > (double)(n - 1)) u = (double)(n - 1);
+        int i0 = (int)floor(u);
+        if (i0 > n - 2) i0 = n - 2;
+        base[a] = i0;
+        frac[a] = u - (double)i0;
+    }
+    g[0] = g[1] = g[2] = 0.0;
+    int corners = 1 << p->dim;
+    for (int corner = 0; corner < corners; ++corner) {
+        int idx[3] = {0, 0, 0};
+        double weight = 1.0;
+        for (int a = 0; a < p->dim; ++a) {
+            int upper = (corner >> a) & 1;
+            idx[a] = base[a] + upper;
+            weight *= upper ? frac[a] : (1.0 - frac[a]);
+        }
+        for (int a = 0; a < p->dim; ++a)
+            g[a] += weight * centre_gradient(p, field, idx, a);
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* C2-C6: one cone step.                                                                  */
+/* ------------------------------------------------------------------------------------ */
+static double domain_length(const oracle_params* p, int a)
+{
+    return (double)axis_size(p, a) * p->dx;
+}
+
+/* C2 (2D): rotate heading angle theta toward theta + angle(h + gain*g), capped. */
+static double turn_2d(const oracle_params* p, double theta, const double g[3], int* ambiguous)
+{
+    double hx = cos(theta), hy = sin(theta);
+    double cross = hx * g[1] - hy * g[0];      /* sine part (Sec. 3.5, Eq. 7 discussion) */
+    double dot = hx * g[0] + hy * g[1];        /* cosine part */
+    double y = p->turn_gain * cross;
+    double x = 1.0 + p->turn_gain * dot;
+    if (y == 0.0) y = 0.0;                     /* -0 -> +0: anti-parallel turns by +cap */
+    if (x < 0.0 && fabs(y) <= 1e-5 * fabs(x)) *ambiguous = 1;
+    double delta = atan2(y, x);
+    if (delta > p->max_turn) delta = p->max_turn;
+    if (delta < -p->max_turn) delta = -p->max_turn;
+    return theta + delta;
+}
+
+/* C2 (3D): rotate h toward h + gain*g in the plane they span, by at most max_turn. */
+static void turn_3d(const oracle_params* p, double h[3], const double g[3], int* ambiguous)
+{
+    double along = g[0] * h[0] + g[1] * h[1] + g[2] * h[2];
+    double perp[3] = {g[0] - along * h[0], g[1] - along * h[1], g[2] - along * h[2]};
+    double perp_norm = sqrt(perp[0] * perp[0] + perp[1] * perp[1] + perp[2] * perp[2]);
+    double x = 1.0 + p->turn_gain * along;
+    if (x < 0.0 && p->turn_gain * perp_norm <= 1e-5 * fabs(x)) *ambiguous = 1;
+    if (perp_norm == 0.0)
+        return;
+    double phi = atan2(p->turn_gain * perp_norm, x);
+    if (phi > p->max_turn) phi = p->max_turn;
+    double c = cos(phi), s = sin(phi);
+    for (int a = 0; a < 3; ++a)
+        h[a] = c * h[a] + s * perp[a] / perp_norm;
+}
+
+/* C3 (3D): tangent-plane Gaussian rotation of h, then renormalisation. */
+static void noise_3d(const oracle_params* p, double h[3], const double z[4])
+{
+    double along = z[0] * h[0] + z[1] * h[1] + z[2] * h[2];
+    double w[3];
+    for (int a = 0; a < 3; ++a)
+        w[a] = p->noise_sigma * (z[a] - along * h[a]);
+    double angle = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (angle > 0.0) {
+        double c = cos(angle), s = sin(angle);
+        for (int a = 0; a < 3; ++a)
+            h[a] = c * h[a] + s * w[a] / angle;
+    }
+    double norm = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+    for (int a = 0; a < 3; ++a)
+        h[a] /= norm;
+}
+
+static void step_one_cone(const oracle_params* p, oracle_state* s, int i,
+                          const double* const fields[2])
+{
+    const int dim = p->dim;
+    const int64_t n = s->step;        /* the step being taken is n -> n+1 */
+    double* pos = s->pos + (int64_t)i * dim;
+    int ambiguous = 0;
+
+    /* C1: signed sum of the species' interpolated gradients. */
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int sp = 0; sp < p->n_species; ++sp) {
+        double gs[3];
+        oracle_sample_gradient(p, fields[sp], pos, gs);
+        for (int a = 0; a < dim; ++a)
+            g[a] += p->sign[sp] * gs[a];
+    }
+
+    /* C2 + C3: turn, then noise keyed by (cone, step, tag 0, simulation). */
+    double z[4];
+    oracle_normals4(p->seed, (uint32_t)i, (uint32_t)n, 0u, p->sim_index, z);
+    for (int q = 0; q < 4; ++q)
+        z[q] *= p->noise_sign;
+    double h[3];
+    if (dim == 2) {
+        double theta = turn_2d(p, s->dir[i], g, &ambiguous);
+        theta += p->noise_sigma * z[0];
+        theta -= 2.0 * ORACLE_PI * floor((theta + ORACLE_PI) / (2.0 * ORACLE_PI));
+        s->dir[i] = theta;
+        h[0] = cos(theta);
+        h[1] = sin(theta);
+        h[2] = 0.0;
+    } else {
+        double* hd = s->dir + (int64_t)i * 3;
+        turn_3d(p, hd, g, &ambiguous);
+        noise_3d(p, hd, z);
+        h[0] = hd[0]; h[1] = hd[1]; h[2] = hd[2];
+    }
+
+    /* C4: advance a fixed distance. */
+    for (int a = 0; a < dim; ++a)
+        pos[a] += p->step_len * h[a];
+
+    /* Near-tie margins (recorded only; they do not change the trajectory). */
+    for (int a = 0; a < dim; ++a) {
+        double L = domain_length(p, a);
+        if (fabs(pos[a]) <= p->flag_tol || fabs(L - pos[a]) <= p->flag_tol)
+            ambiguous = 1;
+    }
+
+    /* C5: leaving the simulation bounds stops the cone (checked before contact). */
+    int outside = 0;
+    for (int a = 0; a < dim; ++a)
+        if (pos[a] < 0.0 || pos[a] >= domain_length(p, a))
+            outside = 1;
+    if (outside) {
+        s->status[i] = ORACLE_EXITED;
+        s->event_step[i] = (int32_t)(n + 1);
+    } else {
+        /* C6: strict squared-distance test against every target (brute force). */
+        const double R = p->contact_radius;
+        double best_d2 = INFINITY, second_d = INFINITY, best_d = INFINITY;
+        int best = -1;
+        for (int t = 0; t < p->n_targets; ++t) {
+            const double* tp = p->target_pos + (int64_t)t * dim;
+            double d2 = 0.0;
+            for (int a = 0; a < dim; ++a)
+                d2 += (pos[a] - tp[a]) * (pos[a] - tp[a]);
+            double d = sqrt(d2);
+            if (fabs(d - R) <= p->flag_tol)
+                ambiguous = 1;
+            if (d < R + p->flag_tol) {
+                if (d < best_d) { second_d = best_d; best_d = d; }
+                else if (d < second_d) second_d = d;
+            }
+            if (d2 < best_d2) {        /* strict: the lowest index wins an exact tie */
+                best_d2 = d2;
+                best = t;
+            }
+        }
+        if (second_d - best_d <= p->flag_tol)
+            ambiguous = 1;
+        if (best >= 0 && best_d2 < R * R) {
+            s->status[i] = ORACLE_CONTACT;
+            s->target[i] = best;
+            s->event_step[i] = (int32_t)(n + 1);
+        }
+    }
+    if (ambiguous && s->flag_step[i] < 0)
+        s->flag_step[i] = (int32_t)(n + 1);
+}
+
+void oracle_cone_step(const oracle_params* p, oracle_state* s)
+{
+    const double* fields[2] = {s->field[0], s->field[1]};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < s->n_cones; ++i)
+        if (s->status[i] == ORACLE_ACTIVE)
+            step_one_cone(p, s, i, fields);
+}
+
+int oracle_run(const oracle_params* p, oracle_state* s, int64_t n_steps)
+{
+    const int64_t cells = n_cells(p);
+    double* scratch[2] = {NULL, NULL};
+    for (int sp = 0; sp < p->n_species; ++sp) {
+        scratch[sp] = (double*)malloc((size_t)cells * sizeof(double));
+        if (!scratch[sp]) {
+            free(scratch[0]);
+            return -1;
+        }
+    }
+    for (int64_t it = 0; it < n_steps; ++it) {
+        const double* in[2] = {s->field[0], s->field[1]};
+        double* out[2] = {scratch[0], scratch[1]};
+        oracle_field_step(p, in, out);
+        for (int sp = 0; sp < p->n_species; ++sp)
+            memcpy(s->field[sp], scratch[sp], (size_t)cells * sizeof(double));
+        oracle_cone_step(p, s);
+        s->step += 1;
+    }
+    free(scratch[0]);
+    free(scratch[1]);
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

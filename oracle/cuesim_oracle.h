@@ -1,0 +1,86 @@
+/*
+ * cuesim_oracle.h -- FP64 CPU oracle of the cue-diffusion / growth-cone time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct simulator that
+ * the GPU library is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header, table or
+ * helper with the GPU library.
+ *
+ * Every array is owned by the caller.  Fields are row-major with x fastest:
+ *   index(i, j, l) = (l * ny + j) * nx + i        (l = 0, nz = 1 in 2D).
+ * Cone headings: 2D -> one angle in radians per cone, wrapped to [-pi, pi);
+ *                3D -> one unit vector (hx, hy, hz) per cone.
+ */
+#ifndef CUESIM_ORACLE_H
+#define CUESIM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORACLE_ACTIVE = 0, ORACLE_CONTACT = 1, ORACLE_EXITED = 2 };
+
+typedef struct oracle_params {
+    int32_t dim;                 /* 2 or 3 */
+    int32_t nx, ny, nz;          /* cells per axis (nz = 1 in 2D) */
+    double dx, dt;
+    int32_t n_species;           /* 1 or 2 */
+    double D[2], k[2], sign[2];  /* diffusion, first-order decay, +1 attract / -1 repel */
+    int32_t n_sources[2];
+    const int32_t* source_cell[2];  /* linear cell index per source */
+    const double* source_q[2];      /* amount emitted per step */
+    int32_t n_targets;
+    const double* target_pos;    /* [T][dim] */
+    double contact_radius;
+    double step_len, turn_gain, max_turn, noise_sigma;
+    uint64_t seed;
+    uint32_t sim_index;
+    double noise_sign;           /* +1 normally; -1 negates every normal deviate (mirror test) */
+    double flag_tol;             /* near-tie margin tau for the flag record */
+} oracle_params;
+
+typedef struct oracle_state {
+    int64_t step;                /* completed steps n */
+    double* field[2];            /* n_cells doubles per species */
+    int32_t n_cones;
+    double* pos;                 /* [M][dim] */
+    double* dir;                 /* 2D: [M] angle; 3D: [M][3] unit vector */
+    int32_t* status;             /* ORACLE_ACTIVE / CONTACT / EXITED */
+    int32_t* target;             /* contacted target, -1 if none */
+    int32_t* event_step;         /* step at which status changed, -1 if none */
+    int32_t* flag_step;          /* first step with a near-tie margin <= flag_tol, -1 if none */
+} oracle_state;
+
+/* Philox4x32-10 bijection (Salmon et al., SC'11). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Four standard normal deviates from one Philox block by Box-Muller on 24-bit uniforms. */
+void oracle_normals4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                     double z[4]);
+
+/* Interpolated cue gradient of one field at point p (the gradient-sampling rule). */
+void oracle_sample_gradient(const oracle_params* p, const double* field, const double* point,
+                            double g[3]);
+
+/* One field update of every species (stencil + decay, then sources): in -> out. */
+void oracle_field_step(const oracle_params* p, const double* const in[2], double* const out[2]);
+
+/* One step of every active cone against the already-updated fields (state->step = n
+ * before the call; the cone part of step n -> n+1).  Does not advance state->step. */
+void oracle_cone_step(const oracle_params* p, oracle_state* s);
+
+/* n_steps full steps: field update, then cones.  Returns 0, or -1 on allocation failure. */
+int oracle_run(const oracle_params* p, oracle_state* s, int64_t n_steps);
+
+/* Total cue amount sum(c) * dx^dim of one species. */
+double oracle_mass(const oracle_params* p, const double* field);
+
+/* Number of OpenMP threads the oracle's loops use (1 when built without OpenMP). */
+int oracle_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
