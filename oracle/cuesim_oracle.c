@@ -70,11 +70,12 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* Uniform in (0,1) from the top 24 bits, centred in its bin: exactly representable in
- * both FP32 and FP64, so every implementation sees the same uniform. */
-static double uniform24(uint32_t x)
+/* Uniform in (0,1) from the top 23 bits, centred in its bin: (2m + 1) * 2^-24 with
+ * m < 2^23 needs 24 significant bits, so it is exact in FP32 as well as FP64 and every
+ * implementation sees the same uniform. */
+static double uniform23(uint32_t x)
 {
-    return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+    return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0);
 }
 
 void oracle_normals4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -86,8 +87,8 @@ void oracle_normals4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint3
     oracle_philox4x32_10(ctr, key, x);
     /* Box-Muller: radius from the first uniform of a pair, angle from the second. */
     for (int pair = 0; pair < 2; ++pair) {
-        double u_r = uniform24(x[2 * pair]);
-        double u_a = uniform24(x[2 * pair + 1]);
+        double u_r = uniform23(x[2 * pair]);
+        double u_a = uniform23(x[2 * pair + 1]);
         double radius = sqrt(-2.0 * log(u_r));
         z[2 * pair] = radius * cos(2.0 * ORACLE_PI * u_a);
         z[2 * pair + 1] = radius * sin(2.0 * ORACLE_PI * u_a);

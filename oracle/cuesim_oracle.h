@@ -56,7 +56,7 @@ typedef struct oracle_state {
 /* Philox4x32-10 bijection (Salmon et al., SC'11). */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
-/* Four standard normal deviates from one Philox block by Box-Muller on 24-bit uniforms. */
+/* Four standard normal deviates from one Philox block by Box-Muller on 23-bit uniforms. */
 void oracle_normals4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                      double z[4]);
 
