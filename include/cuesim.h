@@ -1,0 +1,161 @@
+/*
+ * cuesim.h -- C ABI of the MI355X (gfx950) cue-diffusion / growth-cone simulator.
+ *
+ * The library advances the data-parallel hot path of the axon-guidance simulation of
+ * Mihut, Morgan & Kaiser (2014): every time step first updates the guidance-cue
+ * environment, then moves every growth cone one independent step (Sec. 1: growth per
+ * neuron each time step as a parallel, independent process; Sec. 3.5: cue-diffusion
+ * guidance).  Concretely, one step n -> n+1 is:
+ *
+ *   1. each cue species s: c' = c + r * sum_axes(c[+e] + c[-e] - 2c) - k dt c,
+ *      r = D dt / dx^2 (5-point stencil in 2D, 7-point in 3D), with zero-flux walls: a
+ *      neighbour outside the grid is replaced by the cell itself;
+ *   2. each point source adds q / dx^dim to its cell;
+ *   3. each ACTIVE cone samples g = sum_s sign_s * grad c_s at its tip (central differences
+ *      at cell centres, bilinear / trilinear interpolation to the tip; cell (i,j[,l]) has
+ *      its centre at ((i+1/2)dx, (j+1/2)dx[, (l+1/2)dx]));
+ *   4. turns its heading toward the direction of h + turn_gain * g (the vector-addition
+ *      steering of Sec. 3.5, Eqs. 6-7: angle from the dot and cross products), by at most
+ *      max_turn (pi/30 in Sec. 3.5);
+ *   5. adds angular noise: four normal deviates from Philox4x32-10 with
+ *      key = (seed lo, seed hi), counter = (original cone index, n, 0, sim_index), by
+ *      Box-Muller on uniforms ((x >> 9) + 0.5) * 2^-23 (the stateless per-thread generator
+ *      style of Sec. 5.1).  2D: theta += noise_sigma * Z0, wrapped to [-pi, pi).  3D: h is
+ *      rotated by |w| toward w = noise_sigma * (z - (z.h) h), z = (Z0, Z1, Z2), then
+ *      renormalised;
+ *   6. advances step_len along the heading (a fixed distance per step, Sec. 3.5);
+ *   7. stops as EXITED (event step n+1) if it left [0, n_a dx) on any axis (Sec. 3.4);
+ *   8. otherwise stops as CONTACT (event step n+1) if its squared distance to some target
+ *      is strictly below contact_radius^2 (the sphere test of Sec. 3.3); the nearest target
+ *      is recorded, the lowest index on an exact tie.
+ *
+ * Arithmetic is FP32 on the device.  All entry points return a sim_status and never abort
+ * or throw across the ABI.  Handles are not thread-safe: calls on one handle must not
+ * overlap; different handles are independent.
+ */
+#ifndef CUESIM_H
+#define CUESIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sim_status {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,   /* bad argument: NULL pointer, size, non-finite value, bad item */
+    SIM_ECFL = -2,     /* unstable or non-positive scheme: D dt/dx^2 > 1/(2 dim) or
+                          2 dim D dt/dx^2 + k dt > 1 for some species */
+    SIM_ENOMEM = -3,   /* device or host allocation failed */
+    SIM_EDEVICE = -4,  /* a HIP call failed; see sim_last_error */
+    SIM_ERANGE = -5,   /* destination buffer too small (bytes_written = size needed) */
+    SIM_ESTATE = -6    /* the handle hit a sticky device error earlier: only
+                          sim_last_error and sim_destroy remain usable */
+} sim_status;
+
+/* Cone status codes (CONE_STATUS items and the kind column of EVENTS). */
+enum { SIM_CONE_ACTIVE = 0, SIM_CONE_CONTACT = 1, SIM_CONE_EXITED = 2 };
+
+typedef enum sim_item {
+    SIM_FIELD = 0,           /* float[cells] of species `index`, x fastest        (r/w) */
+    SIM_CONE_POS = 1,        /* float[M][dim]                                      (r/w) */
+    SIM_CONE_DIR = 2,        /* 2D: float[M] angle in [-pi, pi); 3D: float[M][3]  (r/w) */
+    SIM_CONE_STATUS = 3,     /* int32[M] SIM_CONE_*                                (r/w) */
+    SIM_CONE_TARGET = 4,     /* int32[M] contacted target index, -1 if none        (r/w) */
+    SIM_CONE_EVENT_STEP = 5, /* int32[M] step at which the cone stopped, -1        (r/w) */
+    SIM_EVENTS = 6,          /* int32[E][4] (cone, target, step, kind) sorted by
+                                (step, cone); one row per stopped cone             (r)   */
+    SIM_MASS = 7,            /* double[n_species]: sum(c) dx^dim, FP64 accumulation (r)  */
+    SIM_STEP = 8,            /* int64[1] completed steps                           (r/w) */
+    SIM_COUNTS = 9,          /* int32[3]: active, contact, exited                  (r)   */
+    SIM_KERNEL_TIME = 10     /* double[2]: summed device milliseconds and number of
+                                launches of the step kernel since timing was last
+                                enabled (see sim_set_timing)                       (r)   */
+} sim_item;
+
+#define SIM_MAX_SPECIES 2
+
+/*
+ * Simulation parameters.  Every array is read during sim_create and copied; the caller
+ * keeps ownership and may free it when sim_create returns.  Arrays are host pointers.
+ */
+typedef struct sim_params {
+    uint32_t struct_size;              /* = sizeof(sim_params) */
+    int32_t dim;                       /* 2 or 3 */
+    int32_t nx, ny, nz;                /* cells per axis, each >= 2 (nz ignored in 2D) */
+    double dx, dt;                     /* cell side and time step, > 0 */
+    int32_t n_species;                 /* 1 or 2 */
+    double D[SIM_MAX_SPECIES];         /* diffusion coefficient >= 0 */
+    double k[SIM_MAX_SPECIES];         /* first-order decay rate >= 0 */
+    double sign[SIM_MAX_SPECIES];      /* weight of the species in g: +1 attract, -1 repel */
+    int32_t n_sources[SIM_MAX_SPECIES];
+    const int32_t* source_cell[SIM_MAX_SPECIES];  /* linear cell index (x fastest) */
+    const float* source_q[SIM_MAX_SPECIES];       /* amount added per step */
+    const float* init_field[SIM_MAX_SPECIES];     /* NULL = zero field */
+    int32_t n_cones;                   /* M >= 0 */
+    const float* cone_pos;             /* [M][dim], inside [0, n_a dx) */
+    const float* cone_dir;             /* 2D: [M] angle; 3D: [M][3] unit vectors */
+    int32_t n_targets;                 /* T >= 0 */
+    const float* target_pos;           /* [T][dim] */
+    double contact_radius;             /* >= 0 */
+    double step_len;                   /* >= 0 */
+    double turn_gain;                  /* finite */
+    double max_turn;                   /* in [0, pi] */
+    double noise_sigma;                /* >= 0, radians */
+    uint64_t seed;
+    uint32_t sim_index;                /* fourth Philox counter word */
+    int32_t block_steps;               /* steps fused into one launch of the tiled kernel;
+                                          0 = library default, 1 = one kernel sequence per
+                                          step (no temporal blocking), max 32 */
+} sim_params;
+
+typedef struct sim_handle sim_handle;
+
+/* Validate *p, allocate device state on the current HIP device and upload it.  hip_stream
+ * is the hipStream_t every later operation is enqueued on (NULL: a stream the library
+ * creates and owns).  On success *out owns the simulation until sim_destroy; on failure
+ * *out = NULL and sim_last_error(NULL) describes the problem. */
+sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out);
+
+/* Enqueue n_steps >= 0 time steps on the handle's stream and return without waiting. */
+sim_status sim_step(sim_handle* h, int64_t n_steps);
+
+/* Wait for the stream, then copy `what` (species `index` for FIELD, else 0) into the
+ * caller's host buffer dst of dst_bytes.  Cones come back in the caller's original order.
+ * *bytes_written (may be NULL) receives the size of the item; SIM_ERANGE if dst_bytes is
+ * smaller (nothing is copied). */
+sim_status sim_read_state(sim_handle* h, sim_item what, int32_t index, void* dst,
+                          size_t dst_bytes, size_t* bytes_written);
+
+/* Wait for the stream, then replace `what` from the caller's host buffer src (bytes must
+ * equal the item size).  Used to restart from a saved or externally computed state. */
+sim_status sim_write_state(sim_handle* h, sim_item what, int32_t index, const void* src,
+                           size_t bytes);
+
+/* Non-owning device pointer to the current FIELD of species `index` (float[cells]),
+ * valid until the next sim_step / sim_write_state / sim_destroy on the handle. */
+sim_status sim_device_ptr(sim_handle* h, sim_item what, int32_t index, void** dev_ptr,
+                          size_t* bytes);
+
+/* Enable (1) or disable (0) HIP-event timing of every launch of the step kernel (the
+ * tiled kernel, or the stencil kernel when block_steps = 1); enabling resets the totals
+ * read back through SIM_KERNEL_TIME. */
+sim_status sim_set_timing(sim_handle* h, int32_t enable);
+
+/* Block until all work enqueued on the handle's stream has finished. */
+sim_status sim_synchronize(sim_handle* h);
+
+/* Release all resources; NULL is a no-op.  Returns SIM_EDEVICE if a HIP call failed
+ * (resources are released regardless). */
+sim_status sim_destroy(sim_handle* h);
+
+/* Message for the last failed call on h, or for the calling thread's last failed
+ * sim_create when h is NULL.  Library-owned, valid until the next call on h. */
+const char* sim_last_error(const sim_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,284 @@
+// device.hpp -- device-side pieces of one time step shared by every gfx950 kernel:
+// counter-based noise, gradient sampling, the cone turn / advance / exit / contact rule.
+// FP32 throughout.  Field access goes through an accessor so the same cone arithmetic
+// runs on HBM-resident fields and on LDS tiles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cuesim {
+
+constexpr int kActive = 0;
+constexpr int kContact = 1;
+constexpr int kExited = 2;
+
+// ------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of the 4x32 S-box, the
+// key advanced by the Weyl increments between rounds.  Counter-based and stateless, so
+// every cone draws its own stream with no per-thread state in memory (Sec. 5.1).
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = 0xD2511F53u * c.x, a_hi = __umulhi(0xD2511F53u, c.x);
+        const uint32_t b = 0xCD9E8D57u * c.z, b_hi = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(b_hi ^ c.y ^ k0, b, a_hi ^ c.w ^ k1, a);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// (2m + 1) * 2^-24 with m the top 23 bits: exact in FP32.
+__device__ __forceinline__ float unit_open(uint32_t x) {
+    return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;
+}
+
+struct NoiseKey {
+    uint32_t k0, k1;       // seed low / high word
+    uint32_t sim_index;    // fourth counter word
+};
+
+// Box-Muller pairs (Z0, Z1) from (u0, u1) and (Z2, Z3) from (u2, u3).  count selects how
+// many deviates are needed (1 in 2D, 3 in 3D).
+template <int count>
+__device__ __forceinline__ void normals(const NoiseKey& key, uint32_t cone, uint32_t step,
+                                        float* z) {
+    const uint4 x = philox4x32_10(make_uint4(cone, step, 0u, key.sim_index), key.k0, key.k1);
+    float s, c;
+    const float r0 = sqrtf(-2.0f * logf(unit_open(x.x)));
+    sincospif(2.0f * unit_open(x.y), &s, &c);
+    z[0] = r0 * c;
+    if (count > 1) z[1] = r0 * s;
+    if (count > 2) {
+        const float r1 = sqrtf(-2.0f * logf(unit_open(x.z)));
+        float s1, c1;
+        sincospif(2.0f * unit_open(x.w), &s1, &c1);
+        z[2] = r1 * c1;
+        if (count > 3) z[3] = r1 * s1;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Static target grid: targets bucketed into cubic cells of side >= contact radius, so a
+// 3^dim-cell neighbourhood holds every target that can be within range (the uniform-grid
+// broadphase of Secs. 3.3 and 3.5).  pts[k] = (x, y, z, original index as bits).
+// ------------------------------------------------------------------------------------
+struct TargetGrid {
+    const float4* pts;
+    const int32_t* cell_start;   // [gx*gy*gz + 1]
+    int gx, gy, gz;
+    float inv_cell;
+    float r2;                    // contact radius squared (FP32)
+};
+
+// Nearest target with squared distance strictly below r2; ties on the squared distance go
+// to the lowest original index.  Returns -1 when none is in range.
+template <int dim>
+__device__ __forceinline__ int contact_target(const TargetGrid& tg, float x, float y, float z) {
+    const int cx = min(max((int)floorf(x * tg.inv_cell), 0), tg.gx - 1);
+    const int cy = min(max((int)floorf(y * tg.inv_cell), 0), tg.gy - 1);
+    const int cz = dim == 3 ? min(max((int)floorf(z * tg.inv_cell), 0), tg.gz - 1) : 0;
+    float best_d2 = tg.r2;
+    int best = -1;
+    const int z_lo = dim == 3 ? max(cz - 1, 0) : 0;
+    const int z_hi = dim == 3 ? min(cz + 1, tg.gz - 1) : 0;
+    for (int zz = z_lo; zz <= z_hi; ++zz)
+        for (int yy = max(cy - 1, 0); yy <= min(cy + 1, tg.gy - 1); ++yy) {
+            const int row = (zz * tg.gy + yy) * tg.gx;
+            const int lo = tg.cell_start[row + max(cx - 1, 0)];
+            const int hi = tg.cell_start[row + min(cx + 1, tg.gx - 1) + 1];
+            for (int k = lo; k < hi; ++k) {
+                const float4 t = tg.pts[k];
+                const float ddx = x - t.x, ddy = y - t.y;
+                float d2 = ddx * ddx + ddy * ddy;
+                if (dim == 3) {
+                    const float ddz = z - t.z;
+                    d2 += ddz * ddz;
+                }
+                const int idx = __float_as_int(t.w);
+                if (d2 < best_d2 || (d2 == best_d2 && best >= 0 && idx < best)) {
+                    best_d2 = d2;
+                    best = idx;
+                }
+            }
+        }
+    return best;
+}
+
+// ------------------------------------------------------------------------------------
+// Rule constants of the cone step (one simulation).
+// ------------------------------------------------------------------------------------
+struct ConeRules {
+    int nx, ny, nz;
+    float inv_dx, half_inv_dx;
+    float Lx, Ly, Lz;            // domain extent n_a * dx
+    float step_len, gain, max_turn, sigma;
+    float sign0, sign1;          // species weights in g
+    int n_species;
+    NoiseKey key;
+    TargetGrid targets;
+};
+
+// Tip coordinate -> lower corner cell and fraction along one axis (cell centres at
+// (i + 1/2) dx; clamped so the tip is interpolated between in-grid centres).
+__device__ __forceinline__ void corner(float p, float inv_dx, int n, int& i0, float& f) {
+    float u = fmaf(p, inv_dx, -0.5f);
+    u = fminf(fmaxf(u, 0.0f), (float)(n - 1));
+    i0 = min((int)floorf(u), n - 2);
+    f = u - (float)i0;
+}
+
+// Accessor concept: F(i, j) / F(i, j, l) returns the cue value of in-grid cell (i, j[, l])
+// of one species.
+
+// Interpolated central-difference gradient of one species at (x, y).
+template <class F>
+__device__ __forceinline__ void gradient_2d(const F& f, const ConeRules& r, float x, float y,
+                                            float& gx, float& gy) {
+    int i0, j0;
+    float fx, fy;
+    corner(x, r.inv_dx, r.nx, i0, fx);
+    corner(y, r.inv_dx, r.ny, j0, fy);
+    const int im = max(i0 - 1, 0), ip = min(i0 + 2, r.nx - 1);
+    const int jm = max(j0 - 1, 0), jp = min(j0 + 2, r.ny - 1);
+    // rows j0, j0+1: columns im, i0, i0+1, ip
+    const float a0 = f(im, j0), a1 = f(i0, j0), a2 = f(i0 + 1, j0), a3 = f(ip, j0);
+    const float b0 = f(im, j0 + 1), b1 = f(i0, j0 + 1), b2 = f(i0 + 1, j0 + 1), b3 = f(ip, j0 + 1);
+    // columns i0, i0+1: rows jm, jp
+    const float c0 = f(i0, jm), c1 = f(i0 + 1, jm);
+    const float d0 = f(i0, jp), d1 = f(i0 + 1, jp);
+    // central differences at the four corner centres (ghost = own value at walls)
+    const float gx00 = (a2 - a0) * r.half_inv_dx, gx10 = (a3 - a1) * r.half_inv_dx;
+    const float gx01 = (b2 - b0) * r.half_inv_dx, gx11 = (b3 - b1) * r.half_inv_dx;
+    const float gy00 = (b1 - c0) * r.half_inv_dx, gy10 = (b2 - c1) * r.half_inv_dx;
+    const float gy01 = (d0 - a1) * r.half_inv_dx, gy11 = (d1 - a2) * r.half_inv_dx;
+    const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy);
+    const float w01 = (1.0f - fx) * fy, w11 = fx * fy;
+    gx = w00 * gx00 + w10 * gx10 + w01 * gx01 + w11 * gx11;
+    gy = w00 * gy00 + w10 * gy10 + w01 * gy01 + w11 * gy11;
+}
+
+template <class F>
+__device__ __forceinline__ void gradient_3d(const F& f, const ConeRules& r, float x, float y,
+                                            float z, float& gx, float& gy, float& gz) {
+    int i0, j0, l0;
+    float fx, fy, fz;
+    corner(x, r.inv_dx, r.nx, i0, fx);
+    corner(y, r.inv_dx, r.ny, j0, fy);
+    corner(z, r.inv_dx, r.nz, l0, fz);
+    gx = gy = gz = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int i = i0 + (c & 1), j = j0 + ((c >> 1) & 1), l = l0 + ((c >> 2) & 1);
+        const float w = ((c & 1) ? fx : 1.0f - fx) * (((c >> 1) & 1) ? fy : 1.0f - fy) *
+                        (((c >> 2) & 1) ? fz : 1.0f - fz);
+        const float ex = f(min(i + 1, r.nx - 1), j, l) - f(max(i - 1, 0), j, l);
+        const float ey = f(i, min(j + 1, r.ny - 1), l) - f(i, max(j - 1, 0), l);
+        const float ez = f(i, j, min(l + 1, r.nz - 1)) - f(i, j, max(l - 1, 0));
+        gx += w * ex;
+        gy += w * ey;
+        gz += w * ez;
+    }
+    gx *= r.half_inv_dx;
+    gy *= r.half_inv_dx;
+    gz *= r.half_inv_dx;
+}
+
+struct ConeEvent {
+    int status;   // kActive / kContact / kExited after the step
+    int target;   // contacted target or -1
+};
+
+// One step of an active 2D cone: turn toward h + gain*g (capped), noise, advance, exit,
+// contact.  `step` is the number of completed steps n before this one.
+__device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, float gy,
+                                                  uint32_t id, uint32_t step, float& x,
+                                                  float& y, float& theta) {
+    float s, c;
+    sincosf(theta, &s, &c);
+    float cross = r.gain * (c * gy - s * gx);
+    const float along = 1.0f + r.gain * (c * gx + s * gy);
+    if (cross == 0.0f) cross = 0.0f;   // -0 -> +0: an anti-parallel pull turns by +cap
+    float turn = atan2f(cross, along);
+    turn = fminf(fmaxf(turn, -r.max_turn), r.max_turn);
+    float z[1];
+    normals<1>(r.key, id, step, z);
+    float th = theta + turn;
+    th = th + r.sigma * z[0];
+    const float two_pi = 6.28318530717958647692f;
+    th = th - two_pi * floorf((th + 3.14159265358979323846f) * (1.0f / two_pi));
+    theta = th;
+    sincosf(th, &s, &c);
+    x = fmaf(r.step_len, c, x);
+    y = fmaf(r.step_len, s, y);
+    ConeEvent ev{kActive, -1};
+    if (x < 0.0f || x >= r.Lx || y < 0.0f || y >= r.Ly) {
+        ev.status = kExited;
+        return ev;
+    }
+    const int t = contact_target<2>(r.targets, x, y, 0.0f);
+    if (t >= 0) {
+        ev.status = kContact;
+        ev.target = t;
+    }
+    return ev;
+}
+
+// One step of an active 3D cone with unit heading (hx, hy, hz).
+__device__ __forceinline__ ConeEvent cone_step_3d(const ConeRules& r, float gx, float gy,
+                                                  float gz, uint32_t id, uint32_t step,
+                                                  float& x, float& y, float& z, float& hx,
+                                                  float& hy, float& hz) {
+    // turn in the plane of h and g, toward h + gain*g, by at most max_turn
+    const float gh = gx * hx + gy * hy + gz * hz;
+    const float px = gx - gh * hx, py = gy - gh * hy, pz = gz - gh * hz;
+    const float pn = sqrtf(px * px + py * py + pz * pz);
+    if (pn > 0.0f) {
+        float phi = atan2f(r.gain * pn, 1.0f + r.gain * gh);
+        phi = fminf(phi, r.max_turn);
+        float s, c;
+        sincosf(phi, &s, &c);
+        const float k = s / pn;
+        hx = c * hx + k * px;
+        hy = c * hy + k * py;
+        hz = c * hz + k * pz;
+    }
+    // tangent-plane Gaussian rotation
+    float zn[3];
+    normals<3>(r.key, id, step, zn);
+    const float zh = zn[0] * hx + zn[1] * hy + zn[2] * hz;
+    const float wx = r.sigma * (zn[0] - zh * hx);
+    const float wy = r.sigma * (zn[1] - zh * hy);
+    const float wz = r.sigma * (zn[2] - zh * hz);
+    const float wn = sqrtf(wx * wx + wy * wy + wz * wz);
+    if (wn > 0.0f) {
+        float s, c;
+        sincosf(wn, &s, &c);
+        const float k = s / wn;
+        hx = c * hx + k * wx;
+        hy = c * hy + k * wy;
+        hz = c * hz + k * wz;
+    }
+    const float inv = 1.0f / sqrtf(hx * hx + hy * hy + hz * hz);
+    hx *= inv;
+    hy *= inv;
+    hz *= inv;
+    x = fmaf(r.step_len, hx, x);
+    y = fmaf(r.step_len, hy, y);
+    z = fmaf(r.step_len, hz, z);
+    ConeEvent ev{kActive, -1};
+    if (x < 0.0f || x >= r.Lx || y < 0.0f || y >= r.Ly || z < 0.0f || z >= r.Lz) {
+        ev.status = kExited;
+        return ev;
+    }
+    const int t = contact_target<3>(r.targets, x, y, z);
+    if (t >= 0) {
+        ev.status = kContact;
+        ev.target = t;
+    }
+    return ev;
+}
+
+}  // namespace cuesim

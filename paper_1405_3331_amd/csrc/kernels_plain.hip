@@ -1,0 +1,209 @@
+// kernels_plain.hip -- one time step per kernel sequence, no temporal blocking.
+//
+// The stencil reads each cell's 2*dim neighbours from HBM/L2 and writes the new value:
+// 8 algorithmic bytes per cell-update (one FP32 read, one FP32 write), the HBM-bound
+// baseline the tiled kernel improves on.  Cones run one thread each, in the caller's order,
+// against the just-updated field.
+#include "internal.hpp"
+
+namespace cuesim {
+
+namespace {
+
+constexpr int kRowThreads = 256;
+
+__global__ __launch_bounds__(kRowThreads) void k_field2d(const float* __restrict__ in,
+                                                         float* __restrict__ out, int nx,
+                                                         int ny, StencilCoef coef) {
+    const int i = blockIdx.x * kRowThreads + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= nx) return;
+    const int at = j * nx + i;
+    const float c = in[at];
+    const float w = i > 0 ? in[at - 1] : c;
+    const float e = i < nx - 1 ? in[at + 1] : c;
+    const float s = j > 0 ? in[at - nx] : c;
+    const float n = j < ny - 1 ? in[at + nx] : c;
+    const float lap = ((w + e) + (s + n)) - 4.0f * c;
+    out[at] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_field3d(const float* __restrict__ in,
+                                                         float* __restrict__ out, int nx,
+                                                         int ny, int nz, StencilCoef coef) {
+    const int i = blockIdx.x * kRowThreads + threadIdx.x;
+    const int j = blockIdx.y;
+    const int l = blockIdx.z;
+    if (i >= nx) return;
+    const int plane = nx * ny;
+    const int at = l * plane + j * nx + i;
+    const float c = in[at];
+    const float w = i > 0 ? in[at - 1] : c;
+    const float e = i < nx - 1 ? in[at + 1] : c;
+    const float s = j > 0 ? in[at - nx] : c;
+    const float n = j < ny - 1 ? in[at + nx] : c;
+    const float b = l > 0 ? in[at - plane] : c;
+    const float t = l < nz - 1 ? in[at + plane] : c;
+    const float lap = (((w + e) + (s + n)) + (b + t)) - 6.0f * c;
+    out[at] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
+}
+
+__global__ void k_sources(float* __restrict__ field, SourceList src) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < src.n) field[src.cell[m]] += src.q[m];   // cells are unique per list
+}
+
+struct Global2D {
+    const float* f;
+    int nx;
+    __device__ float operator()(int i, int j) const { return f[j * nx + i]; }
+};
+
+struct Global3D {
+    const float* f;
+    int nx, ny;
+    __device__ float operator()(int i, int j, int l) const { return f[(l * ny + j) * nx + i]; }
+};
+
+__global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __restrict__ f0,
+                                                 const float* __restrict__ f1, ConeArrays c,
+                                                 uint32_t step) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n || c.status[i] != kActive) return;
+    float x = c.pos[2 * i], y = c.pos[2 * i + 1], th = c.dir[i];
+    float gx, gy;
+    gradient_2d(Global2D{f0, r.nx}, r, x, y, gx, gy);
+    gx *= r.sign0;
+    gy *= r.sign0;
+    if (r.n_species > 1) {
+        float hx, hy;
+        gradient_2d(Global2D{f1, r.nx}, r, x, y, hx, hy);
+        gx = fmaf(r.sign1, hx, gx);
+        gy = fmaf(r.sign1, hy, gy);
+    }
+    const ConeEvent ev = cone_step_2d(r, gx, gy, (uint32_t)i, step, x, y, th);
+    c.pos[2 * i] = x;
+    c.pos[2 * i + 1] = y;
+    c.dir[i] = th;
+    if (ev.status != kActive) {
+        c.status[i] = ev.status;
+        c.target[i] = ev.target;
+        c.event_step[i] = (int32_t)(step + 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cones3d(ConeRules r, const float* __restrict__ f0,
+                                                 const float* __restrict__ f1, ConeArrays c,
+                                                 uint32_t step) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n || c.status[i] != kActive) return;
+    float x = c.pos[3 * i], y = c.pos[3 * i + 1], z = c.pos[3 * i + 2];
+    float hx = c.dir[3 * i], hy = c.dir[3 * i + 1], hz = c.dir[3 * i + 2];
+    float gx, gy, gz;
+    gradient_3d(Global3D{f0, r.nx, r.ny}, r, x, y, z, gx, gy, gz);
+    gx *= r.sign0;
+    gy *= r.sign0;
+    gz *= r.sign0;
+    if (r.n_species > 1) {
+        float ax, ay, az;
+        gradient_3d(Global3D{f1, r.nx, r.ny}, r, x, y, z, ax, ay, az);
+        gx = fmaf(r.sign1, ax, gx);
+        gy = fmaf(r.sign1, ay, gy);
+        gz = fmaf(r.sign1, az, gz);
+    }
+    const ConeEvent ev = cone_step_3d(r, gx, gy, gz, (uint32_t)i, step, x, y, z, hx, hy, hz);
+    c.pos[3 * i] = x;
+    c.pos[3 * i + 1] = y;
+    c.pos[3 * i + 2] = z;
+    c.dir[3 * i] = hx;
+    c.dir[3 * i + 1] = hy;
+    c.dir[3 * i + 2] = hz;
+    if (ev.status != kActive) {
+        c.status[i] = ev.status;
+        c.target[i] = ev.target;
+        c.event_step[i] = (int32_t)(step + 1);
+    }
+}
+
+// FP64 sum: each block reduces a grid-stride slice (wavefront shuffles, then LDS), the
+// second pass adds the block partials in a fixed order, so the result is deterministic.
+constexpr int kMassThreads = 256;
+
+__device__ double block_sum(double v) {
+    __shared__ double part[kMassThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kMassThreads / 64; ++w) t += part[w];
+    return t;
+}
+
+__global__ __launch_bounds__(kMassThreads) void k_mass_partial(const float* __restrict__ f,
+                                                                int64_t n,
+                                                                double* __restrict__ partial) {
+    double acc = 0.0;
+    for (int64_t x = (int64_t)blockIdx.x * kMassThreads + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * kMassThreads)
+        acc += (double)f[x];
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kMassThreads) void k_mass_final(const double* __restrict__ partial,
+                                                              int n, double* __restrict__ out) {
+    double acc = 0.0;
+    for (int x = threadIdx.x; x < n; x += kMassThreads) acc += partial[x];
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) *out = t;
+}
+
+}  // namespace
+
+hipError_t launch_field_plain(int dim, int nx, int ny, int nz, const float* in, float* out,
+                              StencilCoef coef, hipStream_t stream) {
+    const int bx = (nx + kRowThreads - 1) / kRowThreads;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_field2d, dim3(bx, ny), dim3(kRowThreads), 0, stream, in, out, nx,
+                           ny, coef);
+    else
+        hipLaunchKernelGGL(k_field3d, dim3(bx, ny, nz), dim3(kRowThreads), 0, stream, in, out,
+                           nx, ny, nz, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_sources(float* field, SourceList src, hipStream_t stream) {
+    if (src.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sources, dim3((src.n + 63) / 64), dim3(64), 0, stream, field, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_cones_plain(int dim, const ConeRules& rules, const float* f0,
+                              const float* f1, ConeArrays cones, uint32_t step,
+                              hipStream_t stream) {
+    if (cones.n == 0) return hipSuccess;
+    const int blocks = (cones.n + 255) / 256;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_cones2d, dim3(blocks), dim3(256), 0, stream, rules, f0, f1, cones,
+                           step);
+    else
+        hipLaunchKernelGGL(k_cones3d, dim3(blocks), dim3(256), 0, stream, rules, f0, f1, cones,
+                           step);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass(const float* field, int64_t n, double* partial, int n_partial,
+                       double* out, hipStream_t stream) {
+    int blocks = (int)((n + kMassThreads - 1) / kMassThreads);
+    if (blocks > n_partial) blocks = n_partial;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_mass_partial, dim3(blocks), dim3(kMassThreads), 0, stream, field, n,
+                       partial);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(kMassThreads), 0, stream, partial, blocks,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace cuesim

@@ -1,0 +1,732 @@
+// sim.hip -- host side of the C ABI (include/cuesim.h): parameter validation, device
+// allocation and upload, the step loop, state read-back and write, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cuesim.h"
+#include "internal.hpp"
+#include "tiled.hpp"
+
+using namespace cuesim;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+bool finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct sim_handle {
+    // geometry and coefficients
+    int dim = 2, nx = 0, ny = 0, nz = 1;
+    int64_t n_cells = 0;
+    double dx = 1.0, dt = 1.0;
+    int n_species = 1;
+    StencilCoef coef[SIM_MAX_SPECIES] = {};
+    int n_cones = 0, n_targets = 0;
+    ConeRules rules = {};
+
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+
+    // device state
+    float* field[SIM_MAX_SPECIES][2] = {};
+    int cur[SIM_MAX_SPECIES] = {0, 0};
+    int32_t* src_cell[SIM_MAX_SPECIES] = {};
+    float* src_q[SIM_MAX_SPECIES] = {};
+    int n_src[SIM_MAX_SPECIES] = {};
+    ConeArrays cones = {};
+    float4* target_pts = nullptr;
+    int32_t* target_cells = nullptr;
+    double* mass_partial = nullptr;
+    double* mass_out = nullptr;
+
+    // temporal blocking
+    int block_steps = 1;
+    TiledPlan plan = {};
+    TiledState tiled = {};
+    bool cones_bucketed = false;   // active cones live in the tile buckets
+
+    int64_t step = 0;
+    bool poisoned = false;
+    std::string err;
+
+    // timing of the step kernel
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};
+
+namespace {
+
+sim_status fail(sim_handle* h, sim_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_create_error = buf;
+    return st;
+}
+
+bool sticky(hipError_t e) {
+    return e == hipErrorIllegalAddress || e == hipErrorLaunchFailure ||
+           e == hipErrorAssert || e == hipErrorECCNotCorrectable;
+}
+
+sim_status device_fail(sim_handle* h, hipError_t e, const char* what) {
+    if (h && sticky(e)) h->poisoned = true;
+    return fail(h, e == hipErrorOutOfMemory ? SIM_ENOMEM : SIM_EDEVICE, "%s: %s (%d)", what,
+                hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(h, expr)                                       \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return device_fail(h, e_, #expr); \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void drop_events(sim_handle* h) {
+    for (auto& ev : h->events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    h->events.clear();
+}
+
+void release(sim_handle* h) {
+    for (int s = 0; s < SIM_MAX_SPECIES; ++s) {
+        for (int b = 0; b < 2; ++b) dfree(h->field[s][b]);
+        dfree(h->src_cell[s]);
+        dfree(h->src_q[s]);
+    }
+    dfree(h->cones.pos);
+    dfree(h->cones.dir);
+    dfree(h->cones.status);
+    dfree(h->cones.target);
+    dfree(h->cones.event_step);
+    dfree(h->target_pts);
+    dfree(h->target_cells);
+    dfree(h->mass_partial);
+    dfree(h->mass_out);
+    tiled_release(h->tiled);
+    drop_events(h);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    h->stream = nullptr;
+}
+
+int dir_width(int dim) { return dim == 2 ? 1 : 3; }
+
+// Validate the parameter struct.  Returns SIM_OK or an error with g_create_error set.
+sim_status validate(const sim_params* p) {
+    if (!p) return fail(nullptr, SIM_EINVAL, "params is NULL");
+    if (p->struct_size != sizeof(sim_params))
+        return fail(nullptr, SIM_EINVAL, "struct_size %u != sizeof(sim_params) %zu",
+                    p->struct_size, sizeof(sim_params));
+    if (p->dim != 2 && p->dim != 3) return fail(nullptr, SIM_EINVAL, "dim must be 2 or 3");
+    const int nz = p->dim == 3 ? p->nz : 1;
+    if (p->nx < 2 || p->ny < 2 || (p->dim == 3 && p->nz < 2))
+        return fail(nullptr, SIM_EINVAL, "every axis needs at least 2 cells");
+    const double cells = (double)p->nx * p->ny * nz;
+    if (cells > 2147483647.0) return fail(nullptr, SIM_EINVAL, "grid has more than 2^31-1 cells");
+    if (!finite(p->dx) || !finite(p->dt) || p->dx <= 0 || p->dt <= 0)
+        return fail(nullptr, SIM_EINVAL, "dx and dt must be finite and positive");
+    if (p->n_species < 1 || p->n_species > SIM_MAX_SPECIES)
+        return fail(nullptr, SIM_EINVAL, "n_species must be 1 or 2");
+    for (int s = 0; s < p->n_species; ++s) {
+        if (!finite(p->D[s]) || p->D[s] < 0 || !finite(p->k[s]) || p->k[s] < 0 ||
+            !finite(p->sign[s]))
+            return fail(nullptr, SIM_EINVAL, "species %d: D, k must be finite >= 0, sign finite", s);
+        const double r = p->D[s] * p->dt / (p->dx * p->dx);
+        if (r > 1.0 / (2.0 * p->dim))
+            return fail(nullptr, SIM_ECFL, "species %d: D dt / dx^2 = %g exceeds 1/(2 dim) = %g",
+                        s, r, 1.0 / (2.0 * p->dim));
+        if (2.0 * p->dim * r + p->k[s] * p->dt > 1.0)
+            return fail(nullptr, SIM_ECFL, "species %d: 2 dim r + k dt = %g exceeds 1", s,
+                        2.0 * p->dim * r + p->k[s] * p->dt);
+        if (p->n_sources[s] < 0 || (p->n_sources[s] > 0 && (!p->source_cell[s] || !p->source_q[s])))
+            return fail(nullptr, SIM_EINVAL, "species %d: bad source arrays", s);
+        for (int m = 0; m < p->n_sources[s]; ++m) {
+            if (p->source_cell[s][m] < 0 || (double)p->source_cell[s][m] >= cells)
+                return fail(nullptr, SIM_EINVAL, "species %d source %d: cell %d out of range", s,
+                            m, p->source_cell[s][m]);
+            if (!std::isfinite(p->source_q[s][m]))
+                return fail(nullptr, SIM_EINVAL, "species %d source %d: q not finite", s, m);
+        }
+        if (p->init_field[s])
+            for (int64_t x = 0; x < (int64_t)cells; ++x)
+                if (!std::isfinite(p->init_field[s][x]))
+                    return fail(nullptr, SIM_EINVAL, "species %d: init_field not finite", s);
+    }
+    if (p->n_cones < 0 || (p->n_cones > 0 && (!p->cone_pos || !p->cone_dir)))
+        return fail(nullptr, SIM_EINVAL, "bad cone arrays");
+    const double L[3] = {p->nx * p->dx, p->ny * p->dx, nz * p->dx};
+    for (int i = 0; i < p->n_cones; ++i) {
+        for (int a = 0; a < p->dim; ++a) {
+            const float v = p->cone_pos[(int64_t)i * p->dim + a];
+            if (!std::isfinite(v) || v < 0.0f || (double)v >= L[a])
+                return fail(nullptr, SIM_EINVAL, "cone %d: position outside the domain", i);
+        }
+        if (p->dim == 2) {
+            if (!std::isfinite(p->cone_dir[i]))
+                return fail(nullptr, SIM_EINVAL, "cone %d: heading not finite", i);
+        } else {
+            const float* h = p->cone_dir + (int64_t)i * 3;
+            const double n2 = (double)h[0] * h[0] + (double)h[1] * h[1] + (double)h[2] * h[2];
+            if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > 1e-3)
+                return fail(nullptr, SIM_EINVAL, "cone %d: heading is not a unit vector", i);
+        }
+    }
+    if (p->n_targets < 0 || (p->n_targets > 0 && !p->target_pos))
+        return fail(nullptr, SIM_EINVAL, "bad target arrays");
+    for (int64_t t = 0; t < (int64_t)p->n_targets * p->dim; ++t)
+        if (!std::isfinite(p->target_pos[t]))
+            return fail(nullptr, SIM_EINVAL, "target coordinates must be finite");
+    if (!finite(p->contact_radius) || p->contact_radius < 0 || !finite(p->step_len) ||
+        p->step_len < 0 || !finite(p->turn_gain) || !finite(p->max_turn) || p->max_turn < 0 ||
+        p->max_turn > M_PI || !finite(p->noise_sigma) || p->noise_sigma < 0)
+        return fail(nullptr, SIM_EINVAL,
+                    "contact_radius, step_len >= 0; max_turn in [0, pi]; noise_sigma >= 0");
+    if (p->block_steps < 0 || p->block_steps > 32)
+        return fail(nullptr, SIM_EINVAL, "block_steps must be in [0, 32]");
+    return SIM_OK;
+}
+
+// Bucket targets into cubic cells of side >= contact radius (host counting sort, once).
+sim_status build_targets(sim_handle* h, const sim_params* p) {
+    const int dim = p->dim;
+    const double L[3] = {h->nx * h->dx, h->ny * h->dx, h->nz * h->dx};
+    const double longest = std::max(L[0], std::max(L[1], dim == 3 ? L[2] : 0.0));
+    const int max_per_axis = dim == 2 ? 512 : 128;
+    double cell = std::max(p->contact_radius, longest / max_per_axis);
+    if (!(cell > 0)) cell = longest;
+    int g[3] = {1, 1, 1};
+    for (int a = 0; a < dim; ++a) g[a] = std::max(1, (int)std::ceil(L[a] / cell));
+    const int64_t n_cells = (int64_t)g[0] * g[1] * g[2];
+    std::vector<int32_t> start(n_cells + 1, 0);
+    std::vector<int64_t> key(p->n_targets);
+    for (int t = 0; t < p->n_targets; ++t) {
+        int c[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) {
+            const double v = std::floor((double)p->target_pos[(int64_t)t * dim + a] / cell);
+            c[a] = (int)std::min<double>(std::max<double>(v, 0.0), g[a] - 1);
+        }
+        key[t] = ((int64_t)c[2] * g[1] + c[1]) * g[0] + c[0];
+        start[key[t] + 1] += 1;
+    }
+    for (int64_t c = 0; c < n_cells; ++c) start[c + 1] += start[c];
+    std::vector<float4> pts(std::max(1, p->n_targets));
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (int t = 0; t < p->n_targets; ++t) {
+        const float* tp = p->target_pos + (int64_t)t * dim;
+        float4 v;
+        v.x = tp[0];
+        v.y = tp[1];
+        v.z = dim == 3 ? tp[2] : 0.0f;
+        int32_t idx = t;
+        std::memcpy(&v.w, &idx, sizeof idx);
+        pts[fill[key[t]]++] = v;
+    }
+    HIP_TRY(h, dalloc(&h->target_pts, pts.size()));
+    HIP_TRY(h, dalloc(&h->target_cells, start.size()));
+    HIP_TRY(h, hipMemcpy(h->target_pts, pts.data(), pts.size() * sizeof(float4),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->target_cells, start.data(), start.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+    TargetGrid& tg = h->rules.targets;
+    tg.pts = h->target_pts;
+    tg.cell_start = h->target_cells;
+    tg.gx = g[0];
+    tg.gy = g[1];
+    tg.gz = g[2];
+    tg.inv_cell = (float)(1.0 / cell);
+    tg.r2 = (float)(p->contact_radius * p->contact_radius);
+    return SIM_OK;
+}
+
+// Merge sources sharing a cell (amounts summed in double) and scale by 1/dx^dim.
+sim_status upload_sources(sim_handle* h, const sim_params* p, int s) {
+    std::map<int32_t, double> merged;
+    const double vol = std::pow(p->dx, p->dim);
+    for (int m = 0; m < p->n_sources[s]; ++m)
+        merged[p->source_cell[s][m]] += (double)p->source_q[s][m] / vol;
+    std::vector<int32_t> cells;
+    std::vector<float> q;
+    for (auto& kv : merged) {
+        cells.push_back(kv.first);
+        q.push_back((float)kv.second);
+    }
+    h->n_src[s] = (int)cells.size();
+    HIP_TRY(h, dalloc(&h->src_cell[s], cells.size()));
+    HIP_TRY(h, dalloc(&h->src_q[s], q.size()));
+    if (!cells.empty()) {
+        HIP_TRY(h, hipMemcpy(h->src_cell[s], cells.data(), cells.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->src_q[s], q.data(), q.size() * 4, hipMemcpyHostToDevice));
+    }
+    return SIM_OK;
+}
+
+sim_status item_size(sim_handle* h, sim_item what, int32_t index, size_t* bytes) {
+    const size_t M = (size_t)h->n_cones;
+    switch (what) {
+        case SIM_FIELD:
+            if (index < 0 || index >= h->n_species)
+                return fail(h, SIM_EINVAL, "species index %d out of range", index);
+            *bytes = (size_t)h->n_cells * sizeof(float);
+            return SIM_OK;
+        case SIM_CONE_POS: *bytes = M * h->dim * sizeof(float); break;
+        case SIM_CONE_DIR: *bytes = M * dir_width(h->dim) * sizeof(float); break;
+        case SIM_CONE_STATUS:
+        case SIM_CONE_TARGET:
+        case SIM_CONE_EVENT_STEP: *bytes = M * sizeof(int32_t); break;
+        case SIM_MASS: *bytes = (size_t)h->n_species * sizeof(double); break;
+        case SIM_STEP: *bytes = sizeof(int64_t); break;
+        case SIM_COUNTS: *bytes = 3 * sizeof(int32_t); break;
+        case SIM_KERNEL_TIME: *bytes = 2 * sizeof(double); break;
+        case SIM_EVENTS: *bytes = 0; break;  // computed by the caller of item_size
+        default: return fail(h, SIM_EINVAL, "unknown item %d", (int)what);
+    }
+    if (index != 0) return fail(h, SIM_EINVAL, "index must be 0 for item %d", (int)what);
+    return SIM_OK;
+}
+
+// Bring active cones from the tile buckets back into the caller-order arrays.
+sim_status unbucket(sim_handle* h) {
+    if (!h->cones_bucketed) return SIM_OK;
+    HIP_TRY(h, tiled_unbucket(h->plan, h->tiled, h->cones, h->stream));
+    h->cones_bucketed = false;
+    return SIM_OK;
+}
+
+sim_status record_start(sim_handle* h, hipEvent_t* start) {
+    *start = nullptr;
+    if (!h->timing) return SIM_OK;
+    hipEvent_t a;
+    HIP_TRY(h, hipEventCreate(&a));
+    HIP_TRY(h, hipEventRecord(a, h->stream));
+    *start = a;
+    return SIM_OK;
+}
+
+sim_status record_stop(sim_handle* h, hipEvent_t start) {
+    if (!h->timing || !start) return SIM_OK;
+    hipEvent_t b;
+    HIP_TRY(h, hipEventCreate(&b));
+    HIP_TRY(h, hipEventRecord(b, h->stream));
+    h->events.emplace_back(start, b);
+    return SIM_OK;
+}
+
+sim_status collect_timing(sim_handle* h) {
+    for (auto& ev : h->events) {
+        float ms = 0.0f;
+        HIP_TRY(h, hipEventSynchronize(ev.second));
+        HIP_TRY(h, hipEventElapsedTime(&ms, ev.first, ev.second));
+        h->timed_ms += ms;
+        h->timed_launches += 1;
+    }
+    drop_events(h);
+    return SIM_OK;
+}
+
+// One un-blocked step: stencil, sources, cones.
+sim_status plain_step(sim_handle* h) {
+    for (int s = 0; s < h->n_species; ++s) {
+        const float* in = h->field[s][h->cur[s]];
+        float* out = h->field[s][h->cur[s] ^ 1];
+        hipEvent_t t0;
+        sim_status st = record_start(h, &t0);
+        if (st != SIM_OK) return st;
+        HIP_TRY(h, launch_field_plain(h->dim, h->nx, h->ny, h->nz, in, out, h->coef[s], h->stream));
+        st = record_stop(h, t0);
+        if (st != SIM_OK) return st;
+        HIP_TRY(h, launch_sources(out, SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
+                                  h->stream));
+        h->cur[s] ^= 1;
+    }
+    const float* f0 = h->field[0][h->cur[0]];
+    const float* f1 = h->n_species > 1 ? h->field[1][h->cur[1]] : f0;
+    HIP_TRY(h, launch_cones_plain(h->dim, h->rules, f0, f1, h->cones, (uint32_t)h->step, h->stream));
+    h->step += 1;
+    return SIM_OK;
+}
+
+sim_status tiled_steps(sim_handle* h, int64_t n) {
+    if (!h->cones_bucketed) {
+        HIP_TRY(h, tiled_bucket(h->plan, h->tiled, h->cones, h->stream));
+        h->cones_bucketed = true;
+    }
+    while (n > 0) {
+        const int b = (int)std::min<int64_t>(n, h->plan.block_steps);
+        hipEvent_t t0;
+        sim_status st = record_start(h, &t0);
+        if (st != SIM_OK) return st;
+        float* in[SIM_MAX_SPECIES] = {};
+        float* out[SIM_MAX_SPECIES] = {};
+        for (int s = 0; s < h->n_species; ++s) {
+            in[s] = h->field[s][h->cur[s]];
+            out[s] = h->field[s][h->cur[s] ^ 1];
+        }
+        HIP_TRY(h, tiled_launch(h->plan, h->tiled, h->rules, in, out, h->cones, b,
+                                (uint32_t)h->step, h->stream));
+        st = record_stop(h, t0);
+        if (st != SIM_OK) return st;
+        for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
+        h->step += b;
+        n -= b;
+    }
+    return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out) {
+    if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    sim_status st = validate(p);
+    if (st != SIM_OK) return st;
+    sim_handle* h = new (std::nothrow) sim_handle();
+    if (!h) return fail(nullptr, SIM_ENOMEM, "host allocation failed");
+    auto bail = [&](sim_status s) {
+        g_create_error = h->err;
+        release(h);
+        delete h;
+        return s;
+    };
+    h->dim = p->dim;
+    h->nx = p->nx;
+    h->ny = p->ny;
+    h->nz = p->dim == 3 ? p->nz : 1;
+    h->n_cells = (int64_t)h->nx * h->ny * h->nz;
+    h->dx = p->dx;
+    h->dt = p->dt;
+    h->n_species = p->n_species;
+    h->n_cones = p->n_cones;
+    h->n_targets = p->n_targets;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(device_fail(h, e, "hipGetDevice"));
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(device_fail(h, e, "hipStreamCreate"));
+        h->own_stream = true;
+    }
+    for (int s = 0; s < p->n_species; ++s) {
+        const double r = p->D[s] * p->dt / (p->dx * p->dx);
+        h->coef[s].r = (float)r;
+        h->coef[s].kdt = (float)(p->k[s] * p->dt);
+    }
+    ConeRules& R = h->rules;
+    R.nx = h->nx;
+    R.ny = h->ny;
+    R.nz = h->nz;
+    R.inv_dx = (float)(1.0 / p->dx);
+    R.half_inv_dx = (float)(0.5 / p->dx);
+    R.Lx = (float)(h->nx * p->dx);
+    R.Ly = (float)(h->ny * p->dx);
+    R.Lz = (float)(h->nz * p->dx);
+    R.step_len = (float)p->step_len;
+    R.gain = (float)p->turn_gain;
+    R.max_turn = (float)p->max_turn;
+    R.sigma = (float)p->noise_sigma;
+    R.sign0 = (float)p->sign[0];
+    R.sign1 = p->n_species > 1 ? (float)p->sign[1] : 0.0f;
+    R.n_species = p->n_species;
+    R.key.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    R.key.k1 = (uint32_t)(p->seed >> 32);
+    R.key.sim_index = p->sim_index;
+
+    // fields
+    for (int s = 0; s < p->n_species; ++s) {
+        for (int b = 0; b < 2; ++b) {
+            e = dalloc(&h->field[s][b], (size_t)h->n_cells);
+            if (e != hipSuccess) return bail(device_fail(h, e, "field allocation"));
+        }
+        if (p->init_field[s])
+            e = hipMemcpy(h->field[s][0], p->init_field[s], h->n_cells * sizeof(float),
+                          hipMemcpyHostToDevice);
+        else
+            e = hipMemset(h->field[s][0], 0, h->n_cells * sizeof(float));
+        if (e != hipSuccess) return bail(device_fail(h, e, "field upload"));
+        st = upload_sources(h, p, s);
+        if (st != SIM_OK) return bail(st);
+    }
+    // cones (caller order)
+    const size_t M = (size_t)p->n_cones;
+    h->cones.n = p->n_cones;
+    if ((e = dalloc(&h->cones.pos, M * p->dim)) != hipSuccess ||
+        (e = dalloc(&h->cones.dir, M * dir_width(p->dim))) != hipSuccess ||
+        (e = dalloc(&h->cones.status, M)) != hipSuccess ||
+        (e = dalloc(&h->cones.target, M)) != hipSuccess ||
+        (e = dalloc(&h->cones.event_step, M)) != hipSuccess)
+        return bail(device_fail(h, e, "cone allocation"));
+    if (M > 0) {
+        std::vector<int32_t> minus1(M, -1);
+        if ((e = hipMemcpy(h->cones.pos, p->cone_pos, M * p->dim * 4, hipMemcpyHostToDevice)) ||
+            (e = hipMemcpy(h->cones.dir, p->cone_dir, M * dir_width(p->dim) * 4,
+                           hipMemcpyHostToDevice)) ||
+            (e = hipMemset(h->cones.status, 0, M * 4)) ||
+            (e = hipMemcpy(h->cones.target, minus1.data(), M * 4, hipMemcpyHostToDevice)) ||
+            (e = hipMemcpy(h->cones.event_step, minus1.data(), M * 4, hipMemcpyHostToDevice)))
+            return bail(device_fail(h, e, "cone upload"));
+    }
+    st = build_targets(h, p);
+    if (st != SIM_OK) return bail(st);
+    if ((e = dalloc(&h->mass_partial, kMassPartials)) != hipSuccess ||
+        (e = dalloc(&h->mass_out, SIM_MAX_SPECIES)) != hipSuccess)
+        return bail(device_fail(h, e, "mass buffers"));
+
+    // temporal blocking plan
+    h->block_steps = p->block_steps == 0 ? kDefaultBlockSteps : p->block_steps;
+    if (h->block_steps > 1) {
+        h->plan = tiled_plan(h->dim, h->nx, h->ny, h->nz, h->n_species, p->step_len / p->dx,
+                             h->block_steps, h->n_cones);
+        if (h->plan.block_steps <= 1) {
+            h->block_steps = 1;   // no tile shape fits: fall back to one step per launch
+        } else {
+            e = tiled_allocate(h->plan, h->tiled, h->n_cones, h->rules, p, h->stream);
+            if (e != hipSuccess) return bail(device_fail(h, e, "tiled state allocation"));
+        }
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return bail(device_fail(h, e, "create synchronisation"));
+    *out = h;
+    return SIM_OK;
+}
+
+sim_status sim_step(sim_handle* h, int64_t n_steps) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    if (n_steps < 0) return fail(h, SIM_EINVAL, "n_steps < 0");
+    if (h->step + n_steps > 2147483647LL)
+        return fail(h, SIM_EINVAL, "step count would exceed 2^31-1");
+    if (n_steps == 0) return SIM_OK;
+    if (h->block_steps > 1) return tiled_steps(h, n_steps);
+    for (int64_t i = 0; i < n_steps; ++i) {
+        sim_status st = plain_step(h);
+        if (st != SIM_OK) return st;
+    }
+    return SIM_OK;
+}
+
+sim_status sim_read_state(sim_handle* h, sim_item what, int32_t index, void* dst,
+                          size_t dst_bytes, size_t* bytes_written) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    size_t need = 0;
+    sim_status st = item_size(h, what, index, &need);
+    if (st != SIM_OK) return st;
+    const size_t M = (size_t)h->n_cones;
+    if (what == SIM_EVENTS || what == SIM_COUNTS) {
+        st = unbucket(h);
+        if (st != SIM_OK) return st;
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        std::vector<int32_t> status(M), target(M), ev(M);
+        if (M) {
+            HIP_TRY(h, hipMemcpy(status.data(), h->cones.status, M * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(h, hipMemcpy(target.data(), h->cones.target, M * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(h, hipMemcpy(ev.data(), h->cones.event_step, M * 4, hipMemcpyDeviceToHost));
+        }
+        if (what == SIM_COUNTS) {
+            int32_t counts[3] = {0, 0, 0};
+            for (size_t i = 0; i < M; ++i)
+                if (status[i] >= 0 && status[i] <= 2) counts[status[i]] += 1;
+            if (bytes_written) *bytes_written = sizeof counts;
+            if (dst_bytes < sizeof counts) return fail(h, SIM_ERANGE, "buffer too small");
+            if (!dst) return fail(h, SIM_EINVAL, "dst is NULL");
+            std::memcpy(dst, counts, sizeof counts);
+            return SIM_OK;
+        }
+        std::vector<int32_t> rows;
+        std::vector<size_t> order;
+        for (size_t i = 0; i < M; ++i)
+            if (status[i] != kActive) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return ev[a] < ev[b]; });
+        for (size_t i : order) {
+            rows.push_back((int32_t)i);
+            rows.push_back(target[i]);
+            rows.push_back(ev[i]);
+            rows.push_back(status[i]);
+        }
+        need = rows.size() * sizeof(int32_t);
+        if (bytes_written) *bytes_written = need;
+        if (dst_bytes < need) return fail(h, SIM_ERANGE, "buffer too small: need %zu", need);
+        if (need && !dst) return fail(h, SIM_EINVAL, "dst is NULL");
+        if (need) std::memcpy(dst, rows.data(), need);
+        return SIM_OK;
+    }
+    if (bytes_written) *bytes_written = need;
+    if (dst_bytes < need) return fail(h, SIM_ERANGE, "buffer too small: need %zu", need);
+    if (need && !dst) return fail(h, SIM_EINVAL, "dst is NULL");
+    switch (what) {
+        case SIM_FIELD:
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            HIP_TRY(h, hipMemcpy(dst, h->field[index][h->cur[index]], need, hipMemcpyDeviceToHost));
+            return SIM_OK;
+        case SIM_CONE_POS:
+        case SIM_CONE_DIR:
+        case SIM_CONE_STATUS:
+        case SIM_CONE_TARGET:
+        case SIM_CONE_EVENT_STEP: {
+            st = unbucket(h);
+            if (st != SIM_OK) return st;
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            const void* src = what == SIM_CONE_POS      ? (const void*)h->cones.pos
+                              : what == SIM_CONE_DIR    ? (const void*)h->cones.dir
+                              : what == SIM_CONE_STATUS ? (const void*)h->cones.status
+                              : what == SIM_CONE_TARGET ? (const void*)h->cones.target
+                                                        : (const void*)h->cones.event_step;
+            if (need) HIP_TRY(h, hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
+            return SIM_OK;
+        }
+        case SIM_MASS: {
+            for (int s = 0; s < h->n_species; ++s)
+                HIP_TRY(h, launch_mass(h->field[s][h->cur[s]], h->n_cells, h->mass_partial,
+                                       kMassPartials, h->mass_out + s, h->stream));
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            double m[SIM_MAX_SPECIES];
+            HIP_TRY(h, hipMemcpy(m, h->mass_out, h->n_species * sizeof(double),
+                                 hipMemcpyDeviceToHost));
+            const double vol = std::pow(h->dx, h->dim);
+            for (int s = 0; s < h->n_species; ++s) m[s] *= vol;
+            std::memcpy(dst, m, need);
+            return SIM_OK;
+        }
+        case SIM_STEP:
+            std::memcpy(dst, &h->step, sizeof(int64_t));
+            return SIM_OK;
+        case SIM_KERNEL_TIME: {
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            st = collect_timing(h);
+            if (st != SIM_OK) return st;
+            double v[2] = {h->timed_ms, (double)h->timed_launches};
+            std::memcpy(dst, v, sizeof v);
+            return SIM_OK;
+        }
+        default:
+            return fail(h, SIM_EINVAL, "item %d is not readable", (int)what);
+    }
+}
+
+sim_status sim_write_state(sim_handle* h, sim_item what, int32_t index, const void* src,
+                           size_t bytes) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    size_t need = 0;
+    sim_status st = item_size(h, what, index, &need);
+    if (st != SIM_OK) return st;
+    if (bytes != need) return fail(h, SIM_EINVAL, "size %zu != item size %zu", bytes, need);
+    if (need && !src) return fail(h, SIM_EINVAL, "src is NULL");
+    switch (what) {
+        case SIM_FIELD:
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            HIP_TRY(h, hipMemcpy(h->field[index][h->cur[index]], src, need, hipMemcpyHostToDevice));
+            return SIM_OK;
+        case SIM_CONE_POS:
+        case SIM_CONE_DIR:
+        case SIM_CONE_STATUS:
+        case SIM_CONE_TARGET:
+        case SIM_CONE_EVENT_STEP: {
+            st = unbucket(h);
+            if (st != SIM_OK) return st;
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            void* d = what == SIM_CONE_POS      ? (void*)h->cones.pos
+                      : what == SIM_CONE_DIR    ? (void*)h->cones.dir
+                      : what == SIM_CONE_STATUS ? (void*)h->cones.status
+                      : what == SIM_CONE_TARGET ? (void*)h->cones.target
+                                                : (void*)h->cones.event_step;
+            if (need) HIP_TRY(h, hipMemcpy(d, src, need, hipMemcpyHostToDevice));
+            return SIM_OK;
+        }
+        case SIM_STEP: {
+            int64_t v;
+            std::memcpy(&v, src, sizeof v);
+            if (v < 0 || v > 2147483647LL) return fail(h, SIM_EINVAL, "step out of range");
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            h->step = v;
+            return SIM_OK;
+        }
+        default:
+            return fail(h, SIM_EINVAL, "item %d is not writable", (int)what);
+    }
+}
+
+sim_status sim_device_ptr(sim_handle* h, sim_item what, int32_t index, void** dev_ptr,
+                          size_t* bytes) {
+    if (!h || !dev_ptr) return fail(h, SIM_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    if (what != SIM_FIELD) return fail(h, SIM_EINVAL, "only SIM_FIELD has a device view");
+    size_t need = 0;
+    sim_status st = item_size(h, what, index, &need);
+    if (st != SIM_OK) return st;
+    *dev_ptr = h->field[index][h->cur[index]];
+    if (bytes) *bytes = need;
+    return SIM_OK;
+}
+
+sim_status sim_set_timing(sim_handle* h, int32_t enable) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    drop_events(h);
+    h->timing = enable != 0;
+    h->timed_ms = 0.0;
+    h->timed_launches = 0;
+    return SIM_OK;
+}
+
+sim_status sim_synchronize(sim_handle* h) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return SIM_OK;
+}
+
+sim_status sim_destroy(sim_handle* h) {
+    if (!h) return SIM_OK;
+    hipError_t e = hipSuccess;
+    if (h->stream) e = hipStreamSynchronize(h->stream);
+    release(h);
+    const bool bad = e != hipSuccess || h->poisoned;
+    delete h;
+    if (bad) return fail(nullptr, SIM_EDEVICE, "device error pending at destroy");
+    return SIM_OK;
+}
+
+const char* sim_last_error(const sim_handle* h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

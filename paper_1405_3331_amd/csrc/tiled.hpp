@@ -1,0 +1,54 @@
+// tiled.hpp -- temporally blocked, LDS-tiled step kernel: interface used by the host side.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cuesim.h"
+#include "internal.hpp"
+
+namespace cuesim {
+
+constexpr int kDefaultBlockSteps = 1;
+
+// Tile geometry chosen once per simulation.
+struct TiledPlan {
+    int dim = 2;
+    int block_steps = 1;     // B: steps advanced per launch (1 = tiling unavailable)
+    int halo = 0;            // H: cells loaded around each tile core
+    int core_x = 0, core_y = 0, core_z = 1;
+    int tiles_x = 0, tiles_y = 0, tiles_z = 1;
+    int n_tiles = 0;
+    int n_species = 1;
+    int nx = 0, ny = 0, nz = 1;
+    size_t lds_bytes = 0;
+};
+
+// Device buffers owned by the tiled path.
+struct TiledState {
+    float4* bucket[2] = {nullptr, nullptr};    // per tile: cone slots (x, y, theta, id)
+    int32_t* count[2] = {nullptr, nullptr};    // cones per tile
+    int cur = 0;                               // bucket buffer holding the live cones
+    int capacity = 0;                          // slots per tile
+    int32_t* src_start = nullptr;              // per tile: range into src_entry
+    int2* src_entry = nullptr;                 // (tile-local cell index, species)
+    float* src_amount = nullptr;
+};
+
+TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
+                     int block_steps, int n_cones);
+hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
+                          const ConeRules& rules, const sim_params* p, hipStream_t stream);
+void tiled_release(TiledState& st);
+// Move active cones from the caller-order arrays into the tile buckets.
+hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
+                        hipStream_t stream);
+// Move active cones from the tile buckets back into the caller-order arrays.
+hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
+                          hipStream_t stream);
+// Advance `steps` (<= plan.block_steps) steps in one launch.
+hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, const ConeRules& rules,
+                        float* const in[], float* const out[], ConeArrays cones, int steps,
+                        uint32_t first_step, hipStream_t stream);
+
+}  // namespace cuesim

@@ -1,0 +1,75 @@
+"""Comparison of the GPU library's state with the FP64 oracle's.
+
+Tolerances (FP32 device arithmetic against the FP64 oracle):
+  field   max |c_gpu - c_ref| / max |c_ref|  <= 1e-5 per species
+  tips    max |p_gpu - p_ref| / L            <= 1e-4 (L = longest side) for cones the oracle
+          did not flag as near-ties; headings compared modulo 2 pi
+  events  identical status, target and event step for every non-flagged cone
+A cone is flagged from the first step at which the oracle saw a near-tie (distance to a wall
+or to a contact sphere within tau = 1e-4 L, two in-range targets within tau, or an almost
+exactly anti-parallel pull); flagged cones are excluded from the exact event comparison.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+from paper_1405_3331_amd import binding as B
+
+FIELD_TOL = 1e-5
+TIP_TOL = 1e-4
+
+
+def field_error(sim, ref, s=0):
+    f = sim.field(s)
+    r = ref.fields[s]
+    return float(np.abs(f - r).max() / max(np.abs(r).max(), 1e-300))
+
+
+def heading_error(dim, got, want):
+    if dim == 2:
+        d = (np.asarray(got, dtype=np.float64) - want + math.pi) % (2 * math.pi) - math.pi
+        return np.abs(d)
+    return np.linalg.norm(np.asarray(got, dtype=np.float64) - want, axis=1)
+
+
+def compare(sim, ref, sc):
+    """Dict of error measures between a Simulation and an OracleSim at the same step."""
+    c = sim.cones()
+    ok = ref.flag_step < 0
+    out = {"field": [field_error(sim, ref, s) for s in range(len(sc.species))]}
+    if sc.n_cones:
+        tip = np.abs(c["pos"].astype(np.float64) - ref.pos).max(axis=1) / sc.side
+        out["tip_max"] = float(tip[ok].max()) if ok.any() else 0.0
+        out["tip_all"] = tip
+        out["heading_max"] = float(heading_error(sc.dim, c["dir"], ref.dir)[ok].max()) if ok.any() else 0.0
+        same = ((c["status"] == ref.status) & (c["target"] == ref.target) &
+                (c["event_step"] == ref.event_step))
+        out["event_mismatch"] = np.nonzero(ok & ~same)[0]
+        out["n_flagged"] = int((~ok).sum())
+    else:
+        out["tip_max"] = 0.0
+        out["heading_max"] = 0.0
+        out["event_mismatch"] = np.zeros(0, dtype=np.int64)
+        out["n_flagged"] = 0
+    return out
+
+
+def restart_from_oracle(sim, ref):
+    """Load the oracle's state into the GPU simulation (oracle -> GPU only)."""
+    for s, f in enumerate(ref.fields):
+        sim.write(B.FIELD, f.astype(np.float32), s)
+    sim.write(B.CONE_POS, ref.pos.astype(np.float32))
+    sim.write(B.CONE_DIR, ref.dir.astype(np.float32))
+    sim.write(B.CONE_STATUS, ref.status)
+    sim.write(B.CONE_TARGET, ref.target)
+    sim.write(B.CONE_EVENT_STEP, ref.event_step)
+    sim.write(B.STEP, np.array([ref.step_count], dtype=np.int64))
+
+
+def assert_parity(m, field_tol=FIELD_TOL, tip_tol=TIP_TOL, where=""):
+    assert max(m["field"]) <= field_tol, (where, m["field"])
+    assert m["tip_max"] <= tip_tol, (where, m["tip_max"])
+    assert len(m["event_mismatch"]) == 0, (where, m["event_mismatch"][:10])

@@ -1,0 +1,216 @@
+"""GPU (gfx950) path against the FP64 oracle through the C ABI.
+
+Bars: field max-abs / max <= 1e-5 per species; tips <= 1e-4 x longest side for cones the
+oracle did not flag as near-ties; identical events (status, target, step) for those cones.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import parity
+from paper_1405_3331_amd import binding as B
+from paper_1405_3331_amd import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [1, 0]   # one kernel sequence per step; library default (tiled when available)
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def run_pair(sc, steps, block_steps=0, check_every=None):
+    """Advance oracle and GPU side by side; check parity at every checkpoint."""
+    ref = oracle.OracleSim(sc)
+    sim = B.Simulation(sc, block_steps=block_steps)
+    check_every = check_every or steps
+    done = 0
+    worst = {"field": 0.0, "tip": 0.0}
+    while done < steps:
+        n = min(check_every, steps - done)
+        ref.step(n)
+        sim.step(n)
+        done += n
+        m = parity.compare(sim, ref, sc)
+        parity.assert_parity(m, where=f"step {done}")
+        worst["field"] = max(worst["field"], max(m["field"]))
+        worst["tip"] = max(worst["tip"], m["tip_max"])
+    return sim, ref, worst
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_small_2d_full_run(block):
+    """The 128^2 small workload, 1000 steps, checked every 100 steps."""
+    sc = S.small()
+    _say(f"small 2D 128^2 1000 steps block_steps={block}")
+    sim, ref, worst = run_pair(sc, 1000, block, 100)
+    _say(f"worst field {worst['field']:.2e} tip {worst['tip']:.2e}")
+    sim.close()
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_small_2d_windowed_tips(block):
+    """Windowed tip parity: restart the GPU from the oracle every 100 steps and compare
+    every 10 steps (removes dynamical amplification of rounding differences)."""
+    sc = S.small(seed=1)
+    ref = oracle.OracleSim(sc)
+    sim = B.Simulation(sc, block_steps=block)
+    for window in range(10):
+        parity.restart_from_oracle(sim, ref)
+        for _ in range(10):
+            ref.step(10)
+            sim.step(10)
+            m = parity.compare(sim, ref, sc)
+            parity.assert_parity(m, where=f"window {window} step {ref.step_count}")
+    sim.close()
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+@pytest.mark.parametrize("shape", [(100, 37), (37, 100), (2, 2), (3, 130), (257, 65)])
+def test_ragged_grids(shape, block):
+    n = shape[0] * shape[1]
+    sc = S.make_scenario("ragged", 2, shape, 1.0, 0.2, ((1.0, 0.01, 1.0),),
+                         min(3, n), (0.5, 2.0), 40, 6, seed=3)
+    _say(f"ragged {shape} block_steps={block}")
+    sim, ref, _ = run_pair(sc, 120, block, 40)
+    sim.close()
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_two_species_2d(block):
+    sc = S.make_scenario("2sp", 2, (90, 70), 0.5, 0.04, ((1.0, 0.01, 1.0), (0.5, 0.02, -1.0)),
+                         [4, 3], (0.5, 2.0), 80, 10, seed=4)
+    sim, ref, _ = run_pair(sc, 300, block, 100)
+    sim.close()
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_volume_3d_two_species(block):
+    sc = S.make_scenario("3d", 3, (24, 20, 18), 1.0, 0.15,
+                         ((1.0, 0.01, 1.0), (0.5, 0.02, -1.0)), [6, 6], (1.0, 1.0), 500, 40,
+                         seed=5)
+    _say(f"3D 24x20x18 two species block_steps={block}")
+    sim, ref, _ = run_pair(sc, 200, block, 50)
+    sim.close()
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_degenerate_cases(block):
+    # no cones, no targets, no sources: the field just decays
+    sc = S.make_scenario("empty", 2, (33, 17), 1.0, 0.2, ((1.0, 0.05, 1.0),), 0, (1, 1), 0, 0)
+    sc.init_field = [np.random.default_rng(0).random(sc.shape)]
+    sim, ref, _ = run_pair(sc, 50, block, 25)
+    assert sim.counts().tolist() == [0, 0, 0]
+    assert sim.events().shape == (0, 4)
+    sim.close()
+    # zero step length: cones never move; zero contact radius: no contacts
+    sc = S.make_scenario("still", 2, (40, 40), 1.0, 0.2, ((1.0, 0.01, 1.0),), 2, (1, 1), 30, 5,
+                         contact_radius=0.0, step_len=0.0)
+    sim, ref, _ = run_pair(sc, 30, block, 30)
+    c = sim.cones()
+    assert np.array_equal(c["pos"], sc.cone_pos.astype(np.float32))
+    sim.close()
+    # zero steps is a no-op
+    sim = B.Simulation(sc, block_steps=block)
+    sim.step(0)
+    assert sim.step_count == 0
+    sim.close()
+
+
+def test_mass_recursion_on_gpu():
+    """M^{n+1} = (1 - k dt) M^n + sum q, with the GPU's FP64-accumulated mass."""
+    sc = S.make_scenario("mass", 2, (200, 150), 1.0, 0.2, ((1.0, 0.01, 1.0),), 5, (0.5, 2.0),
+                         0, 0)
+    sim = B.Simulation(sc)
+    M = 0.0
+    kdt = sc.species[0].k * sc.dt
+    Q = float(np.sum(sc.species[0].source_q))
+    for n in range(10):
+        sim.step(100)
+        for _ in range(100):
+            M = (1 - kdt) * M + Q
+        got = sim.mass()[0]
+        assert abs(got - M) <= 2e-6 * M, (n, got, M)
+    sim.close()
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_bitwise_determinism_and_resume(block):
+    sc = S.make_scenario("det", 2, (120, 90), 1.0, 0.2, ((1.0, 0.01, 1.0),), 4, (0.5, 2.0),
+                         300, 20, seed=6)
+    a = B.Simulation(sc, block_steps=block).step(250)
+    b = B.Simulation(sc, block_steps=block).step(250)
+    fa, fb = a.field(), b.field()
+    assert np.array_equal(fa, fb)
+    ca, cb = a.cones(), b.cones()
+    for k in ca:
+        assert np.array_equal(ca[k], cb[k]), k
+    # resume: save at 100, restore into a fresh simulation, continue to 250
+    c = B.Simulation(sc, block_steps=block).step(100)
+    saved = dict(field=c.field(), **c.cones())
+    d = B.Simulation(sc, block_steps=block)
+    d.write(B.FIELD, saved["field"])
+    d.write(B.CONE_POS, saved["pos"])
+    d.write(B.CONE_DIR, saved["dir"])
+    d.write(B.CONE_STATUS, saved["status"])
+    d.write(B.CONE_TARGET, saved["target"])
+    d.write(B.CONE_EVENT_STEP, saved["event_step"])
+    d.write(B.STEP, np.array([100], dtype=np.int64))
+    d.step(150)
+    assert np.array_equal(d.field(), fa)
+    cd = d.cones()
+    for k in ca:
+        assert np.array_equal(ca[k], cd[k]), k
+    for s in (a, b, c, d):
+        s.close()
+
+
+def test_events_sorted_and_consistent():
+    sc = S.small(seed=2)
+    sim = B.Simulation(sc).step(1000)
+    ev = sim.events()
+    c = sim.cones()
+    stopped = np.nonzero(c["status"] != B.ACTIVE)[0]
+    assert len(ev) == len(stopped)
+    assert np.all(np.diff(ev[:, 2]) >= 0)
+    for cone, target, step, kind in ev:
+        assert c["status"][cone] == kind and c["event_step"][cone] == step
+        assert c["target"][cone] == target
+        if kind == B.CONTACT:
+            d = np.linalg.norm(c["pos"][cone] - sc.target_pos[target])
+            assert d < sc.contact_radius * (1 + 1e-6)
+    counts = sim.counts()
+    assert counts.sum() == sc.n_cones
+    sim.close()
+
+
+def test_headline_size_short_run_elementwise():
+    """The 2048^2 headline workload at full size in the default launch configuration: 20
+    steps compared element by element with the oracle."""
+    sc = S.headline()
+    _say("headline 2048^2, 65536 cones, 20 steps")
+    sim, ref, worst = run_pair(sc, 20, 0, 10)
+    _say(f"worst field {worst['field']:.2e} tip {worst['tip']:.2e}")
+    sim.close()
+
+
+def test_headline_size_long_run_mass():
+    """At full size over 2000 steps, the GPU field obeys the exact mass recursion."""
+    sc = S.headline()
+    sim = B.Simulation(sc)
+    kdt = sc.species[0].k * sc.dt
+    Q = float(np.sum(sc.species[0].source_q))
+    M = 0.0
+    for blk in range(4):
+        sim.step(500)
+        for _ in range(500):
+            M = (1 - kdt) * M + Q
+        got = sim.mass()[0]
+        assert abs(got - M) <= 1e-5 * M, (blk, got, M)
+    counts = sim.counts()
+    assert counts.sum() == sc.n_cones
+    sim.close()
