@@ -81,6 +81,7 @@ def main():
     print(f"[bench] {sc.name}: {sc.n_cells} cells, {sc.n_cones} cones, "
           f"warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
     sim = B.Simulation(sc, block_steps=args.block_steps)
+    tiling = sim.tiling()
     sim.step(args.warmup)
     sim.synchronize()
     if not args.no_kernel_timing:
@@ -123,7 +124,7 @@ def main():
         "config": {"workload": sc.name, "grid": [sc.nx, sc.ny], "cones": sc.n_cones,
                    "targets": sc.n_targets, "sources": len(sc.species[0].source_q),
                    "D": sc.species[0].D, "k": sc.species[0].k, "dt": sc.dt,
-                   "block_steps": args.block_steps},
+                   "tiling": tiling},
         "cone_steps_per_s": cone_steps / elapsed,
         "active_cone_steps": cone_steps,
         "effective_GBs": value * BYTES_PER_CELL_UPDATE / 1e9,

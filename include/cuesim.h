@@ -70,9 +70,12 @@ typedef enum sim_item {
     SIM_MASS = 7,            /* double[n_species]: sum(c) dx^dim, FP64 accumulation (r)  */
     SIM_STEP = 8,            /* int64[1] completed steps                           (r/w) */
     SIM_COUNTS = 9,          /* int32[3]: active, contact, exited                  (r)   */
-    SIM_KERNEL_TIME = 10     /* double[2]: summed device milliseconds and number of
+    SIM_KERNEL_TIME = 10,    /* double[2]: summed device milliseconds and number of
                                 launches of the step kernel since timing was last
                                 enabled (see sim_set_timing)                       (r)   */
+    SIM_TILING = 11          /* int32[8]: steps per launch B, halo H, core width TX,
+                                core height TY, number of tiles, columns per lane,
+                                loaded height, LDS bytes per tile (B = 1: no tiling) (r) */
 } sim_item;
 
 #define SIM_MAX_SPECIES 2

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ECFL", -3: "SIM_ENOMEM",
 ACTIVE, CONTACT, EXITED = 0, 1, 2
 
 FIELD, CONE_POS, CONE_DIR, CONE_STATUS, CONE_TARGET, CONE_EVENT_STEP, EVENTS, MASS, STEP, \
-    COUNTS, KERNEL_TIME = range(11)
+    COUNTS, KERNEL_TIME, TILING = range(12)
 
 EXPORTED = ["sim_create", "sim_step", "sim_read_state", "sim_write_state", "sim_device_ptr",
             "sim_set_timing", "sim_synchronize", "sim_destroy", "sim_last_error"]
@@ -176,7 +176,7 @@ def _item_bytes(h, what, index):
 def sim_read_state(h, what: int, index: int = 0, shape=None) -> np.ndarray:
     dtype = {MASS: np.float64, STEP: np.int64, KERNEL_TIME: np.float64,
              CONE_STATUS: np.int32, CONE_TARGET: np.int32, CONE_EVENT_STEP: np.int32,
-             EVENTS: np.int32, COUNTS: np.int32}.get(what, np.float32)
+             EVENTS: np.int32, COUNTS: np.int32, TILING: np.int32}.get(what, np.float32)
     need = _item_bytes(h, what, index)
     out = np.empty(need // np.dtype(dtype).itemsize, dtype=dtype)
     written = C.c_size_t(0)
@@ -253,6 +253,12 @@ class Simulation:
 
     def counts(self) -> np.ndarray:
         return sim_read_state(self.h, COUNTS)
+
+    def tiling(self) -> dict:
+        v = sim_read_state(self.h, TILING)
+        keys = ["block_steps", "halo", "core_x", "core_y", "tiles", "cols_per_lane",
+                "height", "lds_bytes"]
+        return dict(zip(keys, (int(x) for x in v)))
 
     @property
     def step_count(self) -> int:

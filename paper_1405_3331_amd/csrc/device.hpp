@@ -73,6 +73,34 @@ struct TargetGrid {
     float r2;                    // contact radius squared (FP32)
 };
 
+// Keep (d2, idx) if it beats the best so far: strictly closer, or equally close with a
+// lower original index.  best starts at (r2, -1), so only d2 < r2 is ever accepted.
+__device__ __forceinline__ void closer(float d2, int idx, float& best_d2, int& best) {
+    if (d2 < best_d2 || (d2 == best_d2 && best >= 0 && idx < best)) {
+        best_d2 = d2;
+        best = idx;
+    }
+}
+
+// Nearest target in a list (x, y, z, original index as bits), same rule as below.
+template <int dim>
+__device__ __forceinline__ int contact_in_list(const float4* pts, int n, float r2, float x,
+                                               float y, float z) {
+    float best_d2 = r2;
+    int best = -1;
+    for (int k = 0; k < n; ++k) {
+        const float4 t = pts[k];
+        const float ddx = x - t.x, ddy = y - t.y;
+        float d2 = ddx * ddx + ddy * ddy;
+        if (dim == 3) {
+            const float ddz = z - t.z;
+            d2 += ddz * ddz;
+        }
+        closer(d2, __float_as_int(t.w), best_d2, best);
+    }
+    return best;
+}
+
 // Nearest target with squared distance strictly below r2; ties on the squared distance go
 // to the lowest original index.  Returns -1 when none is in range.
 template <int dim>
@@ -97,11 +125,7 @@ __device__ __forceinline__ int contact_target(const TargetGrid& tg, float x, flo
                     const float ddz = z - t.z;
                     d2 += ddz * ddz;
                 }
-                const int idx = __float_as_int(t.w);
-                if (d2 < best_d2 || (d2 == best_d2 && best >= 0 && idx < best)) {
-                    best_d2 = d2;
-                    best = idx;
-                }
+                closer(d2, __float_as_int(t.w), best_d2, best);
             }
         }
     return best;
@@ -191,11 +215,21 @@ struct ConeEvent {
     int target;   // contacted target or -1
 };
 
+// Contact test against the simulation's whole target grid.
+struct GridContact {
+    const TargetGrid* tg;
+    template <int dim>
+    __device__ int find(float x, float y, float z) const { return contact_target<dim>(*tg, x, y, z); }
+};
+
 // One step of an active 2D cone: turn toward h + gain*g (capped), noise, advance, exit,
-// contact.  `step` is the number of completed steps n before this one.
+// contact.  `step` is the number of completed steps n before this one.  `contact` finds
+// the nearest target in range (GridContact, or a list staged in LDS).
+template <class Contact>
 __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, float gy,
                                                   uint32_t id, uint32_t step, float& x,
-                                                  float& y, float& theta) {
+                                                  float& y, float& theta,
+                                                  const Contact& contact) {
     float s, c;
     sincosf(theta, &s, &c);
     float cross = r.gain * (c * gy - s * gx);
@@ -218,7 +252,7 @@ __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, 
         ev.status = kExited;
         return ev;
     }
-    const int t = contact_target<2>(r.targets, x, y, 0.0f);
+    const int t = contact.template find<2>(x, y, 0.0f);
     if (t >= 0) {
         ev.status = kContact;
         ev.target = t;
@@ -227,10 +261,12 @@ __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, 
 }
 
 // One step of an active 3D cone with unit heading (hx, hy, hz).
+template <class Contact>
 __device__ __forceinline__ ConeEvent cone_step_3d(const ConeRules& r, float gx, float gy,
                                                   float gz, uint32_t id, uint32_t step,
                                                   float& x, float& y, float& z, float& hx,
-                                                  float& hy, float& hz) {
+                                                  float& hy, float& hz,
+                                                  const Contact& contact) {
     // turn in the plane of h and g, toward h + gain*g, by at most max_turn
     const float gh = gx * hx + gy * hy + gz * hz;
     const float px = gx - gh * hx, py = gy - gh * hy, pz = gz - gh * hz;
@@ -273,7 +309,7 @@ __device__ __forceinline__ ConeEvent cone_step_3d(const ConeRules& r, float gx, 
         ev.status = kExited;
         return ev;
     }
-    const int t = contact_target<3>(r.targets, x, y, z);
+    const int t = contact.template find<3>(x, y, z);
     if (t >= 0) {
         ev.status = kContact;
         ev.target = t;

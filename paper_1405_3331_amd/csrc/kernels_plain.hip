@@ -81,7 +81,8 @@ __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __res
         gx = fmaf(r.sign1, hx, gx);
         gy = fmaf(r.sign1, hy, gy);
     }
-    const ConeEvent ev = cone_step_2d(r, gx, gy, (uint32_t)i, step, x, y, th);
+    const ConeEvent ev = cone_step_2d(r, gx, gy, (uint32_t)i, step, x, y, th,
+                                      GridContact{&r.targets});
     c.pos[2 * i] = x;
     c.pos[2 * i + 1] = y;
     c.dir[i] = th;
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(256) void k_cones3d(ConeRules r, const float* __res
         gy = fmaf(r.sign1, ay, gy);
         gz = fmaf(r.sign1, az, gz);
     }
-    const ConeEvent ev = cone_step_3d(r, gx, gy, gz, (uint32_t)i, step, x, y, z, hx, hy, hz);
+    const ConeEvent ev = cone_step_3d(r, gx, gy, gz, (uint32_t)i, step, x, y, z, hx, hy, hz,
+                                      GridContact{&r.targets});
     c.pos[3 * i] = x;
     c.pos[3 * i + 1] = y;
     c.pos[3 * i + 2] = z;

@@ -1,27 +1,650 @@
-// kernels_tiled.hip -- temporally blocked, LDS-tiled step kernel (not yet enabled: the
-// plan reports no usable tiling, so every step runs the plain kernels).
+// kernels_tiled.hip -- temporally blocked, LDS-tiled step kernel for 2D grids.
+//
+// One launch advances B steps.  Each workgroup owns one tile: a core of TX x TY cells plus
+// a halo of H cells on every side, loaded once from HBM into LDS.  Each sub-step updates
+// the whole tile in LDS (the valid region shrinks by one cell per sub-step), adds the
+// sources that fall in the tile, and then steps the growth cones bucketed to the tile
+// against the just-updated LDS field -- the field update precedes the cone step within a
+// step, as in the paper's time step.  After B sub-steps the core is written back and every
+// surviving cone is appended to the bucket of the tile that now holds its tip.
+//
+// Halo: a cone bucketed to the core at block start is at most ceil((B-1) s / dx) cells away
+// from the core before its last sub-step and samples cells up to 2 away from its own cell,
+// while the valid region after sub-step b is the core grown by H - b; so
+// H = B + ceil((B-1) s / dx) + 2 keeps every sample inside valid cells.
+//
+// Layout of a tile row in LDS: one wavefront spans the loaded width W = 64 * CPL, lane l
+// owning columns CPL*l .. CPL*l + CPL-1.  The eight wavefronts of a workgroup own
+// consecutive strips of rows and update them in place (see strip_update).
+//
+// HBM traffic per launch: the tile with its halo is read once and the core written once,
+// instead of B reads and B writes of every cell.
 #include "tiled.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <vector>
 
 namespace cuesim {
 
-TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
-                     int block_steps, int n_cones) {
-    (void)step_cells;
-    (void)block_steps;
-    (void)n_cones;
-    TiledPlan p;
-    p.dim = dim;
-    p.nx = nx;
-    p.ny = ny;
-    p.nz = nz;
-    p.n_species = n_species;
-    p.block_steps = 1;
-    return p;
+namespace {
+
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kMaxTileTargets = 256;        // targets staged in LDS per tile
+constexpr size_t kLdsBudget = 154 * 1024;   // dynamic LDS; the rest is static (targets,
+                                            // re-bucketing counters)
+constexpr int kLoadBatch = 4;               // tile rows a wavefront has in flight at load
+constexpr size_t kStaticLds = kMaxTileTargets * 16 + 3 * 9 * 4;   // static LDS per tile
+constexpr int kGuardRows = 4;               // one above and three below each species plane
+
+struct TiledArgs2D {
+    const float* in[SIM_MAX_SPECIES];
+    float* out[SIM_MAX_SPECIES];
+    StencilCoef coef[SIM_MAX_SPECIES];
+    int nx, ny;
+    int tiles_x, n_tiles;
+    int tx_core, ty_core, halo, height;   // TX, TY, H, loaded height HL
+    int steps;
+    uint32_t first_step;
+    const int32_t* src_start;
+    const int2* src_entry;     // (LDS index within the species plane, species)
+    const float* src_amount;
+    const int32_t* tgt_start;  // per tile: targets within reach of its cones this launch
+    const float4* tgt_pts;
+    float4* bucket_in;         // cones at block start (x, y, theta, id bits); this tile's
+                               // slots are owned by its workgroup and updated in place
+    int32_t* count_in;         // zeroed by each workgroup for reuse as the next output
+    float4* bucket_out;
+    int32_t* count_out;
+    int capacity;
+    ConeArrays cones;
+    ConeRules rules;
+};
+
+template <int CPL>
+struct Row;
+template <>
+struct Row<2> {
+    using T = float2;
+};
+template <>
+struct Row<4> {
+    using T = float4;
+};
+
+__device__ __forceinline__ float comp(const float2& v, int k) { return k == 0 ? v.x : v.y; }
+__device__ __forceinline__ float comp(const float4& v, int k) {
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ void set_comp(float2& v, int k, float x) {
+    if (k == 0) v.x = x; else v.y = x;
+}
+__device__ __forceinline__ void set_comp(float4& v, int k, float x) {
+    if (k == 0) v.x = x; else if (k == 1) v.y = x; else if (k == 2) v.z = x; else v.w = x;
 }
 
-hipError_t tiled_allocate(const TiledPlan&, TiledState&, int, const ConeRules&,
-                          const sim_params*, hipStream_t) {
-    return hipErrorNotSupported;
+// LDS view of one species with tile-origin offset; indices are clamped to the tile so a
+// sample can never leave the LDS allocation.
+struct LdsField2D {
+    const float* L;
+    int x0, y0, width, height;
+    __device__ float operator()(int i, int j) const {
+        const int lx = min(max(i - x0, 0), width - 1);
+        const int ly = min(max(j - y0, 0), height - 1);
+        return L[ly * width + lx];
+    }
+};
+
+// New value of the CPL cells of one row from the old rows above (s), at (c) and below (n).
+// Horizontal neighbours across lanes come from the adjacent lanes' registers.  WALLS selects
+// the zero-flux rule for tiles that touch the grid boundary.
+template <int CPL, bool WALLS>
+__device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CPL>::T& s_in,
+                                                           const typename Row<CPL>::T& c,
+                                                           const typename Row<CPL>::T& n_in,
+                                                           int gy, int gx0, int nx, int ny,
+                                                           StencilCoef cf) {
+    using V = typename Row<CPL>::T;
+    const float left = __shfl_up(comp(c, CPL - 1), 1, 64);  // column cx - 1
+    const float right = __shfl_down(comp(c, 0), 1, 64);     // column cx + CPL
+    V s = s_in, n = n_in;
+    if (WALLS) {
+        if (gy == 0) s = c;
+        if (gy == ny - 1) n = c;
+    }
+    V nv;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const float ck = comp(c, k);
+        float w = k == 0 ? left : comp(c, k - 1);
+        float e = k == CPL - 1 ? right : comp(c, k + 1);
+        if (WALLS) {
+            if (gx0 + k == 0) w = ck;
+            if (gx0 + k == nx - 1) e = ck;
+        }
+        const float lap = ((w + e) + (comp(s, k) + comp(n, k))) - 4.0f * ck;
+        set_comp(nv, k, fmaf(cf.r, lap, fmaf(-cf.kdt, ck, ck)));
+    }
+    return nv;
+}
+
+// One stencil + decay sub-step of one species over a wavefront's strip of rows
+// [ybeg, yend), in place.  L points at tile row 0; rows -1 and HL .. HL+2 are guard rows
+// (never meaningful) so reads, which reach at most two rows past the strip, need no
+// clamping.  Within a wavefront every LDS read of a row
+// is issued before that row's write, so interior rows are overwritten as soon as they are
+// computed; the strip's first and last rows are read by the neighbouring wavefronts and
+// are returned for writing after a barrier.  Four row registers cycle through their roles
+// (above / at / below / prefetched), so rows are prefetched two ahead with no register
+// moves: a prefetched row is either this strip's, still unmodified, or a neighbour's first
+// row, written only after the barrier (or is never used).
+template <int CPL>
+struct StripEdges {
+    typename Row<CPL>::T first, last;
+};
+
+template <int CPL, bool WALLS>
+__device__ __forceinline__ StripEdges<CPL> strip_update(float* L, int ybeg, int yend, int cx,
+                                                        int gx0, int y0, int nx, int ny,
+                                                        StencilCoef cf) {
+    using V = typename Row<CPL>::T;
+    V first = {}, last = {};
+    constexpr int W = 64 * CPL;
+    const float* rd = L + cx;
+    float* wr = L + cx;
+    V A = *(const V*)&rd[(ybeg - 1) * W];
+    V Bv = *(const V*)&rd[ybeg * W];
+    V C = *(const V*)&rd[(ybeg + 1) * W];
+    V D = *(const V*)&rd[(ybeg + 2) * W];
+#define CUESIM_PUT(yy, nv)                  \
+    do {                                    \
+        if ((yy) == ybeg)                   \
+            first = (nv);                   \
+        else if ((yy) == yend - 1)          \
+            last = (nv);                    \
+        else                                \
+            *(V*)&wr[(yy) * W] = (nv);      \
+    } while (0)
+    int y = ybeg;
+    for (; y + 4 <= yend; y += 4) {
+        V nv = row_update<CPL, WALLS>(A, Bv, C, y0 + y, gx0, nx, ny, cf);
+        A = *(const V*)&rd[(y + 3) * W];
+        CUESIM_PUT(y, nv);
+        nv = row_update<CPL, WALLS>(Bv, C, D, y0 + y + 1, gx0, nx, ny, cf);
+        Bv = *(const V*)&rd[(y + 4) * W];
+        CUESIM_PUT(y + 1, nv);
+        nv = row_update<CPL, WALLS>(C, D, A, y0 + y + 2, gx0, nx, ny, cf);
+        C = *(const V*)&rd[(y + 5) * W];
+        CUESIM_PUT(y + 2, nv);
+        nv = row_update<CPL, WALLS>(D, A, Bv, y0 + y + 3, gx0, nx, ny, cf);
+        D = *(const V*)&rd[(y + 6) * W];
+        CUESIM_PUT(y + 3, nv);
+    }
+    // remaining 0..3 rows, same register roles as at the top of a group
+    if (y < yend) {
+        V nv = row_update<CPL, WALLS>(A, Bv, C, y0 + y, gx0, nx, ny, cf);
+        A = *(const V*)&rd[(y + 3) * W];
+        CUESIM_PUT(y, nv);
+        if (y + 1 < yend) {
+            nv = row_update<CPL, WALLS>(Bv, C, D, y0 + y + 1, gx0, nx, ny, cf);
+            CUESIM_PUT(y + 1, nv);
+            if (y + 2 < yend) {
+                nv = row_update<CPL, WALLS>(C, D, A, y0 + y + 2, gx0, nx, ny, cf);
+                CUESIM_PUT(y + 2, nv);
+            }
+        }
+    }
+#undef CUESIM_PUT
+    return StripEdges<CPL>{first, last};
+}
+
+// Contact test against the targets staged for this tile (a superset of every target within
+// the contact radius of any tip the tile's cones can reach in this launch), or against the
+// whole grid when the tile's list did not fit in LDS.
+struct TileContact {
+    const float4* pts;
+    int n;
+    bool staged;
+    const TargetGrid* grid;
+    template <int dim>
+    __device__ int find(float x, float y, float z) const {
+        return staged ? contact_in_list<dim>(pts, n, grid->r2, x, y, z)
+                      : contact_target<dim>(*grid, x, y, z);
+    }
+};
+
+// The cone step in two parts.  The first samples the signed gradient g at the tip from the
+// LDS field (the only part that reads the field); the second turns, adds noise, advances
+// and tests exit and contact using g and registers only, so it may run while the next
+// sub-step already overwrites the field.
+template <int NS>
+__device__ __forceinline__ float2 tile_cone_gradient(const float4& st, const LdsField2D& f0,
+                                                     const LdsField2D& f1,
+                                                     const ConeRules& rules) {
+    float gxv = 0.0f, gyv = 0.0f;
+    if (__float_as_int(st.w) < 0) return make_float2(gxv, gyv);
+    gradient_2d(f0, rules, st.x, st.y, gxv, gyv);
+    gxv *= rules.sign0;
+    gyv *= rules.sign0;
+    if (NS > 1) {
+        float hx, hy;
+        gradient_2d(f1, rules, st.x, st.y, hx, hy);
+        gxv = fmaf(rules.sign1, hx, gxv);
+        gyv = fmaf(rules.sign1, hy, gyv);
+    }
+    return make_float2(gxv, gyv);
+}
+
+// Second part; a stopped cone has its final state written to the caller-order arrays and
+// the sign bit of its id set.
+__device__ __forceinline__ void tile_cone_advance(float4& st, float2 g, const ConeRules& rules,
+                                                  uint32_t step, const TileContact& contact,
+                                                  const ConeArrays& cones) {
+    int id = __float_as_int(st.w);
+    if (id < 0) return;
+    float x = st.x, y = st.y, th = st.z;
+    const ConeEvent ev = cone_step_2d(rules, g.x, g.y, (uint32_t)id, step, x, y, th, contact);
+    if (ev.status != kActive) {
+        cones.pos[2 * id] = x;
+        cones.pos[2 * id + 1] = y;
+        cones.dir[id] = th;
+        cones.status[id] = ev.status;
+        cones.target[id] = ev.target;
+        cones.event_step[id] = (int32_t)(step + 1);
+        id = (int)((unsigned)id | 0x80000000u);
+    }
+    st = make_float4(x, y, th, __int_as_float(id));
+}
+
+__device__ __forceinline__ int cell_of(float p, float inv_dx, int n) {
+    return min(max((int)floorf(p * inv_dx), 0), n - 1);
+}
+
+// Destination tile of a cone's tip after a launch, restricted to the 3x3 neighbourhood of
+// the tile it was stepped in (the halo guarantees it never moves further).
+__device__ __forceinline__ int2 next_tile(const float4& st, int tx, int ty, int tiles_x,
+                                          int tiles_y, float inv_dx, int nx, int ny,
+                                          int tx_core, int ty_core) {
+    int ntx = cell_of(st.x, inv_dx, nx) / tx_core;
+    int nty = cell_of(st.y, inv_dx, ny) / ty_core;
+    ntx = min(max(ntx, max(tx - 1, 0)), min(tx + 1, tiles_x - 1));
+    nty = min(max(nty, max(ty - 1, 0)), min(ty + 1, tiles_y - 1));
+    return make_int2(ntx, nty);
+}
+
+template <int NS, int CPL>
+__global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
+    using V = typename Row<CPL>::T;
+    constexpr int W = 64 * CPL;
+    extern __shared__ __align__(16) float lds[];
+    __shared__ int dest_count[9];
+    __shared__ int dest_base[9];
+    __shared__ int dest_fill[9];
+    __shared__ float4 tile_targets[kMaxTileTargets];
+
+    const int tile = blockIdx.x;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int tiles_y = a.n_tiles / a.tiles_x;
+    const int HL = a.height, H = a.halo;
+    const int x0 = tx * a.tx_core - H, y0 = ty * a.ty_core - H;
+    // species plane: guard row, HL tile rows, three guard rows; row 0 at offset W
+    const int plane = W * (HL + kGuardRows);
+    // the wavefront index is uniform across a wavefront: keep it (and the strip bounds
+    // derived from it) in scalar registers so strip bookkeeping is scalar work
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int cx = CPL * lane;
+    const int gx0 = x0 + cx;
+
+    // 1. load the tile, kLoadBatch rows in flight per wavefront; cells outside the grid
+    //    read as zero and are never used by cells inside it, which take their own value
+    //    for out-of-grid neighbours
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        for (int ly0 = wave; ly0 < HL; ly0 += kLoadBatch * kWaves) {
+            V v[kLoadBatch];
+#pragma unroll
+            for (int r = 0; r < kLoadBatch; ++r) {
+                const int ly = ly0 + r * kWaves;
+                const int gy = y0 + ly;
+                const bool row_in = ly < HL && (unsigned)gy < (unsigned)a.ny;
+                const size_t at = row_in ? (size_t)gy * a.nx : 0;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const int gx = gx0 + k;
+                    set_comp(v[r], k, row_in && (unsigned)gx < (unsigned)a.nx ? a.in[s][at + gx]
+                                                                              : 0.0f);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kLoadBatch; ++r) {
+                const int ly = ly0 + r * kWaves;
+                if (ly < HL) *(V*)&lds[s * plane + (ly + 1) * W + cx] = v[r];
+            }
+        }
+    }
+    const int n_cones = a.count_in[tile];
+    float4* live = a.bucket_in + (size_t)tile * a.capacity;
+    const int t_lo = a.tgt_start[tile], n_tt = a.tgt_start[tile + 1] - t_lo;
+    const TileContact contact{tile_targets, n_tt, n_tt <= kMaxTileTargets, &a.rules.targets};
+    if (contact.staged)
+        for (int k = threadIdx.x; k < n_tt; k += kThreads) tile_targets[k] = a.tgt_pts[t_lo + k];
+    // the first kThreads cones stay in registers for the whole launch
+    float4 mine = threadIdx.x < n_cones ? live[threadIdx.x]
+                                        : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    if (threadIdx.x < 9) {
+        dest_count[threadIdx.x] = 0;
+        dest_fill[threadIdx.x] = 0;
+    }
+    __syncthreads();
+
+    const int R = (HL + kWaves - 1) / kWaves;
+    const int ybeg = min(wave * R, HL), yend = min(ybeg + R, HL);
+    const int src_lo = a.src_start[tile], src_hi = a.src_start[tile + 1];
+    const ConeRules& rules = a.rules;
+    const bool walls = x0 <= 0 || x0 + W >= a.nx || y0 <= 0 || y0 + HL >= a.ny;
+    const LdsField2D f0{lds + W, x0, y0, W, HL};
+    const LdsField2D f1{lds + (NS > 1 ? plane : 0) + W, x0, y0, W, HL};
+
+    for (int b = 0; b < a.steps; ++b) {
+        // 2. stencil + decay over the whole tile, in place, strip per wavefront
+        StripEdges<CPL> edge[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (ybeg < yend) {
+                if (walls)
+                    edge[s] = strip_update<CPL, true>(lds + s * plane + W, ybeg, yend, cx, gx0,
+                                                      y0, a.nx, a.ny, a.coef[s]);
+                else
+                    edge[s] = strip_update<CPL, false>(lds + s * plane + W, ybeg, yend, cx, gx0,
+                                                       y0, a.nx, a.ny, a.coef[s]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (ybeg < yend) *(V*)&lds[s * plane + (ybeg + 1) * W + cx] = edge[s].first;
+            if (yend - 1 > ybeg) *(V*)&lds[s * plane + yend * W + cx] = edge[s].last;
+        }
+        __syncthreads();
+        // 3. sources inside the tile (entries are unique cells per species)
+        if (src_hi > src_lo) {
+            for (int e = src_lo + threadIdx.x; e < src_hi; e += kThreads) {
+                const int2 ent = a.src_entry[e];
+                lds[ent.y * plane + W + ent.x] += a.src_amount[e];
+            }
+            __syncthreads();
+        }
+        // 4. cones against the updated field.  Every read of the field happens before the
+        //    barrier (gradients of the register-held cones; whole steps of any further
+        //    cones); the register-held cones then finish their step after it, overlapping
+        //    the next sub-step's in-place stencil, which they no longer read.
+        const uint32_t step = a.first_step + (uint32_t)b;
+        if (n_cones > 0) {
+            const float2 g = tile_cone_gradient<NS>(mine, f0, f1, rules);
+            for (int i = threadIdx.x + kThreads; i < n_cones; i += kThreads) {
+                float4 st = live[i];
+                tile_cone_advance(st, tile_cone_gradient<NS>(st, f0, f1, rules), rules, step,
+                                  contact, a.cones);
+                live[i] = st;
+            }
+            __syncthreads();
+            tile_cone_advance(mine, g, rules, step, contact, a.cones);
+        }
+    }
+
+    // 5. write the core back
+    const int cx0 = tx * a.tx_core, cy0 = ty * a.ty_core;
+    for (int ly = wave; ly < a.ty_core; ly += kWaves) {
+        const int gy = cy0 + ly;
+        if (gy >= a.ny) break;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const V v = *(const V*)&lds[s * plane + (ly + H + 1) * W + cx];
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                const int lx = cx + k - H;   // core column of this lane's k-th cell
+                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx)
+                    a.out[s][(size_t)gy * a.nx + cx0 + lx] = comp(v, k);
+            }
+        }
+    }
+
+    // 6. re-bucket surviving cones into the tile that now holds their tip
+    if (threadIdx.x < n_cones) live[threadIdx.x] = mine;
+    for (int i = threadIdx.x; i < n_cones; i += kThreads) {
+        const float4 st = i == (int)threadIdx.x ? mine : live[i];
+        if (__float_as_int(st.w) < 0) continue;
+        const int2 nt = next_tile(st, tx, ty, a.tiles_x, tiles_y, rules.inv_dx, a.nx, a.ny,
+                                  a.tx_core, a.ty_core);
+        atomicAdd(&dest_count[(nt.y - ty + 1) * 3 + (nt.x - tx + 1)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 9 && dest_count[threadIdx.x] > 0) {
+        const int dtx = tx + threadIdx.x % 3 - 1, dty = ty + threadIdx.x / 3 - 1;
+        dest_base[threadIdx.x] = atomicAdd(&a.count_out[dty * a.tiles_x + dtx],
+                                           dest_count[threadIdx.x]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_cones; i += kThreads) {
+        const float4 st = i == (int)threadIdx.x ? mine : live[i];
+        if (__float_as_int(st.w) < 0) continue;
+        const int2 nt = next_tile(st, tx, ty, a.tiles_x, tiles_y, rules.inv_dx, a.nx, a.ny,
+                                  a.tx_core, a.ty_core);
+        const int d = (nt.y - ty + 1) * 3 + (nt.x - tx + 1);
+        const int slot = dest_base[d] + atomicAdd(&dest_fill[d], 1);
+        a.bucket_out[(size_t)(nt.y * a.tiles_x + nt.x) * a.capacity + slot] = st;
+    }
+    if (threadIdx.x == 0) a.count_in[tile] = 0;
+}
+
+// Initial bucketing from the caller-order arrays (active cones only).
+__global__ void k_bucket2d(ConeArrays c, int nx, int ny, int tx_core, int ty_core, int tiles_x,
+                           float inv_dx, float4* bucket, int32_t* count, int capacity) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n || c.status[i] != kActive) return;
+    const float x = c.pos[2 * i], y = c.pos[2 * i + 1];
+    const int t = cell_of(y, inv_dx, ny) / ty_core * tiles_x + cell_of(x, inv_dx, nx) / tx_core;
+    const int slot = atomicAdd(&count[t], 1);
+    bucket[(size_t)t * capacity + slot] = make_float4(x, y, c.dir[i], __int_as_float(i));
+}
+
+// Active cones from the buckets back into the caller-order arrays.
+__global__ void k_unbucket2d(ConeArrays c, const float4* bucket, const int32_t* count,
+                             int capacity) {
+    const int t = blockIdx.x;
+    const int n = count[t];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const float4 st = bucket[(size_t)t * capacity + k];
+        const int id = __float_as_int(st.w);
+        if (id < 0) continue;
+        c.pos[2 * id] = st.x;
+        c.pos[2 * id + 1] = st.y;
+        c.dir[id] = st.z;
+    }
+}
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+const void* kernel_for(int n_species, int cpl) {
+    if (n_species == 1)
+        return cpl == 4 ? (const void*)k_tiled2d<1, 4> : (const void*)k_tiled2d<1, 2>;
+    return cpl == 4 ? (const void*)k_tiled2d<2, 4> : (const void*)k_tiled2d<2, 2>;
+}
+
+}  // namespace
+
+TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
+                     int block_steps, int n_cones) {
+    TiledPlan best;
+    best.dim = dim;
+    best.nx = nx;
+    best.ny = ny;
+    best.nz = nz;
+    best.n_species = n_species;
+    best.block_steps = 1;
+    if (dim != 2 || block_steps < 2) return best;
+    // Tuning hook: CUESIM_TILE="cpl,height" forces the row width (64 * cpl) and the loaded
+    // tile height when that shape is valid.
+    int force_cpl = 0, force_height = 0;
+    if (const char* env = std::getenv("CUESIM_TILE"))   // height 0: any height
+        if (std::sscanf(env, "%d,%d", &force_cpl, &force_height) != 2) force_cpl = force_height = 0;
+    double best_cost = 1e300;
+    for (int B = block_steps; B >= 2; --B) {
+        // halo: B sub-steps of shrinkage + cone travel before the last sub-step + the
+        // gradient footprint (two cells); the small epsilon covers FP32 rounding of travel
+        const int travel = (int)std::ceil((B - 1) * step_cells + 1e-3);
+        const int H = B + travel + 2;
+        const int move = (int)std::ceil(B * step_cells + 1e-3);
+        for (int cpl : {2, 4}) {
+            if (force_cpl && cpl != force_cpl) continue;
+            const int W = 64 * cpl;
+            const int TX = W - 2 * H;
+            if (TX < 16 || TX <= move) continue;
+            const int max_height =
+                (int)(kLdsBudget / ((size_t)n_species * W * sizeof(float))) - kGuardRows;
+            for (int HL = 2 * H + 16; HL <= max_height; ++HL) {
+                if (force_height && HL != force_height) continue;
+                const int TY = HL - 2 * H;
+                if (TY <= move) continue;
+                const size_t lds = (size_t)n_species * W * (HL + kGuardRows) * sizeof(float);
+                const int tiles = ceil_div(nx, TX) * ceil_div(ny, TY);
+                const int per_cu = ceil_div(tiles, 256);
+                const size_t per_cu_lds = 160 * 1024;
+                const int resident = std::max(1, std::min(2, (int)(per_cu_lds / (lds + kStaticLds))));
+                // per-step cost in cell-updates per compute unit: each tile's loaded area
+                // per sub-step plus its load/store per launch; one resident tile per CU
+                // hides latency poorly
+                double cost = (double)per_cu * W * HL * (1.0 + 2.0 / B) / B;
+                if (resident < 2 || per_cu > resident) cost *= 1.25;
+                if (cost < best_cost * 0.999) {
+                    best_cost = cost;
+                    best.block_steps = B;
+                    best.move = move;
+                    best.halo = H;
+                    best.cpl = cpl;
+                    best.core_x = TX;
+                    best.core_y = TY;
+                    best.tiles_x = ceil_div(nx, TX);
+                    best.tiles_y = ceil_div(ny, TY);
+                    best.n_tiles = best.tiles_x * best.tiles_y;
+                    best.lds_bytes = lds;
+                    best.height = HL;
+                }
+            }
+        }
+        if (best.block_steps > 1) break;   // prefer the deepest blocking that fits
+    }
+    (void)n_cones;
+    return best;
+}
+
+hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
+                          const ConeRules& rules, const sim_params* p, hipStream_t stream) {
+    (void)rules;
+    hipError_t e;
+    const int W = 64 * plan.cpl;
+    st.capacity = std::max(1, n_cones);
+    const size_t slots = (size_t)plan.n_tiles * st.capacity;
+    for (int b = 0; b < 2; ++b) {
+        if ((e = hipMalloc(&st.bucket[b], slots * sizeof(float4))) != hipSuccess) return e;
+        if ((e = hipMalloc(&st.count[b], plan.n_tiles * sizeof(int32_t))) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(st.count[b], 0, plan.n_tiles * sizeof(int32_t), stream)) != hipSuccess)
+            return e;
+    }
+    st.cur = 0;
+    // per-tile source entries: every unique source cell inside a tile's loaded region
+    std::vector<std::vector<std::pair<int2, float>>> per_tile(plan.n_tiles);
+    const double vol = std::pow(p->dx, p->dim);
+    for (int s = 0; s < p->n_species; ++s) {
+        std::map<int32_t, double> merged;
+        for (int m = 0; m < p->n_sources[s]; ++m)
+            merged[p->source_cell[s][m]] += (double)p->source_q[s][m] / vol;
+        for (auto& kv : merged) {
+            const int gx = kv.first % plan.nx, gy = kv.first / plan.nx;
+            for (int ty = 0; ty < plan.tiles_y; ++ty) {
+                const int y0 = ty * plan.core_y - plan.halo;
+                if (gy < y0 || gy >= y0 + plan.height) continue;
+                for (int tx = 0; tx < plan.tiles_x; ++tx) {
+                    const int x0 = tx * plan.core_x - plan.halo;
+                    if (gx < x0 || gx >= x0 + W) continue;
+                    const int local = (gy - y0) * W + (gx - x0);
+                    per_tile[ty * plan.tiles_x + tx].push_back({make_int2(local, s), (float)kv.second});
+                }
+            }
+        }
+    }
+    std::vector<int32_t> start(plan.n_tiles + 1, 0);
+    std::vector<int2> entry;
+    std::vector<float> amount;
+    for (int t = 0; t < plan.n_tiles; ++t) {
+        for (auto& en : per_tile[t]) {
+            entry.push_back(en.first);
+            amount.push_back(en.second);
+        }
+        start[t + 1] = (int32_t)entry.size();
+    }
+    if ((e = hipMalloc(&st.src_start, start.size() * sizeof(int32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc(&st.src_entry, std::max<size_t>(1, entry.size()) * sizeof(int2))) != hipSuccess)
+        return e;
+    if ((e = hipMalloc(&st.src_amount, std::max<size_t>(1, amount.size()) * sizeof(float))) != hipSuccess)
+        return e;
+    if ((e = hipMemcpy(st.src_start, start.data(), start.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if (!entry.empty()) {
+        if ((e = hipMemcpy(st.src_entry, entry.data(), entry.size() * sizeof(int2),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpy(st.src_amount, amount.data(), amount.size() * sizeof(float),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+    }
+    // per-tile target lists: every target within reach of a tip that starts the launch in
+    // the tile core (core grown by the launch's travel, plus the contact radius)
+    {
+        const double reach = (plan.move + 1) * p->dx + p->contact_radius;
+        std::vector<std::vector<float4>> lists(plan.n_tiles);
+        for (int t = 0; t < p->n_targets; ++t) {
+            const float tx_ = p->target_pos[2 * t], ty_ = p->target_pos[2 * t + 1];
+            for (int ty = 0; ty < plan.tiles_y; ++ty) {
+                const double ylo = ty * plan.core_y * p->dx - reach;
+                const double yhi = (ty + 1) * plan.core_y * p->dx + reach;
+                if (ty_ < ylo || ty_ > yhi) continue;
+                for (int tx = 0; tx < plan.tiles_x; ++tx) {
+                    const double xlo = tx * plan.core_x * p->dx - reach;
+                    const double xhi = (tx + 1) * plan.core_x * p->dx + reach;
+                    if (tx_ < xlo || tx_ > xhi) continue;
+                    float4 v = make_float4(tx_, ty_, 0.0f, 0.0f);
+                    int32_t idx = t;
+                    std::memcpy(&v.w, &idx, sizeof idx);
+                    lists[ty * plan.tiles_x + tx].push_back(v);
+                }
+            }
+        }
+        std::vector<int32_t> tstart(plan.n_tiles + 1, 0);
+        std::vector<float4> tpts;
+        for (int t = 0; t < plan.n_tiles; ++t) {
+            tpts.insert(tpts.end(), lists[t].begin(), lists[t].end());
+            tstart[t + 1] = (int32_t)tpts.size();
+        }
+        if (tpts.empty()) tpts.push_back(make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+        if ((e = hipMalloc(&st.tgt_start, tstart.size() * sizeof(int32_t))) != hipSuccess) return e;
+        if ((e = hipMalloc(&st.tgt_pts, tpts.size() * sizeof(float4))) != hipSuccess) return e;
+        if ((e = hipMemcpy(st.tgt_start, tstart.data(), tstart.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpy(st.tgt_pts, tpts.data(), tpts.size() * sizeof(float4),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+    }
+    return hipFuncSetAttribute(kernel_for(plan.n_species, plan.cpl),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
 }
 
 void tiled_release(TiledState& st) {
@@ -34,22 +657,78 @@ void tiled_release(TiledState& st) {
     (void)hipFree(st.src_start);
     (void)hipFree(st.src_entry);
     (void)hipFree(st.src_amount);
+    (void)hipFree(st.tgt_start);
+    (void)hipFree(st.tgt_pts);
+    st.tgt_start = nullptr;
+    st.tgt_pts = nullptr;
     st.src_start = nullptr;
     st.src_entry = nullptr;
     st.src_amount = nullptr;
 }
 
-hipError_t tiled_bucket(const TiledPlan&, TiledState&, ConeArrays, hipStream_t) {
-    return hipErrorNotSupported;
+hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
+                        hipStream_t stream) {
+    hipError_t e;
+    for (int b = 0; b < 2; ++b)
+        if ((e = hipMemsetAsync(st.count[b], 0, plan.n_tiles * sizeof(int32_t), stream)) != hipSuccess)
+            return e;
+    st.cur = 0;
+    if (cones.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket2d, dim3(ceil_div(cones.n, 256)), dim3(256), 0, stream, cones,
+                       plan.nx, plan.ny, plan.core_x, plan.core_y, plan.tiles_x,
+                       plan.inv_dx, st.bucket[0], st.count[0], st.capacity);
+    return hipGetLastError();
 }
 
-hipError_t tiled_unbucket(const TiledPlan&, TiledState&, ConeArrays, hipStream_t) {
-    return hipErrorNotSupported;
+hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_unbucket2d, dim3(plan.n_tiles), dim3(256), 0, stream, cones,
+                       st.bucket[st.cur], st.count[st.cur], st.capacity);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int b = 0; b < 2; ++b)
+        if ((e = hipMemsetAsync(st.count[b], 0, plan.n_tiles * sizeof(int32_t), stream)) != hipSuccess)
+            return e;
+    return hipSuccess;
 }
 
-hipError_t tiled_launch(const TiledPlan&, TiledState&, const ConeRules&, float* const[],
-                        float* const[], ConeArrays, int, uint32_t, hipStream_t) {
-    return hipErrorNotSupported;
+hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, const ConeRules& rules,
+                        float* const in[], float* const out[], ConeArrays cones, int steps,
+                        uint32_t first_step, hipStream_t stream) {
+    TiledArgs2D a = {};
+    for (int s = 0; s < plan.n_species; ++s) {
+        a.in[s] = in[s];
+        a.out[s] = out[s];
+        a.coef[s] = plan.coef[s];
+    }
+    a.nx = plan.nx;
+    a.ny = plan.ny;
+    a.tiles_x = plan.tiles_x;
+    a.n_tiles = plan.n_tiles;
+    a.tx_core = plan.core_x;
+    a.ty_core = plan.core_y;
+    a.halo = plan.halo;
+    a.height = plan.height;
+    a.steps = steps;
+    a.first_step = first_step;
+    a.src_start = st.src_start;
+    a.src_entry = st.src_entry;
+    a.src_amount = st.src_amount;
+    a.tgt_start = st.tgt_start;
+    a.tgt_pts = st.tgt_pts;
+    a.bucket_in = st.bucket[st.cur];
+    a.count_in = st.count[st.cur];
+    a.bucket_out = st.bucket[st.cur ^ 1];
+    a.count_out = st.count[st.cur ^ 1];
+    a.capacity = st.capacity;
+    a.cones = cones;
+    a.rules = rules;
+    void* args[] = {&a};
+    const hipError_t e = hipLaunchKernel(kernel_for(plan.n_species, plan.cpl),
+                                         dim3(plan.n_tiles), dim3(kThreads), args,
+                                         plan.lds_bytes, stream);
+    if (e == hipSuccess) st.cur ^= 1;
+    return e;
 }
 
 }  // namespace cuesim

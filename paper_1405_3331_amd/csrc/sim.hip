@@ -311,6 +311,7 @@ sim_status item_size(sim_handle* h, sim_item what, int32_t index, size_t* bytes)
         case SIM_STEP: *bytes = sizeof(int64_t); break;
         case SIM_COUNTS: *bytes = 3 * sizeof(int32_t); break;
         case SIM_KERNEL_TIME: *bytes = 2 * sizeof(double); break;
+        case SIM_TILING: *bytes = 8 * sizeof(int32_t); break;
         case SIM_EVENTS: *bytes = 0; break;  // computed by the caller of item_size
         default: return fail(h, SIM_EINVAL, "unknown item %d", (int)what);
     }
@@ -512,6 +513,8 @@ sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out) {
     if (h->block_steps > 1) {
         h->plan = tiled_plan(h->dim, h->nx, h->ny, h->nz, h->n_species, p->step_len / p->dx,
                              h->block_steps, h->n_cones);
+        h->plan.inv_dx = h->rules.inv_dx;
+        for (int s = 0; s < h->n_species; ++s) h->plan.coef[s] = h->coef[s];
         if (h->plan.block_steps <= 1) {
             h->block_steps = 1;   // no tile shape fits: fall back to one step per launch
         } else {
@@ -627,6 +630,15 @@ sim_status sim_read_state(sim_handle* h, sim_item what, int32_t index, void* dst
         case SIM_STEP:
             std::memcpy(dst, &h->step, sizeof(int64_t));
             return SIM_OK;
+        case SIM_TILING: {
+            const TiledPlan& t = h->plan;
+            const bool tiled = h->block_steps > 1;
+            int32_t v[8] = {tiled ? t.block_steps : 1, tiled ? t.halo : 0, tiled ? t.core_x : 0,
+                            tiled ? t.core_y : 0, tiled ? t.n_tiles : 0, tiled ? t.cpl : 0,
+                            tiled ? t.height : 0, tiled ? (int32_t)t.lds_bytes : 0};
+            std::memcpy(dst, v, sizeof v);
+            return SIM_OK;
+        }
         case SIM_KERNEL_TIME: {
             HIP_TRY(h, hipStreamSynchronize(h->stream));
             st = collect_timing(h);

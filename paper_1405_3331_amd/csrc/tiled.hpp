@@ -9,7 +9,7 @@
 
 namespace cuesim {
 
-constexpr int kDefaultBlockSteps = 1;
+constexpr int kDefaultBlockSteps = 8;
 
 // Tile geometry chosen once per simulation.
 struct TiledPlan {
@@ -19,8 +19,13 @@ struct TiledPlan {
     int core_x = 0, core_y = 0, core_z = 1;
     int tiles_x = 0, tiles_y = 0, tiles_z = 1;
     int n_tiles = 0;
+    int height = 0;          // loaded tile height (rows), core_y + 2 * halo
+    int move = 0;            // cells a tip can travel in one launch, ceil(B * s / dx)
+    int cpl = 2;             // columns per lane: loaded tile width is 64 * cpl
     int n_species = 1;
     int nx = 0, ny = 0, nz = 1;
+    float inv_dx = 1.0f;
+    StencilCoef coef[SIM_MAX_SPECIES] = {};
     size_t lds_bytes = 0;
 };
 
@@ -33,8 +38,11 @@ struct TiledState {
     int32_t* src_start = nullptr;              // per tile: range into src_entry
     int2* src_entry = nullptr;                 // (tile-local cell index, species)
     float* src_amount = nullptr;
+    int32_t* tgt_start = nullptr;              // per tile: range into tgt_pts
+    float4* tgt_pts = nullptr;                 // targets a tile's cones can reach
 };
 
+// Choose B and the tile shape; block_steps = 1 in the result means no tiling fits.
 TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
                      int block_steps, int n_cones);
 hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,

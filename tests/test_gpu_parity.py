@@ -16,7 +16,8 @@ from paper_1405_3331_amd import scenarios as S
 
 pytestmark = pytest.mark.gpu
 
-BLOCKS = [1, 0]   # one kernel sequence per step; library default (tiled when available)
+# one kernel sequence per step; library default (tiled, 8 steps per launch); 3 steps
+BLOCKS = [1, 0, 3]
 
 
 def _say(msg):
