@@ -26,11 +26,60 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1405_3331_amd import autotune  # noqa: E402
 from paper_1405_3331_amd import binding as B  # noqa: E402
 from paper_1405_3331_amd import scenarios as S  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_UPDATE = 8.0
+# Counter-derived HBM traffic of the step kernel, recorded from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs; used only while the kernel sources still hash to the recorded value.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tiled_step_headline_2048_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1405_3331_amd", "csrc", f)
+                  for f in ("kernels_tiled.hip", "device.hpp", "tiled.hpp", "internal.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(tiling):
+    """HBM bytes per launch from the committed counter record, or None when the record is
+    missing, was taken for another tiling, or the kernel sources changed since."""
+    try:
+        rec = dict(line.strip().split("=", 1) for line in open(TRAFFIC_RECORD)
+                   if "=" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    if rec.get("tiling") != json.dumps(tiling, sort_keys=True):
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
+def copy_calibration(mbytes):
+    """Device-to-device copy of a known size (the runtime's blit kernel), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    n = int(mbytes) << 20
+    src, dst = C.c_void_p(), C.c_void_p()
+    assert hip.hipMalloc(C.byref(src), C.c_size_t(n)) == 0
+    assert hip.hipMalloc(C.byref(dst), C.c_size_t(n)) == 0
+    assert hip.hipMemset(src, 1, C.c_size_t(n)) == 0
+    for _ in range(3):
+        assert hip.hipMemcpy(dst, src, C.c_size_t(n), 3) == 0   # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(src)
+    hip.hipFree(dst)
+    print(f"[bench] copy calibration: 3 x {n} bytes device to device", file=sys.stderr,
+          flush=True)
 
 
 def active_cone_steps(event_step, start, end):
@@ -61,26 +110,138 @@ def cpu_baseline(sc, steps):
     }
 
 
+def bench_batched(args):
+    """512 uneven simulations: one persistent launch per block of steps (hipGraph replay)
+    against the same simulations advanced one after another through sim_step."""
+    scs = S.batched(count=args.batch_count)
+    cells = sum(sc.n_cells for sc in scs)
+    steps = args.batch_steps
+    print(f"[bench] batched: {len(scs)} simulations, {cells} cells, {steps} steps",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    bt = B.Batch(scs, graph_launches=args.graph_launches)
+    create_s = time.perf_counter() - t0
+    bt.step(args.graph_launches * 8 if args.graph_launches else 8)   # warm-up
+    bt.synchronize()
+    t0 = time.perf_counter()
+    bt.step(steps)
+    bt.synchronize()
+    batched_s = time.perf_counter() - t0
+    bt.close()
+    # the same simulations one at a time (library default path per simulation)
+    sims = [B.Simulation(sc) for sc in scs]
+    for sim in sims:
+        sim.step(8)
+    for sim in sims:
+        sim.synchronize()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(steps)
+    for sim in sims:
+        sim.synchronize()
+    single_s = time.perf_counter() - t0
+    for sim in sims:
+        sim.close()
+    out = {
+        "metric": "batched cell-updates/s vs one simulation at a time (same GPU)",
+        "value": cells * steps / batched_s,
+        "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": steps, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched {len(scs)} 2D simulations, side U{{64..512}}, "
+                               "cones log-uniform [16, 4096]", "cells": cells,
+                   "cones": sum(sc.n_cones for sc in scs),
+                   "graph_launches": args.graph_launches},
+        "one_at_a_time_value": cells * steps / single_s,
+        "speedup_vs_one_at_a_time": single_s / batched_s,
+        "create_s": create_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_volume(args):
+    """3D 256^3 two-species workload through the per-step path (stencil kernel per species,
+    sources, one thread per cone)."""
+    sc = S.volume()
+    ns = len(sc.species)
+    steps = args.volume_steps
+    print(f"[bench] {sc.name}: {sc.n_cells} cells x {ns} species, {sc.n_cones} cones, "
+          f"{steps} steps", file=sys.stderr, flush=True)
+    sim = B.Simulation(sc)
+    sim.step(10)
+    sim.synchronize()
+    B.sim_set_timing(sim.h, True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktime = B.sim_read_state(sim.h, B.KERNEL_TIME)
+    c = sim.cones()
+    cone_steps = active_cone_steps(c["event_step"], 10, 10 + steps)
+    sim.close()
+    updates = sc.n_cells * ns * steps
+    avg_us = ktime[0] / ktime[1] * 1e3
+    achieved = BYTES_PER_CELL_UPDATE * sc.n_cells / (avg_us * 1e-6) / 1e9
+    out = {
+        "metric": "species-cell-updates/s & cone-steps/s, 3D 256^3 two species",
+        "value": updates / elapsed, "unit": "species-cell-updates/s", "n_gpus": 1,
+        "steps": steps, "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": sc.name, "grid": [sc.nx, sc.ny, sc.nz], "species": ns,
+                   "cones": sc.n_cones, "targets": sc.n_targets},
+        "cone_steps_per_s": cone_steps / elapsed,
+        "roofline": {"bound": "hbm", "kernel": "stencil (one species, one step)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "kernel_avg_us": avg_us},
+    }
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(sc, max(1, args.cpu_steps // 20))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--block-steps", type=int, default=0,
-                    help="steps per launch of the tiled kernel (0 = library default)")
+                    help="steps per launch of the tiled kernel (0 = the autotuner's record "
+                         "for this workload, else the library default)")
     ap.add_argument("--cpu-steps", type=int, default=60,
                     help="steps of the oracle timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run a device-to-device copy of this size first (for counters)")
+    ap.add_argument("--batched", action="store_true",
+                    help="measure the batched workload instead of the headline one")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--graph-launches", type=int, default=10)
+    ap.add_argument("--volume", action="store_true",
+                    help="measure the 3D two-species workload instead of the headline one")
+    ap.add_argument("--volume-steps", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
               "supported (the single-GPU kernel is the unit of scaling)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration_mb > 0:
+        copy_calibration(args.copy_calibration_mb)
+    if args.batched:
+        bench_batched(args)
+        return
+    if args.volume:
+        bench_volume(args)
+        return
     sc = S.headline()
+    block = args.block_steps
+    if block == 0:   # blocking depth and tile shape recorded by the autotuner, if any
+        block = autotune.apply(sc)
     print(f"[bench] {sc.name}: {sc.n_cells} cells, {sc.n_cones} cones, "
-          f"warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
-    sim = B.Simulation(sc, block_steps=args.block_steps)
+          f"warmup {args.warmup}, timed {args.steps}, block_steps {block or 'default'}",
+          file=sys.stderr, flush=True)
+    sim = B.Simulation(sc, block_steps=block)
     tiling = sim.tiling()
     sim.step(args.warmup)
     sim.synchronize()
@@ -104,8 +265,9 @@ def main():
         steps_per_launch = args.steps / launches
         algo_bytes = BYTES_PER_CELL_UPDATE * cells * steps_per_launch
         achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
+        traffic = recorded_traffic(tiling) if tiling["block_steps"] > 1 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "kernel_avg_us": avg_ms * 1e3, "launches": launches,
                     "steps_per_launch": steps_per_launch}
     out = {

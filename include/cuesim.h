@@ -112,6 +112,10 @@ typedef struct sim_params {
     int32_t block_steps;               /* steps fused into one launch of the tiled kernel;
                                           0 = library default, 1 = one kernel sequence per
                                           step (no temporal blocking), max 32 */
+    int32_t tile_cols_per_lane;        /* tiled kernel row width 64 * this (2 or 4);
+                                          0 = chosen by the library's planner */
+    int32_t tile_height;               /* loaded tile height in rows; 0 = planner's choice.
+                                          A hint that does not fit is ignored */
 } sim_params;
 
 typedef struct sim_handle sim_handle;
@@ -157,6 +161,38 @@ sim_status sim_destroy(sim_handle* h);
 /* Message for the last failed call on h, or for the calling thread's last failed
  * sim_create when h is NULL.  Library-owned, valid until the next call on h. */
 const char* sim_last_error(const sim_handle* h);
+
+/* ----------------------------------------------------------------------------------------
+ * Batches: many independent 2D simulations (same n_species and block_steps, any grid size,
+ * cone and target counts) advanced together.  Each block of steps is ONE persistent
+ * launch in which a fixed grid of workgroups pulls (simulation, tile) work items from an
+ * atomic queue, so uneven simulations share the GPU; every simulation computes exactly what
+ * it would compute alone (its own Philox key and sim_index).
+ * ---------------------------------------------------------------------------------------- */
+typedef struct sim_batch sim_batch;
+
+/* Create n simulations from params[0..n-1] (each validated as by sim_create; arrays
+ * copied).  graph_launches > 0 captures that many full-depth launches in a hipGraph that
+ * sim_batch_step replays; 0 launches directly.  Errors as sim_create; *out = NULL on error
+ * and sim_batch_last_error(NULL) describes it. */
+sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hip_stream,
+                            int32_t graph_launches, sim_batch** out);
+
+/* Enqueue n_steps >= 0 steps of every simulation of the batch. */
+sim_status sim_batch_step(sim_batch* b, int64_t n_steps);
+
+/* sim_read_state of simulation `sim` (0 <= sim < n). */
+sim_status sim_batch_read_state(sim_batch* b, int32_t sim, sim_item what, int32_t index,
+                                void* dst, size_t dst_bytes, size_t* bytes_written);
+
+/* Block until the batch's stream is idle. */
+sim_status sim_batch_synchronize(sim_batch* b);
+
+/* Release everything; NULL is a no-op. */
+sim_status sim_batch_destroy(sim_batch* b);
+
+/* Message for the last failed call on b (or the thread's last failed batch create). */
+const char* sim_batch_last_error(const sim_batch* b);
 
 #ifdef __cplusplus
 }

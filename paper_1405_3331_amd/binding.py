@@ -27,7 +27,9 @@ FIELD, CONE_POS, CONE_DIR, CONE_STATUS, CONE_TARGET, CONE_EVENT_STEP, EVENTS, MA
     COUNTS, KERNEL_TIME, TILING = range(12)
 
 EXPORTED = ["sim_create", "sim_step", "sim_read_state", "sim_write_state", "sim_device_ptr",
-            "sim_set_timing", "sim_synchronize", "sim_destroy", "sim_last_error"]
+            "sim_set_timing", "sim_synchronize", "sim_destroy", "sim_last_error",
+            "sim_batch_create", "sim_batch_step", "sim_batch_read_state",
+            "sim_batch_synchronize", "sim_batch_destroy", "sim_batch_last_error"]
 
 
 class SimError(RuntimeError):
@@ -54,6 +56,7 @@ class SimParams(C.Structure):
         ("step_len", C.c_double), ("turn_gain", C.c_double), ("max_turn", C.c_double),
         ("noise_sigma", C.c_double),
         ("seed", C.c_uint64), ("sim_index", C.c_uint32), ("block_steps", C.c_int32),
+        ("tile_cols_per_lane", C.c_int32), ("tile_height", C.c_int32),
     ]
 
 
@@ -82,8 +85,18 @@ def load(path: str = LIBRARY):
     lib.sim_destroy.argtypes = [H]
     lib.sim_last_error.argtypes = [H]
     lib.sim_last_error.restype = C.c_char_p
-    for name in EXPORTED[:-1]:
-        getattr(lib, name).restype = C.c_int
+    lib.sim_batch_create.argtypes = [C.POINTER(C.POINTER(SimParams)), C.c_int32, C.c_void_p,
+                                     C.c_int32, C.POINTER(H)]
+    lib.sim_batch_step.argtypes = [H, C.c_int64]
+    lib.sim_batch_read_state.argtypes = [H, C.c_int32, C.c_int, C.c_int32, C.c_void_p,
+                                         C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.sim_batch_synchronize.argtypes = [H]
+    lib.sim_batch_destroy.argtypes = [H]
+    lib.sim_batch_last_error.argtypes = [H]
+    lib.sim_batch_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if not name.endswith("last_error"):
+            getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
 
@@ -139,6 +152,8 @@ def make_params(sc, block_steps: int = 0):
     p.max_turn, p.noise_sigma = sc.max_turn, sc.noise_sigma
     p.seed, p.sim_index = sc.seed, sc.sim_index
     p.block_steps = block_steps
+    tile = getattr(sc, "tile", None) or (0, 0)   # (cols per lane, height) hint, 0 = planner
+    p.tile_cols_per_lane, p.tile_height = int(tile[0]), int(tile[1])
     return p, keep
 
 
@@ -274,6 +289,112 @@ class Simulation:
     def close(self):
         if self.h is not None:
             sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# -- batches ----------------------------------------------------------------------------
+
+def _check_batch(status, handle=None):
+    if status != SIM_OK:
+        msg = load().sim_batch_last_error(handle)
+        raise SimError(status, msg.decode() if msg else "")
+
+
+def sim_batch_create(scenarios, stream=None, graph_launches: int = 0, block_steps: int = 0):
+    lib = load()
+    made = [make_params(sc, block_steps) for sc in scenarios]
+    arr = (C.POINTER(SimParams) * len(made))(*[C.pointer(p) for p, _ in made])
+    h = C.c_void_p()
+    _check_batch(lib.sim_batch_create(arr, len(made), _stream_handle(stream), graph_launches,
+                                      C.byref(h)))
+    del made
+    return h
+
+
+def sim_batch_step(b, n_steps: int):
+    _check_batch(load().sim_batch_step(b, int(n_steps)), b)
+
+
+def sim_batch_read_state(b, sim: int, what: int, index: int = 0, shape=None) -> np.ndarray:
+    dtype = {MASS: np.float64, STEP: np.int64, KERNEL_TIME: np.float64,
+             CONE_STATUS: np.int32, CONE_TARGET: np.int32, CONE_EVENT_STEP: np.int32,
+             EVENTS: np.int32, COUNTS: np.int32, TILING: np.int32}.get(what, np.float32)
+    lib = load()
+    need = C.c_size_t(0)
+    st = lib.sim_batch_read_state(b, sim, what, index, None, 0, C.byref(need))
+    if st not in (SIM_OK, SIM_ERANGE):
+        _check_batch(st, b)
+    out = np.empty(need.value // np.dtype(dtype).itemsize, dtype=dtype)
+    _check_batch(lib.sim_batch_read_state(b, sim, what, index,
+                                          out.ctypes.data_as(C.c_void_p), out.nbytes,
+                                          C.byref(need)), b)
+    if what == EVENTS:
+        out = out.reshape(-1, 4)
+    if shape is not None:
+        out = out.reshape(shape)
+    return out
+
+
+def sim_batch_synchronize(b):
+    _check_batch(load().sim_batch_synchronize(b), b)
+
+
+def sim_batch_destroy(b):
+    _check_batch(load().sim_batch_destroy(b))
+
+
+def sim_batch_last_error(b=None) -> str:
+    msg = load().sim_batch_last_error(b)
+    return msg.decode() if msg else ""
+
+
+class Batch:
+    """Owning wrapper around a batch of simulations."""
+
+    def __init__(self, scenarios, stream=None, graph_launches: int = 0, block_steps: int = 0):
+        self.scenarios = list(scenarios)
+        self.h = sim_batch_create(self.scenarios, stream, graph_launches, block_steps)
+
+    def step(self, n: int = 1):
+        sim_batch_step(self.h, n)
+        return self
+
+    def field(self, i: int, s: int = 0) -> np.ndarray:
+        return sim_batch_read_state(self.h, i, FIELD, s, self.scenarios[i].shape)
+
+    def cones(self, i: int):
+        sc = self.scenarios[i]
+        M = sc.n_cones
+        return dict(pos=sim_batch_read_state(self.h, i, CONE_POS, 0, (M, sc.dim)),
+                    dir=sim_batch_read_state(self.h, i, CONE_DIR, 0, (M,)),
+                    status=sim_batch_read_state(self.h, i, CONE_STATUS),
+                    target=sim_batch_read_state(self.h, i, CONE_TARGET),
+                    event_step=sim_batch_read_state(self.h, i, CONE_EVENT_STEP))
+
+    def tiling(self, i: int) -> dict:
+        v = sim_batch_read_state(self.h, i, TILING)
+        keys = ["block_steps", "halo", "core_x", "core_y", "tiles", "cols_per_lane",
+                "height", "lds_bytes"]
+        return dict(zip(keys, (int(x) for x in v)))
+
+    def synchronize(self):
+        sim_batch_synchronize(self.h)
+
+    def close(self):
+        if self.h is not None:
+            sim_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

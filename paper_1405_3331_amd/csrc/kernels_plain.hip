@@ -28,24 +28,38 @@ __global__ __launch_bounds__(kRowThreads) void k_field2d(const float* __restrict
     out[at] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
 }
 
-__global__ __launch_bounds__(kRowThreads) void k_field3d(const float* __restrict__ in,
-                                                         float* __restrict__ out, int nx,
-                                                         int ny, int nz, StencilCoef coef) {
-    const int i = blockIdx.x * kRowThreads + threadIdx.x;
-    const int j = blockIdx.y;
-    const int l = blockIdx.z;
-    if (i >= nx) return;
-    const int plane = nx * ny;
-    const int at = l * plane + j * nx + i;
-    const float c = in[at];
-    const float w = i > 0 ? in[at - 1] : c;
-    const float e = i < nx - 1 ? in[at + 1] : c;
-    const float s = j > 0 ? in[at - nx] : c;
-    const float n = j < ny - 1 ? in[at + nx] : c;
-    const float b = l > 0 ? in[at - plane] : c;
-    const float t = l < nz - 1 ? in[at + plane] : c;
-    const float lap = (((w + e) + (s + n)) + (b + t)) - 6.0f * c;
-    out[at] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
+// 3D stencil marching along z: a workgroup covers an x-y tile of kStreamX x kStreamY
+// columns and kStreamZ consecutive planes; each thread keeps the planes below, at and above
+// its cell in registers, so every cell is read from HBM about once per step while the
+// in-plane neighbours come from lines the workgroup has just brought into L1.
+constexpr int kStreamX = 64, kStreamY = 4, kStreamZ = 32;
+
+__global__ __launch_bounds__(kStreamX * kStreamY) void k_field3d_stream(
+    const float* __restrict__ in, float* __restrict__ out, int nx, int ny, int nz,
+    StencilCoef coef) {
+    const int i = blockIdx.x * kStreamX + threadIdx.x % kStreamX;
+    const int j = blockIdx.y * kStreamY + threadIdx.x / kStreamX;
+    const int z0 = blockIdx.z * kStreamZ;
+    const int z1 = min(z0 + kStreamZ, nz);
+    if (i >= nx || j >= ny) return;
+    const size_t plane = (size_t)nx * ny;
+    const float* col = in + (size_t)j * nx + i;
+    float* dst = out + (size_t)j * nx + i;
+    const bool west = i > 0, east = i < nx - 1, south = j > 0, north = j < ny - 1;
+    float c = col[z0 * plane];
+    float below = z0 > 0 ? col[(z0 - 1) * plane] : c;
+    for (int l = z0; l < z1; ++l) {
+        const float above = l + 1 < nz ? col[(l + 1) * plane] : c;
+        const float* p = col + l * plane;
+        const float w = west ? p[-1] : c;
+        const float e = east ? p[1] : c;
+        const float s = south ? p[-nx] : c;
+        const float n = north ? p[nx] : c;
+        const float lap = (((w + e) + (s + n)) + (below + above)) - 6.0f * c;
+        dst[l * plane] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
+        below = c;
+        c = above;
+    }
 }
 
 __global__ void k_sources(float* __restrict__ field, SourceList src) {
@@ -171,8 +185,10 @@ hipError_t launch_field_plain(int dim, int nx, int ny, int nz, const float* in, 
         hipLaunchKernelGGL(k_field2d, dim3(bx, ny), dim3(kRowThreads), 0, stream, in, out, nx,
                            ny, coef);
     else
-        hipLaunchKernelGGL(k_field3d, dim3(bx, ny, nz), dim3(kRowThreads), 0, stream, in, out,
-                           nx, ny, nz, coef);
+        hipLaunchKernelGGL(k_field3d_stream,
+                           dim3((nx + kStreamX - 1) / kStreamX, (ny + kStreamY - 1) / kStreamY,
+                                (nz + kStreamZ - 1) / kStreamZ),
+                           dim3(kStreamX * kStreamY), 0, stream, in, out, nx, ny, nz, coef);
     return hipGetLastError();
 }
 

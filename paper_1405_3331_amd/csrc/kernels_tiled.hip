@@ -39,32 +39,36 @@ constexpr int kMaxTileTargets = 256;        // targets staged in LDS per tile
 constexpr size_t kLdsBudget = 154 * 1024;   // dynamic LDS; the rest is static (targets,
                                             // re-bucketing counters)
 constexpr int kLoadBatch = 4;               // tile rows a wavefront has in flight at load
+constexpr int kConeSlots = 2;               // cones per thread held in registers
 constexpr size_t kStaticLds = kMaxTileTargets * 16 + 3 * 9 * 4;   // static LDS per tile
 constexpr int kGuardRows = 4;               // one above and three below each species plane
 
+}  // namespace
+
+// Static description of one simulation for the tiled kernel (device-resident table entry).
+// Everything that changes from launch to launch lives in LaunchState.
 struct TiledArgs2D {
-    const float* in[SIM_MAX_SPECIES];
-    float* out[SIM_MAX_SPECIES];
+    float* field[SIM_MAX_SPECIES][2];   // [species][ping-pong buffer]
     StencilCoef coef[SIM_MAX_SPECIES];
     int nx, ny;
     int tiles_x, n_tiles;
     int tx_core, ty_core, halo, height;   // TX, TY, H, loaded height HL
-    int steps;
-    uint32_t first_step;
     const int32_t* src_start;
     const int2* src_entry;     // (LDS index within the species plane, species)
     const float* src_amount;
     const int32_t* tgt_start;  // per tile: targets within reach of its cones this launch
     const float4* tgt_pts;
-    float4* bucket_in;         // cones at block start (x, y, theta, id bits); this tile's
-                               // slots are owned by its workgroup and updated in place
-    int32_t* count_in;         // zeroed by each workgroup for reuse as the next output
-    float4* bucket_out;
-    int32_t* count_out;
+    float4* bucket[2];         // per tile: cone slots (x, y, theta, id bits); the input
+                               // bucket's slots of a tile are owned by its workgroup and
+                               // updated in place
+    int32_t* count[2];         // the input counts are zeroed by each workgroup for reuse as
+                               // the next launch's output
     int capacity;
     ConeArrays cones;
     ConeRules rules;
 };
+
+namespace {
 
 template <int CPL>
 struct Row;
@@ -277,8 +281,11 @@ __device__ __forceinline__ int2 next_tile(const float4& st, int tx, int ty, int 
     return make_int2(ntx, nty);
 }
 
+// One tile of one simulation for `steps` sub-steps.  par selects the input half of every
+// ping-pong pair (fields and cone buckets); the other half is written.
 template <int NS, int CPL>
-__global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
+__device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int steps,
+                                          uint32_t first_step, int par) {
     using V = typename Row<CPL>::T;
     constexpr int W = 64 * CPL;
     extern __shared__ __align__(16) float lds[];
@@ -286,8 +293,13 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
     __shared__ int dest_base[9];
     __shared__ int dest_fill[9];
     __shared__ float4 tile_targets[kMaxTileTargets];
+    const float* in[SIM_MAX_SPECIES] = {a.field[0][par], a.field[NS > 1 ? 1 : 0][par]};
+    float* out[SIM_MAX_SPECIES] = {a.field[0][par ^ 1], a.field[NS > 1 ? 1 : 0][par ^ 1]};
+    float4* const bucket_in = a.bucket[par];
+    int32_t* const count_in = a.count[par];
+    float4* const bucket_out = a.bucket[par ^ 1];
+    int32_t* const count_out = a.count[par ^ 1];
 
-    const int tile = blockIdx.x;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int tiles_y = a.n_tiles / a.tiles_x;
     const int HL = a.height, H = a.halo;
@@ -317,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
 #pragma unroll
                 for (int k = 0; k < CPL; ++k) {
                     const int gx = gx0 + k;
-                    set_comp(v[r], k, row_in && (unsigned)gx < (unsigned)a.nx ? a.in[s][at + gx]
+                    set_comp(v[r], k, row_in && (unsigned)gx < (unsigned)a.nx ? in[s][at + gx]
                                                                               : 0.0f);
                 }
             }
@@ -328,15 +340,20 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
             }
         }
     }
-    const int n_cones = a.count_in[tile];
-    float4* live = a.bucket_in + (size_t)tile * a.capacity;
+    const int n_cones = count_in[tile];
+    float4* live = bucket_in + (size_t)tile * a.capacity;
     const int t_lo = a.tgt_start[tile], n_tt = a.tgt_start[tile + 1] - t_lo;
     const TileContact contact{tile_targets, n_tt, n_tt <= kMaxTileTargets, &a.rules.targets};
     if (contact.staged)
         for (int k = threadIdx.x; k < n_tt; k += kThreads) tile_targets[k] = a.tgt_pts[t_lo + k];
-    // the first kThreads cones stay in registers for the whole launch
-    float4 mine = threadIdx.x < n_cones ? live[threadIdx.x]
-                                        : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    // the first kConeSlots * kThreads cones stay in registers for the whole launch; cone
+    // i sits in thread i % kThreads, slot i / kThreads
+    float4 mine[kConeSlots];
+#pragma unroll
+    for (int k = 0; k < kConeSlots; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        mine[k] = i < n_cones ? live[i] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    }
     if (threadIdx.x < 9) {
         dest_count[threadIdx.x] = 0;
         dest_fill[threadIdx.x] = 0;
@@ -351,25 +368,28 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
     const LdsField2D f0{lds + W, x0, y0, W, HL};
     const LdsField2D f1{lds + (NS > 1 ? plane : 0) + W, x0, y0, W, HL};
 
-    for (int b = 0; b < a.steps; ++b) {
-        // 2. stencil + decay over the whole tile, in place, strip per wavefront
+    for (int b = 0; b < steps; ++b) {
+        // 2. stencil + decay, in place, strip per wavefront.  After this sub-step only rows
+        //    [b + 1, HL - b - 1) are still valid (each sub-step loses one row at either
+        //    edge of the tile), so rows outside that band are not computed.
+        const int lo = max(ybeg, b + 1), hi = min(yend, HL - b - 1);
         StripEdges<CPL> edge[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            if (ybeg < yend) {
+            if (lo < hi) {
                 if (walls)
-                    edge[s] = strip_update<CPL, true>(lds + s * plane + W, ybeg, yend, cx, gx0,
-                                                      y0, a.nx, a.ny, a.coef[s]);
+                    edge[s] = strip_update<CPL, true>(lds + s * plane + W, lo, hi, cx, gx0, y0,
+                                                      a.nx, a.ny, a.coef[s]);
                 else
-                    edge[s] = strip_update<CPL, false>(lds + s * plane + W, ybeg, yend, cx, gx0,
-                                                       y0, a.nx, a.ny, a.coef[s]);
+                    edge[s] = strip_update<CPL, false>(lds + s * plane + W, lo, hi, cx, gx0, y0,
+                                                       a.nx, a.ny, a.coef[s]);
             }
         }
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            if (ybeg < yend) *(V*)&lds[s * plane + (ybeg + 1) * W + cx] = edge[s].first;
-            if (yend - 1 > ybeg) *(V*)&lds[s * plane + yend * W + cx] = edge[s].last;
+            if (lo < hi) *(V*)&lds[s * plane + (lo + 1) * W + cx] = edge[s].first;
+            if (hi - 1 > lo) *(V*)&lds[s * plane + hi * W + cx] = edge[s].last;
         }
         __syncthreads();
         // 3. sources inside the tile (entries are unique cells per species)
@@ -384,17 +404,21 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
         //    barrier (gradients of the register-held cones; whole steps of any further
         //    cones); the register-held cones then finish their step after it, overlapping
         //    the next sub-step's in-place stencil, which they no longer read.
-        const uint32_t step = a.first_step + (uint32_t)b;
+        const uint32_t step = first_step + (uint32_t)b;
         if (n_cones > 0) {
-            const float2 g = tile_cone_gradient<NS>(mine, f0, f1, rules);
-            for (int i = threadIdx.x + kThreads; i < n_cones; i += kThreads) {
+            float2 g[kConeSlots];
+#pragma unroll
+            for (int k = 0; k < kConeSlots; ++k) g[k] = tile_cone_gradient<NS>(mine[k], f0, f1, rules);
+            for (int i = threadIdx.x + kConeSlots * kThreads; i < n_cones; i += kThreads) {
                 float4 st = live[i];
                 tile_cone_advance(st, tile_cone_gradient<NS>(st, f0, f1, rules), rules, step,
                                   contact, a.cones);
                 live[i] = st;
             }
             __syncthreads();
-            tile_cone_advance(mine, g, rules, step, contact, a.cones);
+#pragma unroll
+            for (int k = 0; k < kConeSlots; ++k)
+                tile_cone_advance(mine[k], g[k], rules, step, contact, a.cones);
         }
     }
 
@@ -410,15 +434,19 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
             for (int k = 0; k < CPL; ++k) {
                 const int lx = cx + k - H;   // core column of this lane's k-th cell
                 if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx)
-                    a.out[s][(size_t)gy * a.nx + cx0 + lx] = comp(v, k);
+                    out[s][(size_t)gy * a.nx + cx0 + lx] = comp(v, k);
             }
         }
     }
 
     // 6. re-bucket surviving cones into the tile that now holds their tip
-    if (threadIdx.x < n_cones) live[threadIdx.x] = mine;
+#pragma unroll
+    for (int k = 0; k < kConeSlots; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        if (i < n_cones) live[i] = mine[k];
+    }
     for (int i = threadIdx.x; i < n_cones; i += kThreads) {
-        const float4 st = i == (int)threadIdx.x ? mine : live[i];
+        const float4 st = live[i];
         if (__float_as_int(st.w) < 0) continue;
         const int2 nt = next_tile(st, tx, ty, a.tiles_x, tiles_y, rules.inv_dx, a.nx, a.ny,
                                   a.tx_core, a.ty_core);
@@ -427,20 +455,58 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D a) {
     __syncthreads();
     if (threadIdx.x < 9 && dest_count[threadIdx.x] > 0) {
         const int dtx = tx + threadIdx.x % 3 - 1, dty = ty + threadIdx.x / 3 - 1;
-        dest_base[threadIdx.x] = atomicAdd(&a.count_out[dty * a.tiles_x + dtx],
+        dest_base[threadIdx.x] = atomicAdd(&count_out[dty * a.tiles_x + dtx],
                                            dest_count[threadIdx.x]);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n_cones; i += kThreads) {
-        const float4 st = i == (int)threadIdx.x ? mine : live[i];
+        const float4 st = live[i];
         if (__float_as_int(st.w) < 0) continue;
         const int2 nt = next_tile(st, tx, ty, a.tiles_x, tiles_y, rules.inv_dx, a.nx, a.ny,
                                   a.tx_core, a.ty_core);
         const int d = (nt.y - ty + 1) * 3 + (nt.x - tx + 1);
         const int slot = dest_base[d] + atomicAdd(&dest_fill[d], 1);
-        a.bucket_out[(size_t)(nt.y * a.tiles_x + nt.x) * a.capacity + slot] = st;
+        bucket_out[(size_t)(nt.y * a.tiles_x + nt.x) * a.capacity + slot] = st;
     }
-    if (threadIdx.x == 0) a.count_in[tile] = 0;
+    if (threadIdx.x == 0) count_in[tile] = 0;
+}
+
+// The step kernel.  Work items are (simulation, tile) pairs; without an item list the
+// item is (0, blockIdx.x).  In persistent mode a fixed grid pulls items from an atomic
+// queue until it runs dry.  The launch state (step counter, ping-pong parity) is read by
+// every workgroup at its start and advanced by the last workgroup to finish, so launches
+// need no host-side bookkeeping and can be captured in a graph and replayed.
+template <int NS, int CPL>
+__global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restrict__ table,
+                                                      const int2* __restrict__ items,
+                                                      int n_items, int steps, LaunchState* ls,
+                                                      int persistent) {
+    __shared__ int item_idx;
+    const uint32_t first_step = ls->step;
+    const int par = ls->parity;
+    if (!persistent) {
+        const int2 it = items ? items[blockIdx.x] : make_int2(0, blockIdx.x);
+        tile_body<NS, CPL>(table[it.x], it.y, steps, first_step, par);
+    } else {
+        for (;;) {
+            __syncthreads();   // the previous item is done with LDS and item_idx
+            if (threadIdx.x == 0) item_idx = atomicAdd(&ls->next, 1);
+            __syncthreads();
+            const int i = item_idx;
+            if (i >= n_items) break;
+            const int2 it = items[i];
+            tile_body<NS, CPL>(table[it.x], it.y, steps, first_step, par);
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&ls->exited, 1) == (int)gridDim.x - 1) {
+            ls->exited = 0;
+            ls->next = 0;
+            ls->step = first_step + (uint32_t)steps;
+            ls->parity = par ^ 1;
+        }
+    }
 }
 
 // Initial bucketing from the caller-order arrays (active cones only).
@@ -479,8 +545,12 @@ const void* kernel_for(int n_species, int cpl) {
 
 }  // namespace
 
-TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
-                     int block_steps, int n_cones) {
+namespace {
+
+// Best tile plan by the cost model, restricted to row width 64 * only_cpl and loaded height
+// only_height when those are non-zero.
+TiledPlan plan_search(int dim, int nx, int ny, int nz, int n_species, double step_cells,
+                      int block_steps, int only_cpl, int only_height) {
     TiledPlan best;
     best.dim = dim;
     best.nx = nx;
@@ -489,11 +559,6 @@ TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step
     best.n_species = n_species;
     best.block_steps = 1;
     if (dim != 2 || block_steps < 2) return best;
-    // Tuning hook: CUESIM_TILE="cpl,height" forces the row width (64 * cpl) and the loaded
-    // tile height when that shape is valid.
-    int force_cpl = 0, force_height = 0;
-    if (const char* env = std::getenv("CUESIM_TILE"))   // height 0: any height
-        if (std::sscanf(env, "%d,%d", &force_cpl, &force_height) != 2) force_cpl = force_height = 0;
     double best_cost = 1e300;
     for (int B = block_steps; B >= 2; --B) {
         // halo: B sub-steps of shrinkage + cone travel before the last sub-step + the
@@ -502,14 +567,14 @@ TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step
         const int H = B + travel + 2;
         const int move = (int)std::ceil(B * step_cells + 1e-3);
         for (int cpl : {2, 4}) {
-            if (force_cpl && cpl != force_cpl) continue;
+            if (only_cpl && cpl != only_cpl) continue;
             const int W = 64 * cpl;
             const int TX = W - 2 * H;
             if (TX < 16 || TX <= move) continue;
             const int max_height =
                 (int)(kLdsBudget / ((size_t)n_species * W * sizeof(float))) - kGuardRows;
             for (int HL = 2 * H + 16; HL <= max_height; ++HL) {
-                if (force_height && HL != force_height) continue;
+                if (only_height && HL != only_height) continue;
                 const int TY = HL - 2 * H;
                 if (TY <= move) continue;
                 const size_t lds = (size_t)n_species * W * (HL + kGuardRows) * sizeof(float);
@@ -540,13 +605,25 @@ TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step
         }
         if (best.block_steps > 1) break;   // prefer the deepest blocking that fits
     }
-    (void)n_cones;
     return best;
 }
 
+}  // namespace
+
+TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
+                     int block_steps, int n_cones, int force_cpl, int force_height) {
+    (void)n_cones;
+    if (force_cpl != 0 || force_height != 0) {
+        const TiledPlan forced = plan_search(dim, nx, ny, nz, n_species, step_cells,
+                                             block_steps, force_cpl, force_height);
+        if (forced.block_steps > 1) return forced;
+    }
+    return plan_search(dim, nx, ny, nz, n_species, step_cells, block_steps, 0, 0);
+}
+
 hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
-                          const ConeRules& rules, const sim_params* p, hipStream_t stream) {
-    (void)rules;
+                          const ConeRules& rules, const sim_params* p, float* const fields[][2],
+                          ConeArrays cones, hipStream_t stream) {
     hipError_t e;
     const int W = 64 * plan.cpl;
     st.capacity = std::max(1, n_cones);
@@ -643,8 +720,47 @@ hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
                            hipMemcpyHostToDevice)) != hipSuccess)
             return e;
     }
+    // argument table and launch state
+    TiledArgs2D a = {};
+    for (int s = 0; s < plan.n_species; ++s) {
+        a.field[s][0] = fields[s][0];
+        a.field[s][1] = fields[s][1];
+        a.coef[s] = plan.coef[s];
+    }
+    a.nx = plan.nx;
+    a.ny = plan.ny;
+    a.tiles_x = plan.tiles_x;
+    a.n_tiles = plan.n_tiles;
+    a.tx_core = plan.core_x;
+    a.ty_core = plan.core_y;
+    a.halo = plan.halo;
+    a.height = plan.height;
+    a.src_start = st.src_start;
+    a.src_entry = st.src_entry;
+    a.src_amount = st.src_amount;
+    a.tgt_start = st.tgt_start;
+    a.tgt_pts = st.tgt_pts;
+    a.bucket[0] = st.bucket[0];
+    a.bucket[1] = st.bucket[1];
+    a.count[0] = st.count[0];
+    a.count[1] = st.count[1];
+    a.capacity = st.capacity;
+    a.cones = cones;
+    a.rules = rules;
+    if ((e = hipMalloc(&st.table, sizeof(TiledArgs2D))) != hipSuccess) return e;
+    if ((e = hipMemcpy(st.table, &a, sizeof a, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMalloc(&st.launch, sizeof(LaunchState))) != hipSuccess) return e;
+    if ((e = tiled_set_launch_state(st, 0, 0, stream)) != hipSuccess) return e;
     return hipFuncSetAttribute(kernel_for(plan.n_species, plan.cpl),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
+}
+
+hipError_t tiled_set_launch_state(TiledState& st, uint32_t step, int parity, hipStream_t stream) {
+    const LaunchState ls = {step, parity, 0, 0};
+    st.cur = parity;
+    hipError_t e = hipMemcpyAsync(st.launch, &ls, sizeof ls, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(stream);
 }
 
 void tiled_release(TiledState& st) {
@@ -659,6 +775,10 @@ void tiled_release(TiledState& st) {
     (void)hipFree(st.src_amount);
     (void)hipFree(st.tgt_start);
     (void)hipFree(st.tgt_pts);
+    (void)hipFree(st.table);
+    (void)hipFree(st.launch);
+    st.table = nullptr;
+    st.launch = nullptr;
     st.tgt_start = nullptr;
     st.tgt_pts = nullptr;
     st.src_start = nullptr;
@@ -672,11 +792,10 @@ hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
     for (int b = 0; b < 2; ++b)
         if ((e = hipMemsetAsync(st.count[b], 0, plan.n_tiles * sizeof(int32_t), stream)) != hipSuccess)
             return e;
-    st.cur = 0;
     if (cones.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bucket2d, dim3(ceil_div(cones.n, 256)), dim3(256), 0, stream, cones,
                        plan.nx, plan.ny, plan.core_x, plan.core_y, plan.tiles_x,
-                       plan.inv_dx, st.bucket[0], st.count[0], st.capacity);
+                       plan.inv_dx, st.bucket[st.cur], st.count[st.cur], st.capacity);
     return hipGetLastError();
 }
 
@@ -692,43 +811,40 @@ hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cone
     return hipSuccess;
 }
 
-hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, const ConeRules& rules,
-                        float* const in[], float* const out[], ConeArrays cones, int steps,
-                        uint32_t first_step, hipStream_t stream) {
-    TiledArgs2D a = {};
-    for (int s = 0; s < plan.n_species; ++s) {
-        a.in[s] = in[s];
-        a.out[s] = out[s];
-        a.coef[s] = plan.coef[s];
-    }
-    a.nx = plan.nx;
-    a.ny = plan.ny;
-    a.tiles_x = plan.tiles_x;
-    a.n_tiles = plan.n_tiles;
-    a.tx_core = plan.core_x;
-    a.ty_core = plan.core_y;
-    a.halo = plan.halo;
-    a.height = plan.height;
-    a.steps = steps;
-    a.first_step = first_step;
-    a.src_start = st.src_start;
-    a.src_entry = st.src_entry;
-    a.src_amount = st.src_amount;
-    a.tgt_start = st.tgt_start;
-    a.tgt_pts = st.tgt_pts;
-    a.bucket_in = st.bucket[st.cur];
-    a.count_in = st.count[st.cur];
-    a.bucket_out = st.bucket[st.cur ^ 1];
-    a.count_out = st.count[st.cur ^ 1];
-    a.capacity = st.capacity;
-    a.cones = cones;
-    a.rules = rules;
-    void* args[] = {&a};
+hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream) {
+    const TiledArgs2D* table = st.table;
+    const int2* items = nullptr;
+    int n_items = plan.n_tiles;
+    LaunchState* ls = st.launch;
+    int persistent = 0;
+    void* args[] = {&table, &items, &n_items, &steps, &ls, &persistent};
     const hipError_t e = hipLaunchKernel(kernel_for(plan.n_species, plan.cpl),
                                          dim3(plan.n_tiles), dim3(kThreads), args,
                                          plan.lds_bytes, stream);
     if (e == hipSuccess) st.cur ^= 1;
     return e;
+}
+
+size_t tiled_table_entry_bytes() { return sizeof(TiledArgs2D); }
+
+int tiled_persistent_grid(size_t lds_bytes) {
+    const size_t per_cu_lds = 160 * 1024;
+    const int resident = std::max(1, std::min(2, (int)(per_cu_lds / (lds_bytes + kStaticLds))));
+    return 256 * resident;
+}
+
+hipError_t tiled_launch_batch(const TiledArgs2D* table, const int2* items, int n_items,
+                              int n_species, int cpl, size_t lds_bytes, int steps,
+                              LaunchState* launch, hipStream_t stream) {
+    int persistent = 1;
+    void* args[] = {&table, &items, &n_items, &steps, &launch, &persistent};
+    return hipLaunchKernel(kernel_for(n_species, cpl), dim3(tiled_persistent_grid(lds_bytes)),
+                           dim3(kThreads), args, lds_bytes, stream);
+}
+
+hipError_t tiled_prepare_batch(int n_species, int cpl, size_t lds_bytes) {
+    return hipFuncSetAttribute(kernel_for(n_species, cpl),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
 }  // namespace cuesim

@@ -217,6 +217,10 @@ sim_status validate(const sim_params* p) {
                     "contact_radius, step_len >= 0; max_turn in [0, pi]; noise_sigma >= 0");
     if (p->block_steps < 0 || p->block_steps > 32)
         return fail(nullptr, SIM_EINVAL, "block_steps must be in [0, 32]");
+    if (p->tile_cols_per_lane != 0 && p->tile_cols_per_lane != 2 && p->tile_cols_per_lane != 4)
+        return fail(nullptr, SIM_EINVAL, "tile_cols_per_lane must be 0, 2 or 4");
+    if (p->tile_height < 0 || p->tile_height > 4096)
+        return fail(nullptr, SIM_EINVAL, "tile_height must be in [0, 4096]");
     return SIM_OK;
 }
 
@@ -390,14 +394,7 @@ sim_status tiled_steps(sim_handle* h, int64_t n) {
         hipEvent_t t0;
         sim_status st = record_start(h, &t0);
         if (st != SIM_OK) return st;
-        float* in[SIM_MAX_SPECIES] = {};
-        float* out[SIM_MAX_SPECIES] = {};
-        for (int s = 0; s < h->n_species; ++s) {
-            in[s] = h->field[s][h->cur[s]];
-            out[s] = h->field[s][h->cur[s] ^ 1];
-        }
-        HIP_TRY(h, tiled_launch(h->plan, h->tiled, h->rules, in, out, h->cones, b,
-                                (uint32_t)h->step, h->stream));
+        HIP_TRY(h, tiled_launch(h->plan, h->tiled, b, h->stream));
         st = record_stop(h, t0);
         if (st != SIM_OK) return st;
         for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
@@ -407,11 +404,8 @@ sim_status tiled_steps(sim_handle* h, int64_t n) {
     return SIM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out) {
+// sim_create with an optional forced tile row width (batches need one kernel variant).
+sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim_handle** out) {
     if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
     *out = nullptr;
     sim_status st = validate(p);
@@ -512,13 +506,15 @@ sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out) {
     h->block_steps = p->block_steps == 0 ? kDefaultBlockSteps : p->block_steps;
     if (h->block_steps > 1) {
         h->plan = tiled_plan(h->dim, h->nx, h->ny, h->nz, h->n_species, p->step_len / p->dx,
-                             h->block_steps, h->n_cones);
+                             h->block_steps, h->n_cones,
+                             force_cpl ? force_cpl : p->tile_cols_per_lane, p->tile_height);
         h->plan.inv_dx = h->rules.inv_dx;
         for (int s = 0; s < h->n_species; ++s) h->plan.coef[s] = h->coef[s];
         if (h->plan.block_steps <= 1) {
             h->block_steps = 1;   // no tile shape fits: fall back to one step per launch
         } else {
-            e = tiled_allocate(h->plan, h->tiled, h->n_cones, h->rules, p, h->stream);
+            e = tiled_allocate(h->plan, h->tiled, h->n_cones, h->rules, p, h->field, h->cones,
+                               h->stream);
             if (e != hipSuccess) return bail(device_fail(h, e, "tiled state allocation"));
         }
     }
@@ -526,6 +522,94 @@ sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out) {
     if (e != hipSuccess) return bail(device_fail(h, e, "create synchronisation"));
     *out = h;
     return SIM_OK;
+}
+
+}  // namespace
+
+struct sim_batch {
+    std::vector<sim_handle*> sims;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* table = nullptr;            // concatenated device argument tables
+    int2* items = nullptr;            // (simulation, tile) work items
+    int n_items = 0;
+    LaunchState* launch = nullptr;
+    int n_species = 1, cpl = 2, block_steps = 1;
+    size_t lds_bytes = 0;
+    int64_t step = 0;
+    int graph_launches = 0;           // launches captured in `graph` (0: no graph)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+sim_status batch_fail(sim_batch* b, sim_status st, const char* msg) {
+    if (b)
+        b->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+#define BATCH_TRY(b, expr)                                                        \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            char m_[256];                                                         \
+            snprintf(m_, sizeof m_, "%s: %s (%d)", #expr, hipGetErrorString(e_), (int)e_); \
+            return batch_fail(b, e_ == hipErrorOutOfMemory ? SIM_ENOMEM : SIM_EDEVICE, m_); \
+        }                                                                         \
+    } while (0)
+
+void batch_release(sim_batch* b) {
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+    for (sim_handle* h : b->sims) {
+        if (!h) continue;
+        release(h);
+        delete h;
+    }
+    b->sims.clear();
+    if (b->table) (void)hipFree(b->table);
+    if (b->items) (void)hipFree(b->items);
+    if (b->launch) (void)hipFree(b->launch);
+    b->table = nullptr;
+    b->items = nullptr;
+    b->launch = nullptr;
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    b->stream = nullptr;
+}
+
+// One launch of `steps` steps for every simulation of the batch.
+sim_status batch_launch(sim_batch* b, int steps) {
+    BATCH_TRY(b, tiled_launch_batch((const TiledArgs2D*)b->table, b->items, b->n_items,
+                                    b->n_species, b->cpl, b->lds_bytes, steps, b->launch,
+                                    b->stream));
+    return SIM_OK;
+}
+
+// Mirror a completed launch of `steps` steps in every simulation's host-side state.
+void batch_advance(sim_batch* b, int steps, int launches) {
+    for (sim_handle* h : b->sims) {
+        for (int l = 0; l < launches; ++l) {
+            for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
+            h->tiled.cur ^= 1;
+        }
+        h->step += (int64_t)steps * launches;
+    }
+    b->step += (int64_t)steps * launches;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out) {
+    return create_impl(p, hip_stream, 0, out);
 }
 
 sim_status sim_step(sim_handle* h, int64_t n_steps) {
@@ -688,6 +772,8 @@ sim_status sim_write_state(sim_handle* h, sim_item what, int32_t index, const vo
             if (v < 0 || v > 2147483647LL) return fail(h, SIM_EINVAL, "step out of range");
             HIP_TRY(h, hipStreamSynchronize(h->stream));
             h->step = v;
+            if (h->block_steps > 1)
+                HIP_TRY(h, tiled_set_launch_state(h->tiled, (uint32_t)v, h->cur[0], h->stream));
             return SIM_OK;
         }
         default:
@@ -739,6 +825,174 @@ sim_status sim_destroy(sim_handle* h) {
 
 const char* sim_last_error(const sim_handle* h) {
     return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hip_stream,
+                            int32_t graph_launches, sim_batch** out) {
+    if (!out) return batch_fail(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || n < 1) return batch_fail(nullptr, SIM_EINVAL, "need at least one simulation");
+    if (graph_launches < 0 || graph_launches > 1024)
+        return batch_fail(nullptr, SIM_EINVAL, "graph_launches must be in [0, 1024]");
+    for (int i = 0; i < n; ++i) {
+        if (!params[i]) return batch_fail(nullptr, SIM_EINVAL, "params[i] is NULL");
+        if (params[i]->dim != 2) return batch_fail(nullptr, SIM_EINVAL, "batches are 2D only");
+        if (params[i]->n_species != params[0]->n_species)
+            return batch_fail(nullptr, SIM_EINVAL, "all simulations need the same n_species");
+        if (params[i]->block_steps != params[0]->block_steps)
+            return batch_fail(nullptr, SIM_EINVAL, "all simulations need the same block_steps");
+    }
+    sim_batch* b = new (std::nothrow) sim_batch();
+    if (!b) return batch_fail(nullptr, SIM_ENOMEM, "host allocation failed");
+    auto bail = [&](sim_status st) {
+        const std::string msg = b->err.empty() ? g_create_error : b->err;
+        batch_release(b);
+        delete b;
+        g_create_error = msg;
+        return st;
+    };
+    hipError_t e;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess)
+            return bail(batch_fail(b, SIM_EDEVICE, "hipStreamCreate failed"));
+        b->own_stream = true;
+    }
+    b->n_species = params[0]->n_species;
+    b->cpl = 2;
+    for (int i = 0; i < n; ++i) {
+        sim_params q = *params[i];
+        if (q.block_steps == 0) q.block_steps = kDefaultBlockSteps;
+        sim_handle* h = nullptr;
+        sim_status st = create_impl(&q, b->stream, b->cpl, &h);
+        if (st != SIM_OK) return bail(st);
+        b->sims.push_back(h);
+        if (h->block_steps <= 1 || h->plan.block_steps != b->sims[0]->plan.block_steps) {
+            char m[160];
+            snprintf(m, sizeof m, "simulation %d: no tiling with %d steps per launch fits", i,
+                     q.block_steps);
+            return bail(batch_fail(b, SIM_EINVAL, m));
+        }
+        b->lds_bytes = std::max(b->lds_bytes, h->plan.lds_bytes);
+        b->n_items += h->plan.n_tiles;
+    }
+    b->block_steps = b->sims[0]->plan.block_steps;
+    // concatenated argument tables, work items, shared launch state
+    const size_t entry = tiled_table_entry_bytes();
+    std::vector<int2> items;
+    items.reserve(b->n_items);
+    for (int i = 0; i < n; ++i)
+        for (int t = 0; t < b->sims[i]->plan.n_tiles; ++t) items.push_back(make_int2(i, t));
+    // largest simulations first, so the persistent grid finishes with small work items
+    std::stable_sort(items.begin(), items.end(), [&](const int2& x, const int2& y) {
+        return b->sims[x.x]->plan.height * b->sims[x.x]->n_cones >
+               b->sims[y.x]->plan.height * b->sims[y.x]->n_cones;
+    });
+    if ((e = hipMalloc(&b->table, entry * n)) != hipSuccess ||
+        (e = hipMalloc(&b->items, sizeof(int2) * items.size())) != hipSuccess ||
+        (e = hipMalloc(&b->launch, sizeof(LaunchState))) != hipSuccess)
+        return bail(batch_fail(b, SIM_ENOMEM, "batch allocation failed"));
+    for (int i = 0; i < n; ++i)
+        if ((e = hipMemcpy((char*)b->table + entry * i, b->sims[i]->tiled.table, entry,
+                           hipMemcpyDeviceToDevice)) != hipSuccess)
+            return bail(batch_fail(b, SIM_EDEVICE, "table copy failed"));
+    if ((e = hipMemcpy(b->items, items.data(), sizeof(int2) * items.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(batch_fail(b, SIM_EDEVICE, "item upload failed"));
+    const LaunchState ls = {0, 0, 0, 0};
+    if ((e = hipMemcpy(b->launch, &ls, sizeof ls, hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(batch_fail(b, SIM_EDEVICE, "launch state upload failed"));
+    if ((e = tiled_prepare_batch(b->n_species, b->cpl, b->lds_bytes)) != hipSuccess)
+        return bail(batch_fail(b, SIM_EDEVICE, "kernel attribute failed"));
+    // initial bucketing of every simulation's cones
+    for (sim_handle* h : b->sims) {
+        if ((e = tiled_bucket(h->plan, h->tiled, h->cones, b->stream)) != hipSuccess)
+            return bail(batch_fail(b, SIM_EDEVICE, "bucketing failed"));
+        h->cones_bucketed = true;
+    }
+    // optional graph of `graph_launches` full-depth launches, replayed by sim_batch_step
+    if (graph_launches > 0) {
+        if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return bail(batch_fail(b, SIM_EDEVICE, "graph capture failed to start"));
+        for (int l = 0; l < graph_launches; ++l) {
+            e = tiled_launch_batch((const TiledArgs2D*)b->table, b->items, b->n_items,
+                                   b->n_species, b->cpl, b->lds_bytes, b->block_steps,
+                                   b->launch, b->stream);
+            if (e != hipSuccess) break;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return bail(batch_fail(b, SIM_EDEVICE, "graph capture failed"));
+        b->graph = g;
+        if ((e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess)
+            return bail(batch_fail(b, SIM_EDEVICE, "graph instantiation failed"));
+        b->graph_launches = graph_launches;
+    }
+    if ((e = hipStreamSynchronize(b->stream)) != hipSuccess)
+        return bail(batch_fail(b, SIM_EDEVICE, "create synchronisation failed"));
+    *out = b;
+    return SIM_OK;
+}
+
+sim_status sim_batch_step(sim_batch* b, int64_t n_steps) {
+    if (!b) return batch_fail(nullptr, SIM_EINVAL, "batch is NULL");
+    if (n_steps < 0) return batch_fail(b, SIM_EINVAL, "n_steps < 0");
+    if (b->step + n_steps > 2147483647LL)
+        return batch_fail(b, SIM_EINVAL, "step count would exceed 2^31-1");
+    for (sim_handle* h : b->sims) {
+        if (h->poisoned) return batch_fail(b, SIM_ESTATE, "a simulation hit a device error");
+        if (!h->cones_bucketed) {   // after a read of cones: put them back in the buckets
+            BATCH_TRY(b, tiled_bucket(h->plan, h->tiled, h->cones, b->stream));
+            h->cones_bucketed = true;
+        }
+    }
+    const int64_t per_graph = (int64_t)b->graph_launches * b->block_steps;
+    while (per_graph > 0 && n_steps >= per_graph) {
+        BATCH_TRY(b, hipGraphLaunch(b->graph_exec, b->stream));
+        batch_advance(b, b->block_steps, b->graph_launches);
+        n_steps -= per_graph;
+    }
+    while (n_steps > 0) {
+        const int steps = (int)std::min<int64_t>(n_steps, b->block_steps);
+        sim_status st = batch_launch(b, steps);
+        if (st != SIM_OK) return st;
+        batch_advance(b, steps, 1);
+        n_steps -= steps;
+    }
+    return SIM_OK;
+}
+
+sim_status sim_batch_read_state(sim_batch* b, int32_t sim, sim_item what, int32_t index,
+                                void* dst, size_t dst_bytes, size_t* bytes_written) {
+    if (!b) return batch_fail(nullptr, SIM_EINVAL, "batch is NULL");
+    if (sim < 0 || sim >= (int32_t)b->sims.size())
+        return batch_fail(b, SIM_EINVAL, "simulation index out of range");
+    sim_handle* h = b->sims[sim];
+    const sim_status st = sim_read_state(h, what, index, dst, dst_bytes, bytes_written);
+    if (st != SIM_OK) b->err = h->err;
+    return st;
+}
+
+sim_status sim_batch_synchronize(sim_batch* b) {
+    if (!b) return batch_fail(nullptr, SIM_EINVAL, "batch is NULL");
+    BATCH_TRY(b, hipStreamSynchronize(b->stream));
+    return SIM_OK;
+}
+
+sim_status sim_batch_destroy(sim_batch* b) {
+    if (!b) return SIM_OK;
+    hipError_t e = hipSuccess;
+    if (b->stream) e = hipStreamSynchronize(b->stream);
+    batch_release(b);
+    delete b;
+    if (e != hipSuccess) return batch_fail(nullptr, SIM_EDEVICE, "device error pending at destroy");
+    return SIM_OK;
+}
+
+const char* sim_batch_last_error(const sim_batch* b) {
+    return b ? b->err.c_str() : g_create_error.c_str();
 }
 
 }  // extern "C"

@@ -29,6 +29,18 @@ struct TiledPlan {
     size_t lds_bytes = 0;
 };
 
+// Launch-to-launch state of the tiled kernel, in device memory: completed steps, which half
+// of every ping-pong pair is the input, and the work-queue counters (reset by the last
+// workgroup of each launch).
+struct LaunchState {
+    uint32_t step;
+    int32_t parity;
+    int32_t next;
+    int32_t exited;
+};
+
+struct TiledArgs2D;
+
 // Device buffers owned by the tiled path.
 struct TiledState {
     float4* bucket[2] = {nullptr, nullptr};    // per tile: cone slots (x, y, theta, id)
@@ -40,13 +52,22 @@ struct TiledState {
     float* src_amount = nullptr;
     int32_t* tgt_start = nullptr;              // per tile: range into tgt_pts
     float4* tgt_pts = nullptr;                 // targets a tile's cones can reach
+    TiledArgs2D* table = nullptr;              // device copy of this simulation's arguments
+    LaunchState* launch = nullptr;             // device launch state
 };
 
 // Choose B and the tile shape; block_steps = 1 in the result means no tiling fits.
+// force_cpl != 0 restricts the row width to 64 * force_cpl columns, force_height != 0 the
+// loaded tile height; a forced shape that does not fit falls back to the planner's choice.
 TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
-                     int block_steps, int n_cones);
+                     int block_steps, int n_cones, int force_cpl = 0, int force_height = 0);
+// Allocate buckets and per-tile tables and upload the argument table; fields[s][b] are the
+// simulation's ping-pong field buffers, cones its caller-order arrays.
 hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
-                          const ConeRules& rules, const sim_params* p, hipStream_t stream);
+                          const ConeRules& rules, const sim_params* p, float* const fields[][2],
+                          ConeArrays cones, hipStream_t stream);
+// Set the device launch state (step counter; parity = input half of the ping-pong pairs).
+hipError_t tiled_set_launch_state(TiledState& st, uint32_t step, int parity, hipStream_t stream);
 void tiled_release(TiledState& st);
 // Move active cones from the caller-order arrays into the tile buckets.
 hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
@@ -54,9 +75,21 @@ hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
 // Move active cones from the tile buckets back into the caller-order arrays.
 hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
                           hipStream_t stream);
-// Advance `steps` (<= plan.block_steps) steps in one launch.
-hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, const ConeRules& rules,
-                        float* const in[], float* const out[], ConeArrays cones, int steps,
-                        uint32_t first_step, hipStream_t stream);
+// Advance `steps` (<= plan.block_steps) steps in one launch; flips st.cur like the device
+// parity.
+hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream);
+
+// Size in bytes of one argument-table entry (for batching several simulations).
+size_t tiled_table_entry_bytes();
+// One persistent launch over the work items (simulation, tile) of a batch whose argument
+// tables are concatenated in `table`; all simulations share n_species, cpl and `launch`.
+hipError_t tiled_launch_batch(const TiledArgs2D* table, const int2* items, int n_items,
+                              int n_species, int cpl, size_t lds_bytes, int steps,
+                              LaunchState* launch, hipStream_t stream);
+// Number of workgroups of the persistent batch launch for a given dynamic LDS size.
+int tiled_persistent_grid(size_t lds_bytes);
+// Allow the batch kernel variant lds_bytes of dynamic LDS (call before launching or
+// capturing it).
+hipError_t tiled_prepare_batch(int n_species, int cpl, size_t lds_bytes);
 
 }  // namespace cuesim

@@ -122,6 +122,17 @@ def test_degenerate_cases(block):
     sim.close()
 
 
+@pytest.mark.parametrize("block", BLOCKS)
+def test_crowded_tiles(block):
+    """Thousands of cones per tile: cones held in registers (two slots per thread) and the
+    overflow path that steps further cones from memory, crossing tile borders."""
+    sc = S.make_scenario("crowded", 2, (200, 180), 1.0, 0.2, ((1.0, 0.01, 1.0),), 5,
+                         (0.5, 2.0), 7000, 30, seed=8)
+    _say(f"crowded 200x180, 7000 cones, block_steps={block}")
+    sim, ref, _ = run_pair(sc, 120, block, 40)
+    sim.close()
+
+
 def test_mass_recursion_on_gpu():
     """M^{n+1} = (1 - k dt) M^n + sum q, with the GPU's FP64-accumulated mass."""
     sc = S.make_scenario("mass", 2, (200, 150), 1.0, 0.2, ((1.0, 0.01, 1.0),), 5, (0.5, 2.0),
