@@ -192,19 +192,41 @@ __device__ __forceinline__ void gradient_3d(const F& f, const ConeRules& r, floa
     corner(x, r.inv_dx, r.nx, i0, fx);
     corner(y, r.inv_dx, r.ny, j0, fy);
     corner(z, r.inv_dx, r.nz, l0, fz);
+    // The 32 distinct cells of the footprint: the 2x2x2 corner block and, beyond each of its
+    // faces, the 2x2 cells one further out (clamped at walls: ghost = own value).
+    const int im = max(i0 - 1, 0), ip = min(i0 + 2, r.nx - 1);
+    const int jm = max(j0 - 1, 0), jp = min(j0 + 2, r.ny - 1);
+    const int lm = max(l0 - 1, 0), lp = min(l0 + 2, r.nz - 1);
+    float blk[2][2][2], xm[2][2], xp[2][2], ym[2][2], yp[2][2], zm[2][2], zp[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            blk[0][b][c] = f(i0, j0 + b, l0 + c);
+            blk[1][b][c] = f(i0 + 1, j0 + b, l0 + c);
+            xm[b][c] = f(im, j0 + b, l0 + c);
+            xp[b][c] = f(ip, j0 + b, l0 + c);
+            ym[b][c] = f(i0 + b, jm, l0 + c);      // [x offset][z offset]
+            yp[b][c] = f(i0 + b, jp, l0 + c);
+            zm[b][c] = f(i0 + b, j0 + c, lm);      // [x offset][y offset]
+            zp[b][c] = f(i0 + b, j0 + c, lp);
+        }
     gx = gy = gz = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int i = i0 + (c & 1), j = j0 + ((c >> 1) & 1), l = l0 + ((c >> 2) & 1);
-        const float w = ((c & 1) ? fx : 1.0f - fx) * (((c >> 1) & 1) ? fy : 1.0f - fy) *
-                        (((c >> 2) & 1) ? fz : 1.0f - fz);
-        const float ex = f(min(i + 1, r.nx - 1), j, l) - f(max(i - 1, 0), j, l);
-        const float ey = f(i, min(j + 1, r.ny - 1), l) - f(i, max(j - 1, 0), l);
-        const float ez = f(i, j, min(l + 1, r.nz - 1)) - f(i, j, max(l - 1, 0));
-        gx += w * ex;
-        gy += w * ey;
-        gz += w * ez;
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float w = (a ? fx : 1.0f - fx) * (b ? fy : 1.0f - fy) * (c ? fz : 1.0f - fz);
+                // central differences at corner (i0+a, j0+b, l0+c)
+                const float ex = (a ? xp[b][c] : blk[1][b][c]) - (a ? blk[0][b][c] : xm[b][c]);
+                const float ey = (b ? yp[a][c] : blk[a][1][c]) - (b ? blk[a][0][c] : ym[a][c]);
+                const float ez = (c ? zp[a][b] : blk[a][b][1]) - (c ? blk[a][b][0] : zm[a][b]);
+                gx += w * ex;
+                gy += w * ey;
+                gz += w * ez;
+            }
     gx *= r.half_inv_dx;
     gy *= r.half_inv_dx;
     gz *= r.half_inv_dx;

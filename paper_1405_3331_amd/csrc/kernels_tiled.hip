@@ -40,7 +40,8 @@ constexpr size_t kLdsBudget = 154 * 1024;   // dynamic LDS; the rest is static (
                                             // re-bucketing counters)
 constexpr int kLoadBatch = 4;               // tile rows a wavefront has in flight at load
 constexpr int kConeSlots = 2;               // cones per thread held in registers
-constexpr size_t kStaticLds = kMaxTileTargets * 16 + 3 * 9 * 4;   // static LDS per tile
+constexpr int kPartCones = kConeSlots * kThreads;   // cones one work item steps
+constexpr size_t kStaticLds = kMaxTileTargets * 16 + 3 * 9 * 4 + 16;   // static LDS per tile
 constexpr int kGuardRows = 4;               // one above and three below each species plane
 
 }  // namespace
@@ -281,10 +282,13 @@ __device__ __forceinline__ int2 next_tile(const float4& st, int tx, int ty, int 
     return make_int2(ntx, nty);
 }
 
-// One tile of one simulation for `steps` sub-steps.  par selects the input half of every
-// ping-pong pair (fields and cone buckets); the other half is written.
+// One work item: part `part` of one tile of one simulation for `steps` sub-steps.  Every
+// part of a tile computes the tile's field; part p steps the tile's cones
+// [p * kPartCones, (p + 1) * kPartCones) and only part 0 writes the field back, so a tile
+// crowded with cones is spread over several workgroups.  par selects the input half of
+// every ping-pong pair (fields and cone buckets); the other half is written.
 template <int NS, int CPL>
-__device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int steps,
+__device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int part, int steps,
                                           uint32_t first_step, int par) {
     using V = typename Row<CPL>::T;
     constexpr int W = 64 * CPL;
@@ -340,8 +344,9 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int st
             }
         }
     }
-    const int n_cones = count_in[tile];
-    float4* live = bucket_in + (size_t)tile * a.capacity;
+    const int first_cone = part * kPartCones;
+    const int n_cones = max(0, min(count_in[tile] - first_cone, kPartCones));
+    float4* live = bucket_in + (size_t)tile * a.capacity + first_cone;
     const int t_lo = a.tgt_start[tile], n_tt = a.tgt_start[tile + 1] - t_lo;
     const TileContact contact{tile_targets, n_tt, n_tt <= kMaxTileTargets, &a.rules.targets};
     if (contact.staged)
@@ -422,9 +427,9 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int st
         }
     }
 
-    // 5. write the core back
+    // 5. write the core back (one part per tile does)
     const int cx0 = tx * a.tx_core, cy0 = ty * a.ty_core;
-    for (int ly = wave; ly < a.ty_core; ly += kWaves) {
+    for (int ly = wave; part == 0 && ly < a.ty_core; ly += kWaves) {
         const int gy = cy0 + ly;
         if (gy >= a.ny) break;
 #pragma unroll
@@ -468,7 +473,44 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int st
         const int slot = dest_base[d] + atomicAdd(&dest_fill[d], 1);
         bucket_out[(size_t)(nt.y * a.tiles_x + nt.x) * a.capacity + slot] = st;
     }
-    if (threadIdx.x == 0) count_in[tile] = 0;
+}
+
+// Expand the base items (simulation, tile) into work items (simulation, tile, part), one
+// part per kPartCones cones (at least one per tile), from the tile counts of input half
+// par_in; optionally zero the counts of half par_zero for reuse as the next output.  Run by
+// one whole workgroup.
+__device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* __restrict__ base,
+                            int n_base, int par_in, int par_zero, bool zero, int4* items,
+                            int item_cap, LaunchState* ls) {
+    extern __shared__ __align__(16) float lds[];
+    int* scan = reinterpret_cast<int*>(lds);   // kThreads ints of the (idle) dynamic LDS
+    const int per = (n_base + kThreads - 1) / kThreads;
+    const int lo = min((int)threadIdx.x * per, n_base), hi = min(lo + per, n_base);
+    int mine = 0;
+    for (int k = lo; k < hi; ++k) {
+        const int c = __hip_atomic_load(&table[base[k].x].count[par_in][base[k].y],
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        mine += max(1, (c + kPartCones - 1) / kPartCones);
+    }
+    scan[threadIdx.x] = mine;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {   // inclusive scan
+        const int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int at = scan[threadIdx.x] - mine;
+    for (int k = lo; k < hi; ++k) {
+        const TiledArgs2D& a = table[base[k].x];
+        const int c = __hip_atomic_load(&a.count[par_in][base[k].y], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        const int parts = max(1, (c + kPartCones - 1) / kPartCones);
+        for (int q = 0; q < parts; ++q, ++at)
+            if (at < item_cap) items[at] = make_int4(base[k].x, base[k].y, q, 0);
+        if (zero) a.count[par_zero][base[k].y] = 0;
+    }
+    if (threadIdx.x == kThreads - 1) ls->n_items = min(scan[kThreads - 1], item_cap);
 }
 
 // The step kernel.  Work items are (simulation, tile) pairs; without an item list the
@@ -478,15 +520,19 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int st
 // need no host-side bookkeeping and can be captured in a graph and replayed.
 template <int NS, int CPL>
 __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restrict__ table,
-                                                      const int2* __restrict__ items,
-                                                      int n_items, int steps, LaunchState* ls,
-                                                      int persistent) {
+                                                      int4* items, const int2* __restrict__ base,
+                                                      int n_base, int item_cap, int steps,
+                                                      LaunchState* ls, int persistent) {
     __shared__ int item_idx;
+    __shared__ int last_out;
     const uint32_t first_step = ls->step;
     const int par = ls->parity;
+    const int n_items = ls->n_items;
     if (!persistent) {
-        const int2 it = items ? items[blockIdx.x] : make_int2(0, blockIdx.x);
-        tile_body<NS, CPL>(table[it.x], it.y, steps, first_step, par);
+        if ((int)blockIdx.x < n_items) {
+            const int4 it = items[blockIdx.x];
+            tile_body<NS, CPL>(table[it.x], it.y, it.z, steps, first_step, par);
+        }
     } else {
         for (;;) {
             __syncthreads();   // the previous item is done with LDS and item_idx
@@ -494,19 +540,37 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
             __syncthreads();
             const int i = item_idx;
             if (i >= n_items) break;
-            const int2 it = items[i];
-            tile_body<NS, CPL>(table[it.x], it.y, steps, first_step, par);
+            const int4 it = items[i];
+            tile_body<NS, CPL>(table[it.x], it.y, it.z, steps, first_step, par);
         }
     }
+    // The last workgroup to finish lists the next launch's work items from the final tile
+    // counts, zeroes this launch's input counts and advances the launch state.
+    __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        if (atomicAdd(&ls->exited, 1) == (int)gridDim.x - 1) {
+        last_out = atomicAdd(&ls->exited, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last_out) {
+        __threadfence();
+        build_items(table, base, n_base, par ^ 1, par, true, items, item_cap, ls);
+        if (threadIdx.x == 0) {
             ls->exited = 0;
             ls->next = 0;
             ls->step = first_step + (uint32_t)steps;
             ls->parity = par ^ 1;
         }
     }
+}
+
+// Work items for the current cone counts (after cones were put into the buckets).
+__global__ __launch_bounds__(kThreads) void k_build_items(const TiledArgs2D* __restrict__ table,
+                                                          int4* items,
+                                                          const int2* __restrict__ base,
+                                                          int n_base, int item_cap,
+                                                          LaunchState* ls) {
+    build_items(table, base, n_base, ls->parity, 0, false, items, item_cap, ls);
 }
 
 // Initial bucketing from the caller-order arrays (active cones only).
@@ -749,18 +813,40 @@ hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
     a.rules = rules;
     if ((e = hipMalloc(&st.table, sizeof(TiledArgs2D))) != hipSuccess) return e;
     if ((e = hipMemcpy(st.table, &a, sizeof a, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    // work items: one per tile plus one per kPartCones further cones in a crowded tile
+    st.item_cap = tiled_item_capacity(plan.n_tiles, n_cones);
+    std::vector<int2> base(plan.n_tiles);
+    for (int t = 0; t < plan.n_tiles; ++t) base[t] = make_int2(0, t);
+    if ((e = hipMalloc(&st.base, base.size() * sizeof(int2))) != hipSuccess) return e;
+    if ((e = hipMemcpy(st.base, base.data(), base.size() * sizeof(int2),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if ((e = hipMalloc(&st.items, (size_t)st.item_cap * sizeof(int4))) != hipSuccess) return e;
     if ((e = hipMalloc(&st.launch, sizeof(LaunchState))) != hipSuccess) return e;
-    if ((e = tiled_set_launch_state(st, 0, 0, stream)) != hipSuccess) return e;
+    const LaunchState ls0 = {0, 0, 0, 0, 0};
+    if ((e = hipMemcpy(st.launch, &ls0, sizeof ls0, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    st.cur = 0;
     return hipFuncSetAttribute(kernel_for(plan.n_species, plan.cpl),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
 }
 
 hipError_t tiled_set_launch_state(TiledState& st, uint32_t step, int parity, hipStream_t stream) {
-    const LaunchState ls = {step, parity, 0, 0};
+    const int32_t head[2] = {(int32_t)step, parity};   // step and parity; items untouched
     st.cur = parity;
-    hipError_t e = hipMemcpyAsync(st.launch, &ls, sizeof ls, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(st.launch, head, sizeof head, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(stream);
+}
+
+int tiled_item_capacity(int n_tiles, int n_cones) {
+    return n_tiles + (n_cones + kPartCones - 1) / kPartCones + 1;
+}
+
+hipError_t tiled_build_items(const TiledArgs2D* table, int4* items, const int2* base,
+                             int n_base, int item_cap, LaunchState* launch, hipStream_t stream) {
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(kThreads), kThreads * sizeof(int), stream,
+                       table, items, base, n_base, item_cap, launch);
+    return hipGetLastError();
 }
 
 void tiled_release(TiledState& st) {
@@ -777,8 +863,12 @@ void tiled_release(TiledState& st) {
     (void)hipFree(st.tgt_pts);
     (void)hipFree(st.table);
     (void)hipFree(st.launch);
+    (void)hipFree(st.items);
+    (void)hipFree(st.base);
     st.table = nullptr;
     st.launch = nullptr;
+    st.items = nullptr;
+    st.base = nullptr;
     st.tgt_start = nullptr;
     st.tgt_pts = nullptr;
     st.src_start = nullptr;
@@ -792,11 +882,14 @@ hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
     for (int b = 0; b < 2; ++b)
         if ((e = hipMemsetAsync(st.count[b], 0, plan.n_tiles * sizeof(int32_t), stream)) != hipSuccess)
             return e;
-    if (cones.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket2d, dim3(ceil_div(cones.n, 256)), dim3(256), 0, stream, cones,
-                       plan.nx, plan.ny, plan.core_x, plan.core_y, plan.tiles_x,
-                       plan.inv_dx, st.bucket[st.cur], st.count[st.cur], st.capacity);
-    return hipGetLastError();
+    if (cones.n > 0) {
+        hipLaunchKernelGGL(k_bucket2d, dim3(ceil_div(cones.n, 256)), dim3(256), 0, stream,
+                           cones, plan.nx, plan.ny, plan.core_x, plan.core_y, plan.tiles_x,
+                           plan.inv_dx, st.bucket[st.cur], st.count[st.cur], st.capacity);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return tiled_build_items(st.table, st.items, st.base, plan.n_tiles, st.item_cap, st.launch,
+                             stream);
 }
 
 hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
@@ -813,13 +906,15 @@ hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cone
 
 hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream) {
     const TiledArgs2D* table = st.table;
-    const int2* items = nullptr;
-    int n_items = plan.n_tiles;
+    int4* items = st.items;
+    const int2* base = st.base;
+    int n_base = plan.n_tiles;
+    int item_cap = st.item_cap;
     LaunchState* ls = st.launch;
     int persistent = 0;
-    void* args[] = {&table, &items, &n_items, &steps, &ls, &persistent};
+    void* args[] = {&table, &items, &base, &n_base, &item_cap, &steps, &ls, &persistent};
     const hipError_t e = hipLaunchKernel(kernel_for(plan.n_species, plan.cpl),
-                                         dim3(plan.n_tiles), dim3(kThreads), args,
+                                         dim3(item_cap), dim3(kThreads), args,
                                          plan.lds_bytes, stream);
     if (e == hipSuccess) st.cur ^= 1;
     return e;
@@ -833,11 +928,12 @@ int tiled_persistent_grid(size_t lds_bytes) {
     return 256 * resident;
 }
 
-hipError_t tiled_launch_batch(const TiledArgs2D* table, const int2* items, int n_items,
-                              int n_species, int cpl, size_t lds_bytes, int steps,
-                              LaunchState* launch, hipStream_t stream) {
+hipError_t tiled_launch_batch(const TiledArgs2D* table, int4* items, const int2* base,
+                              int n_base, int item_cap, int n_species, int cpl,
+                              size_t lds_bytes, int steps, LaunchState* launch,
+                              hipStream_t stream) {
     int persistent = 1;
-    void* args[] = {&table, &items, &n_items, &steps, &launch, &persistent};
+    void* args[] = {&table, &items, &base, &n_base, &item_cap, &steps, &launch, &persistent};
     return hipLaunchKernel(kernel_for(n_species, cpl), dim3(tiled_persistent_grid(lds_bytes)),
                            dim3(kThreads), args, lds_bytes, stream);
 }

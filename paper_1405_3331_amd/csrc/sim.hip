@@ -531,8 +531,10 @@ struct sim_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void* table = nullptr;            // concatenated device argument tables
-    int2* items = nullptr;            // (simulation, tile) work items
-    int n_items = 0;
+    int2* base = nullptr;             // every (simulation, tile), largest simulations first
+    int n_base = 0;
+    int4* items = nullptr;            // (simulation, tile, part) work items of the next launch
+    int item_cap = 0;
     LaunchState* launch = nullptr;
     int n_species = 1, cpl = 2, block_steps = 1;
     size_t lds_bytes = 0;
@@ -576,9 +578,11 @@ void batch_release(sim_batch* b) {
     b->sims.clear();
     if (b->table) (void)hipFree(b->table);
     if (b->items) (void)hipFree(b->items);
+    if (b->base) (void)hipFree(b->base);
     if (b->launch) (void)hipFree(b->launch);
     b->table = nullptr;
     b->items = nullptr;
+    b->base = nullptr;
     b->launch = nullptr;
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     b->stream = nullptr;
@@ -586,9 +590,9 @@ void batch_release(sim_batch* b) {
 
 // One launch of `steps` steps for every simulation of the batch.
 sim_status batch_launch(sim_batch* b, int steps) {
-    BATCH_TRY(b, tiled_launch_batch((const TiledArgs2D*)b->table, b->items, b->n_items,
-                                    b->n_species, b->cpl, b->lds_bytes, steps, b->launch,
-                                    b->stream));
+    BATCH_TRY(b, tiled_launch_batch((const TiledArgs2D*)b->table, b->items, b->base,
+                                    b->n_base, b->item_cap, b->n_species, b->cpl,
+                                    b->lds_bytes, steps, b->launch, b->stream));
     return SIM_OK;
 }
 
@@ -861,6 +865,7 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
     }
     b->n_species = params[0]->n_species;
     b->cpl = 2;
+    int64_t total_cones = 0;
     for (int i = 0; i < n; ++i) {
         sim_params q = *params[i];
         if (q.block_steps == 0) q.block_steps = kDefaultBlockSteps;
@@ -875,13 +880,17 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
             return bail(batch_fail(b, SIM_EINVAL, m));
         }
         b->lds_bytes = std::max(b->lds_bytes, h->plan.lds_bytes);
-        b->n_items += h->plan.n_tiles;
+        b->n_base += h->plan.n_tiles;
+        total_cones += h->n_cones;
     }
     b->block_steps = b->sims[0]->plan.block_steps;
+    if (total_cones > INT32_MAX / 2)
+        return bail(batch_fail(b, SIM_EINVAL, "too many cones in the batch"));
+    b->item_cap = tiled_item_capacity(b->n_base, (int)total_cones);
     // concatenated argument tables, work items, shared launch state
     const size_t entry = tiled_table_entry_bytes();
     std::vector<int2> items;
-    items.reserve(b->n_items);
+    items.reserve(b->n_base);
     for (int i = 0; i < n; ++i)
         for (int t = 0; t < b->sims[i]->plan.n_tiles; ++t) items.push_back(make_int2(i, t));
     // largest simulations first, so the persistent grid finishes with small work items
@@ -890,17 +899,18 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
                b->sims[y.x]->plan.height * b->sims[y.x]->n_cones;
     });
     if ((e = hipMalloc(&b->table, entry * n)) != hipSuccess ||
-        (e = hipMalloc(&b->items, sizeof(int2) * items.size())) != hipSuccess ||
+        (e = hipMalloc(&b->base, sizeof(int2) * items.size())) != hipSuccess ||
+        (e = hipMalloc(&b->items, sizeof(int4) * b->item_cap)) != hipSuccess ||
         (e = hipMalloc(&b->launch, sizeof(LaunchState))) != hipSuccess)
         return bail(batch_fail(b, SIM_ENOMEM, "batch allocation failed"));
     for (int i = 0; i < n; ++i)
         if ((e = hipMemcpy((char*)b->table + entry * i, b->sims[i]->tiled.table, entry,
                            hipMemcpyDeviceToDevice)) != hipSuccess)
             return bail(batch_fail(b, SIM_EDEVICE, "table copy failed"));
-    if ((e = hipMemcpy(b->items, items.data(), sizeof(int2) * items.size(),
+    if ((e = hipMemcpy(b->base, items.data(), sizeof(int2) * items.size(),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return bail(batch_fail(b, SIM_EDEVICE, "item upload failed"));
-    const LaunchState ls = {0, 0, 0, 0};
+    const LaunchState ls = {0, 0, 0, 0, 0};
     if ((e = hipMemcpy(b->launch, &ls, sizeof ls, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(batch_fail(b, SIM_EDEVICE, "launch state upload failed"));
     if ((e = tiled_prepare_batch(b->n_species, b->cpl, b->lds_bytes)) != hipSuccess)
@@ -911,14 +921,17 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
             return bail(batch_fail(b, SIM_EDEVICE, "bucketing failed"));
         h->cones_bucketed = true;
     }
+    if ((e = tiled_build_items((const TiledArgs2D*)b->table, b->items, b->base, b->n_base,
+                               b->item_cap, b->launch, b->stream)) != hipSuccess)
+        return bail(batch_fail(b, SIM_EDEVICE, "work item listing failed"));
     // optional graph of `graph_launches` full-depth launches, replayed by sim_batch_step
     if (graph_launches > 0) {
         if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return bail(batch_fail(b, SIM_EDEVICE, "graph capture failed to start"));
         for (int l = 0; l < graph_launches; ++l) {
-            e = tiled_launch_batch((const TiledArgs2D*)b->table, b->items, b->n_items,
-                                   b->n_species, b->cpl, b->lds_bytes, b->block_steps,
-                                   b->launch, b->stream);
+            e = tiled_launch_batch((const TiledArgs2D*)b->table, b->items, b->base,
+                                   b->n_base, b->item_cap, b->n_species, b->cpl,
+                                   b->lds_bytes, b->block_steps, b->launch, b->stream);
             if (e != hipSuccess) break;
         }
         hipGraph_t g = nullptr;
@@ -941,13 +954,18 @@ sim_status sim_batch_step(sim_batch* b, int64_t n_steps) {
     if (n_steps < 0) return batch_fail(b, SIM_EINVAL, "n_steps < 0");
     if (b->step + n_steps > 2147483647LL)
         return batch_fail(b, SIM_EINVAL, "step count would exceed 2^31-1");
+    bool rebucketed = false;
     for (sim_handle* h : b->sims) {
         if (h->poisoned) return batch_fail(b, SIM_ESTATE, "a simulation hit a device error");
         if (!h->cones_bucketed) {   // after a read of cones: put them back in the buckets
             BATCH_TRY(b, tiled_bucket(h->plan, h->tiled, h->cones, b->stream));
             h->cones_bucketed = true;
+            rebucketed = true;
         }
     }
+    if (rebucketed)
+        BATCH_TRY(b, tiled_build_items((const TiledArgs2D*)b->table, b->items, b->base,
+                                       b->n_base, b->item_cap, b->launch, b->stream));
     const int64_t per_graph = (int64_t)b->graph_launches * b->block_steps;
     while (per_graph > 0 && n_steps >= per_graph) {
         BATCH_TRY(b, hipGraphLaunch(b->graph_exec, b->stream));

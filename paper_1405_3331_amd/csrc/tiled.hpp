@@ -37,6 +37,7 @@ struct LaunchState {
     int32_t parity;
     int32_t next;
     int32_t exited;
+    int32_t n_items;   // work items of the next launch (listed by the last workgroup)
 };
 
 struct TiledArgs2D;
@@ -54,6 +55,9 @@ struct TiledState {
     float4* tgt_pts = nullptr;                 // targets a tile's cones can reach
     TiledArgs2D* table = nullptr;              // device copy of this simulation's arguments
     LaunchState* launch = nullptr;             // device launch state
+    int2* base = nullptr;                      // (simulation, tile) per tile
+    int4* items = nullptr;                     // (simulation, tile, part) of the next launch
+    int item_cap = 0;
 };
 
 // Choose B and the tile shape; block_steps = 1 in the result means no tiling fits.
@@ -81,11 +85,18 @@ hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStr
 
 // Size in bytes of one argument-table entry (for batching several simulations).
 size_t tiled_table_entry_bytes();
-// One persistent launch over the work items (simulation, tile) of a batch whose argument
-// tables are concatenated in `table`; all simulations share n_species, cpl and `launch`.
-hipError_t tiled_launch_batch(const TiledArgs2D* table, const int2* items, int n_items,
-                              int n_species, int cpl, size_t lds_bytes, int steps,
-                              LaunchState* launch, hipStream_t stream);
+// One persistent launch over the work items of a batch whose argument tables are
+// concatenated in `table`; all simulations share n_species, cpl and `launch`.  base lists
+// every (simulation, tile); items receives the expanded (simulation, tile, part) list.
+hipError_t tiled_launch_batch(const TiledArgs2D* table, int4* items, const int2* base,
+                              int n_base, int item_cap, int n_species, int cpl,
+                              size_t lds_bytes, int steps, LaunchState* launch,
+                              hipStream_t stream);
+// Upper bound on the work items of n_tiles tiles holding n_cones cones in total.
+int tiled_item_capacity(int n_tiles, int n_cones);
+// List the work items for the current cone counts (after cones were bucketed).
+hipError_t tiled_build_items(const TiledArgs2D* table, int4* items, const int2* base,
+                             int n_base, int item_cap, LaunchState* launch, hipStream_t stream);
 // Number of workgroups of the persistent batch launch for a given dynamic LDS size.
 int tiled_persistent_grid(size_t lds_bytes);
 // Allow the batch kernel variant lds_bytes of dynamic LDS (call before launching or

@@ -11,13 +11,14 @@ import pytest
 
 import oracle
 import parity
+from paper_1405_3331_amd import autotune
 from paper_1405_3331_amd import binding as B
 from paper_1405_3331_amd import scenarios as S
 
 pytestmark = pytest.mark.gpu
 
-# one kernel sequence per step; library default (tiled, 8 steps per launch); 3 steps
-BLOCKS = [1, 0, 3]
+# one kernel sequence per step; library default (tiled, 8 steps per launch); 3 and 12 steps
+BLOCKS = [1, 0, 3, 12]
 
 
 def _say(msg):
@@ -204,8 +205,9 @@ def test_headline_size_short_run_elementwise():
     """The 2048^2 headline workload at full size in the default launch configuration: 20
     steps compared element by element with the oracle."""
     sc = S.headline()
-    _say("headline 2048^2, 65536 cones, 20 steps")
-    sim, ref, worst = run_pair(sc, 20, 0, 10)
+    block = autotune.apply(sc)   # the depth and tile shape bench.py uses
+    _say(f"headline 2048^2, 65536 cones, 30 steps, block_steps {block}")
+    sim, ref, worst = run_pair(sc, 30, block, 15)
     _say(f"worst field {worst['field']:.2e} tip {worst['tip']:.2e}")
     sim.close()
 
