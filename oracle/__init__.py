@@ -71,6 +71,10 @@ def load(path: str = LIBRARY):
     lib.oracle_mass.argtypes = [C.POINTER(_Params), _dp]
     lib.oracle_mass.restype = C.c_double
     lib.oracle_num_threads.restype = C.c_int
+    if hasattr(lib, "oracle_adjoint"):
+        lib.oracle_adjoint.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.c_int64,
+                                       C.POINTER(C.c_int32), _dp, _dp, _dp, _dp, _dp]
+        lib.oracle_adjoint.restype = C.c_int
     if path == LIBRARY:
         _lib = lib
     return lib
@@ -193,6 +197,31 @@ class OracleSim:
         for s in range(len(out)):
             self.fields[s][...] = out[s]
         return self
+
+    def adjoint(self, n_steps: int, assign, weight):
+        """Run n_steps forward (advancing this simulation) and return the trajectory loss
+        sum_i weight[i] |p_i^N - target[assign[i]]|^2 with its gradient along the run's
+        branch: (loss, dL/dq [all sources, species 0 first], dL/dD [species], dL/dk)."""
+        assign = np.ascontiguousarray(assign, dtype=np.int32)
+        weight = np.ascontiguousarray(weight, dtype=np.float64)
+        assert assign.shape == (self.pos.shape[0],) and weight.shape == assign.shape
+        nq = int(sum(self.params.n_sources[s] for s in range(self.params.n_species)))
+        dq = np.zeros(max(nq, 1))
+        dD = np.zeros(2)
+        dk = np.zeros(2)
+        loss = np.zeros(1)
+        self.state.step = self.step_count
+        rc = self.lib.oracle_adjoint(C.byref(self.params), C.byref(self.state), int(n_steps),
+                                     _ptr(assign, C.c_int32), _ptr(weight, C.c_double),
+                                     _ptr(loss, C.c_double), _ptr(dq, C.c_double),
+                                     _ptr(dD, C.c_double), _ptr(dk, C.c_double))
+        if rc == -2:
+            raise ValueError("oracle_adjoint: 2D only")
+        if rc != 0:
+            raise MemoryError("oracle_adjoint: allocation failed")
+        self.step_count = int(self.state.step)
+        ns = self.params.n_species
+        return float(loss[0]), dq[:nq].copy(), dD[:ns].copy(), dk[:ns].copy()
 
     # -- reading ---------------------------------------------------------------------
     def mass(self, s: int = 0) -> float:

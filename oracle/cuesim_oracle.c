@@ -400,3 +400,237 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Reverse-mode gradient of a trajectory loss (2D).                                       */
+/*                                                                                        */
+/* L = sum_i w_i |p_i^N - t_{a(i)}|^2 over the cones' tips after N steps (a frozen cone   */
+/* keeps the tip it stopped at), differentiated with respect to every source amount q,    */
+/* and D and k of every species, along the forward run's branch: the exit and contact    */
+/* decisions and the turn cap's active side are held as the forward run took them.       */
+/*                                                                                        */
+/* The forward run is recorded in full (c^n for n = 0..N and the cone states at the      */
+/* start of every step), then the steps are reversed from N-1 down to 0:                  */
+/*   cones of step n:  adjoints of (p, theta) through advance, turn and gradient sample;   */
+/*                     the sample's adjoint is scattered into a^{n+1}, the field adjoint  */
+/*   field of step n:  c^{n+1} = c^n + r Lap c^n - k dt c^n + S q, so                     */
+/*                     dL/dq_m += a^{n+1}[cell_m] / dx^dim,                               */
+/*                     dL/dD   += sum a^{n+1} (dt / dx^2) Lap c^n,                        */
+/*                     dL/dk   += sum a^{n+1} (-dt c^n),                                  */
+/*                     a^n = a^{n+1} + r Lap a^{n+1} - k dt a^{n+1}                       */
+/*                     (the zero-flux Laplacian is symmetric, so its transpose is itself). */
+/* ------------------------------------------------------------------------------------ */
+
+/* Lap(c) at every cell of one 2D field (zero-flux walls): the sum over in-grid neighbours
+ * of (neighbour - cell). */
+static void laplacian_2d(const oracle_params* p, const double* c, double* out)
+{
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            int idx[3] = {i, j, 0};
+            double here = c[cell_index(p, idx)];
+            double sum = 0.0;
+            for (int a = 0; a < 2; ++a)
+                sum += (neighbour(p, c, idx, a, +1) - here) + (neighbour(p, c, idx, a, -1) - here);
+            out[cell_index(p, idx)] = sum;
+        }
+}
+
+/* Linear index of the neighbour of cell idx along axis a, direction d (the cell itself
+ * outside the grid). */
+static int64_t neighbour_index(const oracle_params* p, const int idx[3], int a, int d)
+{
+    int nb[3] = {idx[0], idx[1], idx[2]};
+    nb[a] += d;
+    if (nb[a] < 0 || nb[a] >= axis_size(p, a))
+        return cell_index(p, idx);
+    return cell_index(p, nb);
+}
+
+/* Reverse of one 2D cone step.  In: the state at the start of the step (pos, theta), the
+ * updated fields, the deviate z0 and the adjoints (ap[2], ath) of the state after the
+ * step.  Out: ap, ath become the adjoints of the state before the step, and the gradient
+ * sample's adjoint is added into afield[s]. */
+static void cone_reverse_2d(const oracle_params* p, const double* const fields[2],
+                            double* const afield[2], const double pos[2], double theta,
+                            double z0, double ap[2], double* ath)
+{
+    /* recompute the forward quantities of the step */
+    int base[2];
+    double frac[2];
+    int inside[2];
+    for (int a = 0; a < 2; ++a) {
+        int n = axis_size(p, a);
+        double u = pos[a] / p->dx - 0.5;
+        inside[a] = u > 0.0 && u < (double)(n - 1);
+        if (u < 0.0) u = 0.0;
+        if (u > (double)(n - 1)) u = (double)(n - 1);
+        int i0 = (int)floor(u);
+        if (i0 > n - 2) i0 = n - 2;
+        base[a] = i0;
+        frac[a] = u - (double)i0;
+    }
+    double g[2] = {0.0, 0.0};
+    for (int sp = 0; sp < p->n_species; ++sp) {
+        double gs[3];
+        oracle_sample_gradient(p, fields[sp], pos, gs);
+        g[0] += p->sign[sp] * gs[0];
+        g[1] += p->sign[sp] * gs[1];
+    }
+    const double lam = p->turn_gain;
+    double hx = cos(theta), hy = sin(theta);
+    double y = lam * (hx * g[1] - hy * g[0]);
+    double x = 1.0 + lam * (hx * g[0] + hy * g[1]);
+    double delta = atan2(y, x);
+    int capped = delta > p->max_turn || delta < -p->max_turn;
+    delta = fmin(fmax(delta, -p->max_turn), p->max_turn);
+    double theta_new = theta + delta + p->noise_sigma * z0;   /* the wrap is a constant shift */
+
+    /* advance: p' = p + s (cos theta', sin theta') */
+    double a_thn = *ath + p->step_len * (-sin(theta_new) * ap[0] + cos(theta_new) * ap[1]);
+    /* theta' = theta + delta(theta, g) + noise */
+    double a_theta = a_thn;
+    double a_g[2] = {0.0, 0.0};
+    if (!capped) {
+        double den = x * x + y * y;
+        double a_y = a_thn * x / den, a_x = -a_thn * y / den;
+        a_theta += a_y * (-lam * (hx * g[0] + hy * g[1])) + a_x * y;
+        a_g[0] = a_y * (-lam * hy) + a_x * (lam * hx);
+        a_g[1] = a_y * (lam * hx) + a_x * (lam * hy);
+    }
+    /* gradient sample: g_a = sum_s sign_s sum_corners w(u) G_{s,a}[corner] */
+    for (int sp = 0; sp < p->n_species; ++sp) {
+        const double* c = fields[sp];
+        double* ac = afield[sp];
+        for (int corner = 0; corner < 4; ++corner) {
+            int idx[3] = {0, 0, 0};
+            int up[2];
+            double w = 1.0;
+            for (int a = 0; a < 2; ++a) {
+                up[a] = (corner >> a) & 1;
+                idx[a] = base[a] + up[a];
+                w *= up[a] ? frac[a] : (1.0 - frac[a]);
+            }
+            /* the corner's central-difference gradient and its dependence on the tip */
+            double G[2];
+            for (int a = 0; a < 2; ++a)
+                G[a] = (neighbour(p, c, idx, a, +1) - neighbour(p, c, idx, a, -1)) / (2.0 * p->dx);
+            double sum = a_g[0] * G[0] + a_g[1] * G[1];
+            for (int b = 0; b < 2; ++b) {
+                if (!inside[b])
+                    continue;
+                double dw = up[b] ? 1.0 : -1.0;   /* d w / d frac_b */
+                for (int a = 0; a < 2; ++a)
+                    if (a != b)
+                        dw *= up[a] ? frac[a] : (1.0 - frac[a]);
+                ap[b] += p->sign[sp] * dw / p->dx * sum;
+            }
+            /* scatter into the field adjoint */
+            for (int a = 0; a < 2; ++a) {
+                double v = p->sign[sp] * w * a_g[a] / (2.0 * p->dx);
+                ac[neighbour_index(p, idx, a, +1)] += v;
+                ac[neighbour_index(p, idx, a, -1)] -= v;
+            }
+        }
+    }
+    *ath = a_theta;
+}
+
+int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
+                   const int32_t* assign, const double* weight, double* loss,
+                   double* dL_dq, double* dL_dD, double* dL_dk)
+{
+    if (p->dim != 2)
+        return -2;
+    const int64_t cells = n_cells(p);
+    const int ns = p->n_species;
+    const int M = s->n_cones;
+    const int64_t N = n_steps;
+    const int64_t n0 = s->step;
+    /* tape: fields c^n (n = 0..N) per species, cone (x, y, theta) at the start of each step */
+    double* tape_c = (double*)malloc((size_t)(N + 1) * ns * cells * sizeof(double));
+    double* tape_cone = (double*)malloc((size_t)(N > 0 ? N : 1) * M * 3 * sizeof(double) + 8);
+    double* afield = (double*)calloc((size_t)ns * cells, sizeof(double));
+    double* lap = (double*)malloc((size_t)cells * sizeof(double));
+    double* aprev = (double*)malloc((size_t)cells * sizeof(double));
+    double* acone = (double*)calloc((size_t)M * 3 + 1, sizeof(double));
+    if (!tape_c || !tape_cone || !afield || !lap || !aprev || !acone) {
+        free(tape_c); free(tape_cone); free(afield); free(lap); free(aprev); free(acone);
+        return -1;
+    }
+    for (int sp = 0; sp < ns; ++sp)
+        memcpy(tape_c + (size_t)sp * cells, s->field[sp], (size_t)cells * sizeof(double));
+    for (int64_t n = 0; n < N; ++n) {
+        for (int i = 0; i < M; ++i) {
+            tape_cone[((size_t)n * M + i) * 3 + 0] = s->pos[2 * i];
+            tape_cone[((size_t)n * M + i) * 3 + 1] = s->pos[2 * i + 1];
+            tape_cone[((size_t)n * M + i) * 3 + 2] = s->dir[i];
+        }
+        if (oracle_run(p, s, 1) != 0) {
+            free(tape_c); free(tape_cone); free(afield); free(lap); free(aprev); free(acone);
+            return -1;
+        }
+        for (int sp = 0; sp < ns; ++sp)
+            memcpy(tape_c + ((size_t)(n + 1) * ns + sp) * cells, s->field[sp],
+                   (size_t)cells * sizeof(double));
+    }
+    /* loss and its adjoint at the final tips */
+    double L = 0.0;
+    for (int i = 0; i < M; ++i) {
+        const double* t = p->target_pos + (int64_t)assign[i] * 2;
+        double dx0 = s->pos[2 * i] - t[0], dx1 = s->pos[2 * i + 1] - t[1];
+        L += weight[i] * (dx0 * dx0 + dx1 * dx1);
+        acone[3 * i + 0] = 2.0 * weight[i] * dx0;
+        acone[3 * i + 1] = 2.0 * weight[i] * dx1;
+        acone[3 * i + 2] = 0.0;
+    }
+    *loss = L;
+    int q_off[2] = {0, p->n_sources[0]};
+    for (int sp = 0; sp < ns; ++sp) {
+        for (int m = 0; m < p->n_sources[sp]; ++m)
+            dL_dq[q_off[sp] + m] = 0.0;
+        dL_dD[sp] = 0.0;
+        dL_dk[sp] = 0.0;
+    }
+    const double vol = p->dx * p->dx;
+    for (int64_t n = N - 1; n >= 0; --n) {
+        const double* fnext[2] = {tape_c + ((size_t)(n + 1) * ns) * cells,
+                                  tape_c + ((size_t)(n + 1) * ns + (ns > 1 ? 1 : 0)) * cells};
+        double* af[2] = {afield, afield + (size_t)(ns > 1 ? 1 : 0) * cells};
+        /* cones active at the start of step n0 + n */
+        for (int i = 0; i < M; ++i) {
+            int32_t e = s->event_step[i];
+            if (s->status[i] != ORACLE_ACTIVE && e <= n0 + n)
+                continue;
+            double z[4];
+            oracle_normals4(p->seed, (uint32_t)i, (uint32_t)(n0 + n), 0u, p->sim_index, z);
+            const double* st = tape_cone + ((size_t)n * M + i) * 3;
+            double pos[2] = {st[0], st[1]};
+            cone_reverse_2d(p, fnext, af, pos, st[2], z[0] * p->noise_sign, acone + 3 * i,
+                            acone + 3 * i + 2);
+        }
+        /* field of step n: parameters, then a^n = A a^{n+1} */
+        for (int sp = 0; sp < ns; ++sp) {
+            const double* c = tape_c + ((size_t)n * ns + sp) * cells;
+            double* a = afield + (size_t)sp * cells;
+            for (int m = 0; m < p->n_sources[sp]; ++m)
+                dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]] / vol;
+            laplacian_2d(p, c, lap);
+            double sD = 0.0, sk = 0.0;
+            for (int64_t x = 0; x < cells; ++x) {
+                sD += a[x] * lap[x];
+                sk += a[x] * c[x];
+            }
+            dL_dD[sp] += sD * p->dt / (p->dx * p->dx);
+            dL_dk[sp] += -p->dt * sk;
+            const double r = p->D[sp] * p->dt / (p->dx * p->dx);
+            const double kdt = p->k[sp] * p->dt;
+            laplacian_2d(p, a, lap);
+            for (int64_t x = 0; x < cells; ++x)
+                aprev[x] = a[x] + r * lap[x] - kdt * a[x];
+            memcpy(a, aprev, (size_t)cells * sizeof(double));
+        }
+    }
+    free(tape_c); free(tape_cone); free(afield); free(lap); free(aprev); free(acone);
+    return 0;
+}

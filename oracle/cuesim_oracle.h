@@ -74,6 +74,16 @@ void oracle_cone_step(const oracle_params* p, oracle_state* s);
 /* n_steps full steps: field update, then cones.  Returns 0, or -1 on allocation failure. */
 int oracle_run(const oracle_params* p, oracle_state* s, int64_t n_steps);
 
+/* Trajectory loss L = sum_i weight[i] * |p_i^N - target[assign[i]]|^2 after n_steps steps
+ * from state s (which is advanced by them), and its gradient along the forward run's
+ * branch (exit/contact decisions and the active side of the turn cap held fixed) with
+ * respect to every source amount (dL_dq: species 0's sources, then species 1's), and D
+ * and k of every species (dL_dD, dL_dk: [n_species]).  2D only.  Returns 0, -1 on
+ * allocation failure, -2 for 3D.  Records the whole forward run (n_steps + 1 fields). */
+int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
+                   const int32_t* assign, const double* weight, double* loss,
+                   double* dL_dq, double* dL_dD, double* dL_dk);
+
 /* Total cue amount sum(c) * dx^dim of one species. */
 double oracle_mass(const oracle_params* p, const double* field);
 

@@ -630,6 +630,75 @@ def pin_normal_statistics(lib_path=LIB, n_blocks=100_000):
     assert abs(np.corrcoef(z[:-1, 0], z[1:, 0])[0, 1]) < bound
 
 
+# ---------------------------------------------------------------------------------------
+# Reverse-mode gradient of the trajectory loss L = sum_i w_i |p_i^N - t_a(i)|^2 against
+# central finite differences of the forward run (the definition of the derivative).  The
+# derivative is taken along the forward run's branch, so a cone whose exit/contact record
+# differs between the +h and -h runs is given weight 0 before comparing.
+# ---------------------------------------------------------------------------------------
+def _adjoint_case(n_species):
+    species = ((1.0, 0.01, 1.0),) if n_species == 1 else ((1.0, 0.01, 1.0), (0.6, 0.02, -1.0))
+    # dx != 1 so that every dx factor of the gradient is exercised
+    return make_scenario("adjoint pin", 2, (40, 32), 0.5, 0.05, species, 3, (1.0, 4.0), 12, 6,
+                         0.5, 0.25, 10.0, math.pi / 30.0, 0.1, seed=2)
+
+
+def _perturbed(sc, kind, s, m, h):
+    import copy
+    out = copy.deepcopy(sc)
+    spc = out.species[s]
+    if kind == "q":
+        spc.source_q = spc.source_q.copy()
+        spc.source_q[m] += h
+    elif kind == "D":
+        spc.D += h
+    else:
+        spc.k += h
+    return out
+
+
+def pin_adjoint_fd(lib_path=LIB, n_species=1, steps=60):
+    sc = _adjoint_case(n_species)
+    M = sc.n_cones
+    assign = np.arange(M) % sc.target_pos.shape[0]
+
+    def forward(s2):
+        o = OracleSim(s2, lib_path=lib_path).step(steps)
+        d = o.pos - s2.target_pos[assign]
+        return (d * d).sum(1), np.stack([o.status, o.target, o.event_step], 1)
+
+    checks = []
+    for s, spc in enumerate(sc.species):
+        for m in range(len(spc.source_q)):
+            checks.append(("q", s, m, 1e-5 * spc.source_q[m]))
+        checks.append(("D", s, 0, 1e-6 * spc.D))
+        checks.append(("k", s, 0, 1e-5 * spc.k))
+    nq0 = len(sc.species[0].source_q)
+    for kind, s, m, h in checks:
+        (la, ea), (lb, eb) = forward(_perturbed(sc, kind, s, m, +h)), forward(_perturbed(sc, kind, s, m, -h))
+        w = np.where((ea == eb).all(1), 1.0, 0.0)
+        assert w.sum() >= M // 2, "too many event changes for a meaningful check"
+        fd = float((w * (la - lb)).sum()) / (2.0 * h)
+        _, dq, dD, dk = OracleSim(sc, lib_path=lib_path).adjoint(steps, assign, w)
+        got = {"q": dq[(nq0 if s else 0) + m], "D": dD[s], "k": dk[s]}[kind]
+        scale = max(abs(fd), 1e-3 * max(np.abs(dq).max(), np.abs(dD).max(), np.abs(dk).max()))
+        assert abs(got - fd) <= 2e-5 * scale, (kind, s, m, got, fd)
+
+
+def pin_adjoint_no_coupling(lib_path=LIB):
+    """With gain 0 the tips do not feel the field: every gradient is exactly zero, while
+    the loss itself is the direct-guidance one."""
+    sc = _adjoint_case(2)
+    sc.turn_gain = 0.0
+    M = sc.n_cones
+    assign = np.arange(M) % sc.target_pos.shape[0]
+    loss, dq, dD, dk = OracleSim(sc, lib_path=lib_path).adjoint(40, assign, np.ones(M))
+    assert not dq.any() and not dD.any() and not dk.any()
+    ref = OracleSim(sc, lib_path=lib_path).step(40)
+    d = ref.pos - sc.target_pos[assign]
+    assert abs(loss - float((d * d).sum())) <= 1e-12 * loss
+
+
 ALL_PINS = {
     "mass2d": lambda p: pin_mass_recursion(p, 2),
     "mass3d": lambda p: pin_mass_recursion(p, 3),
@@ -649,4 +718,6 @@ ALL_PINS = {
     "noise3d": pin_noise_3d,
     "philox": lambda p: pin_philox_vs_torch(p, cases=[(0, 0, 0), (12345, 7, 99), (2 ** 40 + 3, 2 ** 33 + 1, 2 ** 35 + 5)]),
     "normals": lambda p: pin_normal_statistics(p, 20_000),
+    "adjoint": lambda p: pin_adjoint_fd(p, 1, 40),
+    "adjoint2": lambda p: pin_adjoint_fd(p, 2, 40),
 }

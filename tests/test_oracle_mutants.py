@@ -52,6 +52,21 @@ MUTANTS = [
      "z[2 * pair] = radius * cos(ORACLE_PI * u_a);", ["normals"]),
     ("box_muller_radius", "double radius = sqrt(-2.0 * log(u_r));", "double radius = sqrt(-log(u_r));",
      ["normals"]),
+    ("adjoint_no_position_term", "ap[b] += p->sign[sp] * dw / p->dx * sum;", "", ["adjoint"]),
+    ("adjoint_scatter_sign", "ac[neighbour_index(p, idx, a, -1)] -= v;",
+     "ac[neighbour_index(p, idx, a, -1)] += v;", ["adjoint"]),
+    ("adjoint_decay_sign", "aprev[x] = a[x] + r * lap[x] - kdt * a[x];",
+     "aprev[x] = a[x] + r * lap[x] + kdt * a[x];", ["adjoint"]),
+    ("adjoint_turn_theta", "a_theta += a_y * (-lam * (hx * g[0] + hy * g[1])) + a_x * y;",
+     "a_theta += a_x * y;", ["adjoint"]),
+    ("adjoint_advance_sign", "(-sin(theta_new) * ap[0] + cos(theta_new) * ap[1])",
+     "(sin(theta_new) * ap[0] + cos(theta_new) * ap[1])", ["adjoint"]),
+    ("adjoint_species_sign", "double v = p->sign[sp] * w * a_g[a] / (2.0 * p->dx);",
+     "double v = w * a_g[a] / (2.0 * p->dx);", ["adjoint2"]),
+    ("adjoint_D_units", "dL_dD[sp] += sD * p->dt / (p->dx * p->dx);", "dL_dD[sp] += sD * p->dt;",
+     ["adjoint"]),
+    ("adjoint_source_units", "dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]] / vol;",
+     "dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]];", ["adjoint"]),
 ]
 
 

@@ -90,3 +90,12 @@ def test_philox_matches_torch_engine():
 
 def test_box_muller_statistics():
     pins.pin_normal_statistics()
+
+
+@pytest.mark.parametrize("n_species", [1, 2])
+def test_adjoint_matches_finite_differences(n_species):
+    pins.pin_adjoint_fd(n_species=n_species)
+
+
+def test_adjoint_zero_without_coupling():
+    pins.pin_adjoint_no_coupling()
