@@ -159,6 +159,52 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """Gradient of the trajectory loss sum_i |p_i^N - t_(i mod 256)|^2 of the 2D 1024^2
+    workload (32 sources, 8192 cones) with respect to the 32 source amounts, D and k: the
+    checkpointed forward run plus the reverse sweep, against the plain forward run of the
+    same steps on the same GPU."""
+    sc = S.adjoint()
+    steps = args.adjoint_steps
+    every = args.checkpoint_every
+    M = sc.n_cones
+    assign = np.arange(M) % sc.target_pos.shape[0]
+    weight = np.ones(M)
+    print(f"[bench] {sc.name}: {sc.n_cells} cells, {M} cones, {steps} steps, checkpoint "
+          f"every {every}", file=sys.stderr, flush=True)
+    block = autotune.apply(sc)
+    sim = B.Simulation(sc, block_steps=block)
+    sim.step(16)
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    forward_s = time.perf_counter() - t0
+    sim.close()
+    sim = B.Simulation(sc, block_steps=block)
+    t0 = time.perf_counter()
+    loss = sim.adjoint(steps, assign, weight, every)
+    t1 = time.perf_counter()
+    dq, dD, dk = sim.adjoint_backward()
+    t2 = time.perf_counter()
+    sim.close()
+    grad_s = t2 - t0
+    out = {
+        "metric": "adjoint (trajectory-loss gradient) cell-updates/s vs the plain forward run",
+        "value": sc.n_cells * steps / grad_s,
+        "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": steps, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "adjoint 2D 1024^2, 32 sources, 8192 cones, 256 targets, "
+                               "loss sum |p_i - t_(i mod 256)|^2", "checkpoint_every": every},
+        "forward_s": forward_s, "adjoint_forward_s": t1 - t0, "reverse_s": t2 - t1,
+        "gradient_over_forward": grad_s / forward_s,
+        "loss": loss, "dL_dD": float(dD[0]), "dL_dk": float(dk[0]),
+        "dL_dq_norm": float(np.linalg.norm(dq)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_volume(args):
     """3D 256^3 two-species workload through the per-step path (stencil kernel per species,
     sources, one thread per cone)."""
@@ -220,6 +266,10 @@ def main():
     ap.add_argument("--volume", action="store_true",
                     help="measure the 3D two-species workload instead of the headline one")
     ap.add_argument("--volume-steps", type=int, default=400)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="measure the trajectory-loss gradient of the 1024^2 workload")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--checkpoint-every", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
@@ -233,6 +283,9 @@ def main():
         return
     if args.volume:
         bench_volume(args)
+        return
+    if args.adjoint:
+        bench_adjoint(args)
         return
     sc = S.headline()
     block = args.block_steps

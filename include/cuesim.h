@@ -163,6 +163,56 @@ sim_status sim_destroy(sim_handle* h);
 const char* sim_last_error(const sim_handle* h);
 
 /* ----------------------------------------------------------------------------------------
+ * Gradient of a trajectory loss (2D simulations).
+ *
+ * L = sum_i weight[i] * |p_i^N - t_assign[i]|^2 over the cones' tips after a run (a stopped
+ * cone keeps the tip it stopped at), differentiated by reverse-mode (adjoint) sweeps of the
+ * step above with respect to every source amount q, and D and k of every species.  The
+ * derivative is taken along the run's branch: the exit and contact decisions and the active
+ * side of the turn cap are held as the run took them (the cone rules of Sec. 3.4-3.5 are
+ * not differentiable at those switches).  Memory: checkpoints of the fields and cone state
+ * every checkpoint_every steps, and during the reverse sweep one segment of
+ * checkpoint_every + 1 fields per species that is recomputed from its checkpoint; a
+ * checkpoint_every of at least n_steps records the whole run and recomputes it once.
+ * ---------------------------------------------------------------------------------------- */
+
+/* Advance n_steps >= 0 steps (as sim_step does), checkpointing every checkpoint_every >= 1
+ * steps, and return the loss in *loss (synchronises the stream).  assign[M] (target index
+ * per cone, 0 <= assign[i] < n_targets) and weight[M] are host arrays copied during the
+ * call.  Replaces any earlier record on the handle.  SIM_EINVAL for a 3D handle, bad
+ * counts or indices, non-finite weights; SIM_ENOMEM if the checkpoints do not fit. */
+sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_every,
+                           const int32_t* assign, const float* weight, double* loss);
+
+/* Reverse sweep of the last sim_adjoint_run (the handle must not have been stepped since;
+ * SIM_ESTATE otherwise).  Writes host arrays dL_dq[sum of n_sources] (species 0's sources
+ * in the caller's order, then species 1's), dL_dD[n_species] and dL_dk[n_species].  May be
+ * called again for the same record.  Synchronises the stream. */
+sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, double* dL_dk);
+
+/* ----------------------------------------------------------------------------------------
+ * Connectivity (Sec. 3.4, Figs. 4-5): a cone that stopped on a target is a connection from
+ * the neuron owning the cone to the neuron owning the target.
+ * ---------------------------------------------------------------------------------------- */
+
+/* Build the adjacency list of the connections made so far (on the device) and copy it to
+ * the caller's host arrays: row_start[n_neurons + 1] (V_a: neuron v's neighbours are
+ * edges[row_start[v] .. row_start[v+1]-1]) and edges (E_a, one entry per contacting cone,
+ * within a neuron in increasing cone index; a neighbour appears once per connection).
+ * cone_owner[M] and target_owner[T] (values in [0, n_neurons)) are host arrays.  *n_edges
+ * receives the edge count; SIM_ERANGE if edge_capacity is smaller (row_start is still
+ * written, edges is not).  The graph is kept on the handle for sim_bfs_levels. */
+sim_status sim_connectivity(sim_handle* h, int32_t n_neurons, const int32_t* cone_owner,
+                            const int32_t* target_owner, int32_t* row_start, int32_t* edges,
+                            int64_t edge_capacity, int64_t* n_edges);
+
+/* Level-synchronous breadth-first traversal of the last sim_connectivity graph from root
+ * (one device launch per level, one thread per vertex): level[n_neurons] (host) receives
+ * the number of edges on a shortest path from root, -1 where unreachable.  SIM_ESTATE if no
+ * graph was built. */
+sim_status sim_bfs_levels(sim_handle* h, int32_t root, int32_t* level);
+
+/* ----------------------------------------------------------------------------------------
  * Batches: many independent 2D simulations (same n_species and block_steps, any grid size,
  * cone and target counts) advanced together.  Each block of steps is ONE persistent
  * launch in which a fixed grid of workgroups pulls (simulation, tile) work items from an

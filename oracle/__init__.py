@@ -71,6 +71,13 @@ def load(path: str = LIBRARY):
     lib.oracle_mass.argtypes = [C.POINTER(_Params), _dp]
     lib.oracle_mass.restype = C.c_double
     lib.oracle_num_threads.restype = C.c_int
+    if hasattr(lib, "oracle_connectivity"):
+        _i32p = C.POINTER(C.c_int32)
+        lib.oracle_connectivity.argtypes = [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p,
+                                            _i32p, _i32p]
+        lib.oracle_connectivity.restype = C.c_int64
+        lib.oracle_bfs_levels.argtypes = [C.c_int32, _i32p, _i32p, C.c_int32, _i32p]
+        lib.oracle_bfs_levels.restype = C.c_int
     if hasattr(lib, "oracle_adjoint"):
         lib.oracle_adjoint.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.c_int64,
                                        C.POINTER(C.c_int32), _dp, _dp, _dp, _dp, _dp]
@@ -102,6 +109,35 @@ def normals4(seed, c0, c1, c2, c3, lib=None) -> np.ndarray:
 
 def num_threads(lib=None) -> int:
     return int((lib or load()).oracle_num_threads())
+
+
+def connectivity(n_neurons, status, target, cone_owner, target_owner, lib=None):
+    """(row_start [n_neurons + 1], edges) of the contacts: cone i with status CONTACT is an
+    edge cone_owner[i] -> target_owner[target[i]], lists in increasing cone index."""
+    lib = lib or load()
+    st = np.ascontiguousarray(status, dtype=np.int32)
+    tg = np.ascontiguousarray(target, dtype=np.int32)
+    ow = np.ascontiguousarray(cone_owner, dtype=np.int32)
+    to = np.ascontiguousarray(target_owner, dtype=np.int32)
+    row = np.zeros(int(n_neurons) + 1, dtype=np.int32)
+    edges = np.zeros(max(st.size, 1), dtype=np.int32)
+    p = lambda a: _ptr(a, C.c_int32)
+    n = lib.oracle_connectivity(int(n_neurons), st.size, p(st), p(tg), p(ow), p(to), p(row),
+                                p(edges))
+    if n < 0:
+        raise MemoryError("oracle_connectivity")
+    return row, edges[:n].copy()
+
+
+def bfs_levels(row_start, edges, root, lib=None):
+    lib = lib or load()
+    row = np.ascontiguousarray(row_start, dtype=np.int32)
+    e = np.ascontiguousarray(edges if len(edges) else np.zeros(1), dtype=np.int32)
+    level = np.zeros(row.size - 1, dtype=np.int32)
+    if lib.oracle_bfs_levels(row.size - 1, _ptr(row, C.c_int32), _ptr(e, C.c_int32), int(root),
+                             _ptr(level, C.c_int32)) != 0:
+        raise MemoryError("oracle_bfs_levels")
+    return level
 
 
 class OracleSim:

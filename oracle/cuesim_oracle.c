@@ -634,3 +634,56 @@ int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
     free(tape_c); free(tape_cone); free(afield); free(lap); free(aprev); free(acone);
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Connectivity (Sec. 3.4, Figs. 4-5).                                                    */
+/* ------------------------------------------------------------------------------------ */
+int64_t oracle_connectivity(int32_t n_neurons, int32_t n_cones, const int32_t* status,
+                            const int32_t* target, const int32_t* cone_owner,
+                            const int32_t* target_owner, int32_t* row_start, int32_t* edges)
+{
+    /* degree of every neuron, then the start of its list (V_a) */
+    for (int v = 0; v <= n_neurons; ++v)
+        row_start[v] = 0;
+    for (int i = 0; i < n_cones; ++i)
+        if (status[i] == ORACLE_CONTACT)
+            row_start[cone_owner[i] + 1] += 1;
+    for (int v = 0; v < n_neurons; ++v)
+        row_start[v + 1] += row_start[v];
+    /* the lists (E_a): cones visited in increasing index, appended to their owner's list */
+    int32_t* fill = (int32_t*)malloc(((size_t)n_neurons + 1) * sizeof(int32_t));
+    if (!fill)
+        return -1;
+    memcpy(fill, row_start, (size_t)n_neurons * sizeof(int32_t));
+    for (int i = 0; i < n_cones; ++i)
+        if (status[i] == ORACLE_CONTACT)
+            edges[fill[cone_owner[i]]++] = target_owner[target[i]];
+    free(fill);
+    return row_start[n_neurons];
+}
+
+int oracle_bfs_levels(int32_t n_neurons, const int32_t* row_start, const int32_t* edges,
+                      int32_t root, int32_t* level)
+{
+    /* textbook queue-based breadth-first search */
+    int32_t* queue = (int32_t*)malloc(((size_t)n_neurons + 1) * sizeof(int32_t));
+    if (!queue)
+        return -1;
+    for (int v = 0; v < n_neurons; ++v)
+        level[v] = -1;
+    int head = 0, tail = 0;
+    level[root] = 0;
+    queue[tail++] = root;
+    while (head < tail) {
+        int v = queue[head++];
+        for (int e = row_start[v]; e < row_start[v + 1]; ++e) {
+            int u = edges[e];
+            if (level[u] < 0) {
+                level[u] = level[v] + 1;
+                queue[tail++] = u;
+            }
+        }
+    }
+    free(queue);
+    return 0;
+}

@@ -84,6 +84,19 @@ int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
                    const int32_t* assign, const double* weight, double* loss,
                    double* dL_dq, double* dL_dD, double* dL_dk);
 
+/* Adjacency list of the connections (a cone with status CONTACT links its owner neuron to
+ * the owner of its target): row_start[n_neurons + 1] (V_a) and edges (E_a, capacity
+ * n_cones; each neuron's list in increasing cone index).  Returns the edge count, -1 on
+ * allocation failure. */
+int64_t oracle_connectivity(int32_t n_neurons, int32_t n_cones, const int32_t* status,
+                            const int32_t* target, const int32_t* cone_owner,
+                            const int32_t* target_owner, int32_t* row_start, int32_t* edges);
+
+/* Breadth-first levels from root (-1 where unreachable).  Returns 0, -1 on allocation
+ * failure. */
+int oracle_bfs_levels(int32_t n_neurons, const int32_t* row_start, const int32_t* edges,
+                      int32_t root, int32_t* level);
+
 /* Total cue amount sum(c) * dx^dim of one species. */
 double oracle_mass(const oracle_params* p, const double* field);
 

@@ -29,7 +29,8 @@ FIELD, CONE_POS, CONE_DIR, CONE_STATUS, CONE_TARGET, CONE_EVENT_STEP, EVENTS, MA
 EXPORTED = ["sim_create", "sim_step", "sim_read_state", "sim_write_state", "sim_device_ptr",
             "sim_set_timing", "sim_synchronize", "sim_destroy", "sim_last_error",
             "sim_batch_create", "sim_batch_step", "sim_batch_read_state",
-            "sim_batch_synchronize", "sim_batch_destroy", "sim_batch_last_error"]
+            "sim_batch_synchronize", "sim_batch_destroy", "sim_batch_last_error",
+            "sim_adjoint_run", "sim_adjoint_backward", "sim_connectivity", "sim_bfs_levels"]
 
 
 class SimError(RuntimeError):
@@ -94,6 +95,12 @@ def load(path: str = LIBRARY):
     lib.sim_batch_destroy.argtypes = [H]
     lib.sim_batch_last_error.argtypes = [H]
     lib.sim_batch_last_error.restype = C.c_char_p
+    _dp = C.POINTER(C.c_double)
+    lib.sim_adjoint_run.argtypes = [H, C.c_int64, C.c_int32, _ip, _fp, _dp]
+    lib.sim_adjoint_backward.argtypes = [H, _dp, _dp, _dp]
+    lib.sim_connectivity.argtypes = [H, C.c_int32, _ip, _ip, _ip, _ip, C.c_int64,
+                                     C.POINTER(C.c_int64)]
+    lib.sim_bfs_levels.argtypes = [H, C.c_int32, _ip]
     for name in EXPORTED:
         if not name.endswith("last_error"):
             getattr(lib, name).restype = C.c_int
@@ -235,6 +242,47 @@ def sim_last_error(h=None) -> str:
     return msg.decode() if msg else ""
 
 
+def sim_adjoint_run(h, n_steps: int, checkpoint_every: int, assign, weight) -> float:
+    assign = np.ascontiguousarray(assign, dtype=np.int32)
+    weight = np.ascontiguousarray(weight, dtype=np.float32)
+    loss = C.c_double(0.0)
+    _check(load().sim_adjoint_run(h, int(n_steps), int(checkpoint_every),
+                                  assign.ctypes.data_as(_ip), weight.ctypes.data_as(_fp),
+                                  C.byref(loss)), h)
+    return float(loss.value)
+
+
+def sim_adjoint_backward(h, n_q: int, n_species: int):
+    """(dL/dq [n_q], dL/dD [n_species], dL/dk [n_species]) of the last sim_adjoint_run."""
+    dq = np.zeros(max(n_q, 1))
+    dD = np.zeros(n_species)
+    dk = np.zeros(n_species)
+    dp = C.POINTER(C.c_double)
+    _check(load().sim_adjoint_backward(h, dq.ctypes.data_as(dp), dD.ctypes.data_as(dp),
+                                       dk.ctypes.data_as(dp)), h)
+    return dq[:n_q], dD, dk
+
+
+def sim_connectivity(h, n_neurons: int, cone_owner, target_owner):
+    """(row_start [n_neurons + 1], edges [n_edges]) of the connections made so far."""
+    owner = np.ascontiguousarray(cone_owner, dtype=np.int32)
+    towner = np.ascontiguousarray(target_owner, dtype=np.int32)
+    row_start = np.zeros(n_neurons + 1, dtype=np.int32)
+    n_edges = C.c_int64(0)
+    cap = max(int(owner.size), 1)
+    edges = np.zeros(cap, dtype=np.int32)
+    _check(load().sim_connectivity(h, int(n_neurons), owner.ctypes.data_as(_ip),
+                                   towner.ctypes.data_as(_ip), row_start.ctypes.data_as(_ip),
+                                   edges.ctypes.data_as(_ip), cap, C.byref(n_edges)), h)
+    return row_start, edges[: n_edges.value].copy()
+
+
+def sim_bfs_levels(h, root: int, n_neurons: int) -> np.ndarray:
+    level = np.zeros(n_neurons, dtype=np.int32)
+    _check(load().sim_bfs_levels(h, int(root), level.ctypes.data_as(_ip)), h)
+    return level
+
+
 class Simulation:
     """Owning wrapper around a handle with numpy views of the state."""
 
@@ -282,6 +330,21 @@ class Simulation:
     def write(self, what, array, index=0):
         sim_write_state(self.h, what, index, array)
         return self
+
+    def adjoint(self, n_steps: int, assign, weight, checkpoint_every: int = 100):
+        """Run n_steps with checkpoints and return the trajectory loss
+        sum_i weight[i] |p_i^N - target[assign[i]]|^2; gradients via adjoint_backward()."""
+        return sim_adjoint_run(self.h, n_steps, checkpoint_every, assign, weight)
+
+    def connectivity(self, n_neurons: int, cone_owner, target_owner):
+        return sim_connectivity(self.h, n_neurons, cone_owner, target_owner)
+
+    def bfs_levels(self, root: int, n_neurons: int):
+        return sim_bfs_levels(self.h, root, n_neurons)
+
+    def adjoint_backward(self):
+        n_q = sum(len(s.source_q) for s in self.sc.species)
+        return sim_adjoint_backward(self.h, n_q, len(self.sc.species))
 
     def synchronize(self):
         sim_synchronize(self.h)

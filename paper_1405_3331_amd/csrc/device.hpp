@@ -21,9 +21,11 @@ constexpr int kExited = 2;
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a = 0xD2511F53u * c.x, a_hi = __umulhi(0xD2511F53u, c.x);
-        const uint32_t b = 0xCD9E8D57u * c.z, b_hi = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(b_hi ^ c.y ^ k0, b, a_hi ^ c.w ^ k1, a);
+        // one 32 x 32 -> 64-bit product per S-box multiply gives both halves at once
+        const uint64_t pa = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(pb >> 32) ^ c.y ^ k0, (uint32_t)pb,
+                       (uint32_t)(pa >> 32) ^ c.w ^ k1, (uint32_t)pa);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -246,14 +248,14 @@ struct GridContact {
 
 // One step of an active 2D cone: turn toward h + gain*g (capped), noise, advance, exit,
 // contact.  `step` is the number of completed steps n before this one.  `contact` finds
-// the nearest target in range (GridContact, or a list staged in LDS).
+// the nearest target in range (GridContact, or a list staged in LDS).  (s, c) carry
+// sincosf(theta) in and sincosf of the new heading out, so a caller stepping a cone
+// repeatedly evaluates it once per step.
 template <class Contact>
 __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, float gy,
                                                   uint32_t id, uint32_t step, float& x,
-                                                  float& y, float& theta,
+                                                  float& y, float& theta, float& s, float& c,
                                                   const Contact& contact) {
-    float s, c;
-    sincosf(theta, &s, &c);
     float cross = r.gain * (c * gy - s * gx);
     const float along = 1.0f + r.gain * (c * gx + s * gy);
     if (cross == 0.0f) cross = 0.0f;   // -0 -> +0: an anti-parallel pull turns by +cap

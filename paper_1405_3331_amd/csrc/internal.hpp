@@ -43,6 +43,46 @@ hipError_t launch_cones_plain(int dim, const ConeRules& rules, const float* f0,
                               const float* f1, ConeArrays cones, uint32_t step,
                               hipStream_t stream);
 
+// Reverse pass of the 2D step (kernels_adjoint.hip).  Field adjoint grids have
+// adjoint_field_blocks(nx, ny) workgroups, each owning one slot of acc_D / acc_k.
+int adjoint_field_blocks(int nx, int ny);
+int adjoint_cone_blocks(int n);
+hipError_t launch_cone_adjoint2d(int n_species, const ConeRules& rules, const float* f0,
+                                 const float* f1, float* af0, float* af1, const float4* state,
+                                 const int32_t* status, const int32_t* event_step,
+                                 uint32_t step, float* acone, int n, hipStream_t stream);
+hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* c,
+                                  float* a_out, StencilCoef coef, double* acc_D,
+                                  double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
+                                  hipStream_t stream);
+hipError_t launch_adjoint_seed2d(const float* pos, const float* tip_target, const float* weight,
+                                 float* acone, double* partial, int n, hipStream_t stream);
+hipError_t launch_record_cones2d(ConeArrays cones, float4* out, hipStream_t stream);
+
+// Adjacency list of the connections and its breadth-first levels (kernels_graph.hip).
+struct GraphBuffers {
+    int32_t* owner = nullptr;          // [M] neuron owning each cone
+    int32_t* target_owner = nullptr;   // [T] neuron owning each target
+    int32_t* key = nullptr;            // [M] sort keys / values and their sorted copies
+    int32_t* cone = nullptr;
+    int32_t* key_sorted = nullptr;
+    int32_t* cone_sorted = nullptr;
+    int32_t* degree = nullptr;         // [N]
+    int32_t* row_start = nullptr;      // [N + 1]  (V_a)
+    int32_t* edges = nullptr;          // [M]      (E_a; the first row_start[N] are used)
+    int32_t* level = nullptr;          // [N]
+    int32_t* grew = nullptr;           // [1]
+    void* temp = nullptr;              // radix-sort scratch
+    size_t temp_bytes = 0;
+    int n_neurons = 0;
+};
+size_t graph_sort_temp_bytes(int n_cones, int n_neurons);
+hipError_t launch_adjacency(const GraphBuffers& g, const int32_t* status, const int32_t* target,
+                            int n_cones, int n_neurons, hipStream_t stream);
+hipError_t launch_bfs_init(int32_t* level, int n, int root, hipStream_t stream);
+hipError_t launch_bfs_level(const int32_t* row_start, const int32_t* edges, int n, int depth,
+                            int32_t* level, int32_t* grew, hipStream_t stream);
+
 // Sum of a field in FP64 (deterministic two-pass reduction) into *out (device).
 hipError_t launch_mass(const float* field, int64_t n, double* partial, int n_partial,
                        double* out, hipStream_t stream);

@@ -95,7 +95,9 @@ __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __res
         gx = fmaf(r.sign1, hx, gx);
         gy = fmaf(r.sign1, hy, gy);
     }
-    const ConeEvent ev = cone_step_2d(r, gx, gy, (uint32_t)i, step, x, y, th,
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    const ConeEvent ev = cone_step_2d(r, gx, gy, (uint32_t)i, step, x, y, th, sn, cs,
                                       GridContact{&r.targets});
     c.pos[2 * i] = x;
     c.pos[2 * i + 1] = y;

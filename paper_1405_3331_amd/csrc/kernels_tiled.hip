@@ -105,6 +105,19 @@ struct LdsField2D {
     }
 };
 
+// Value held by the lane below (lane_from_left) or above (lane_from_right) in the
+// wavefront: a whole-wave DPP shift by one lane, which moves data between lanes inside the
+// VALU instead of through the LDS crossbar.  Lane 0 (resp. 63) receives 0; it holds the
+// tile's outermost column, which is never valid after the first sub-step.
+__device__ __forceinline__ float lane_from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138 /* wave_shr:1 */,
+                                                      0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130 /* wave_shl:1 */,
+                                                      0xF, 0xF, false));
+}
+
 // New value of the CPL cells of one row from the old rows above (s), at (c) and below (n).
 // Horizontal neighbours across lanes come from the adjacent lanes' registers.  WALLS selects
 // the zero-flux rule for tiles that touch the grid boundary.
@@ -115,8 +128,8 @@ __device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CP
                                                            int gy, int gx0, int nx, int ny,
                                                            StencilCoef cf) {
     using V = typename Row<CPL>::T;
-    const float left = __shfl_up(comp(c, CPL - 1), 1, 64);  // column cx - 1
-    const float right = __shfl_down(comp(c, 0), 1, 64);     // column cx + CPL
+    const float left = lane_from_left(comp(c, CPL - 1));   // column cx - 1
+    const float right = lane_from_right(comp(c, 0));       // column cx + CPL
     V s = s_in, n = n_in;
     if (WALLS) {
         if (gy == 0) s = c;
@@ -247,13 +260,15 @@ __device__ __forceinline__ float2 tile_cone_gradient(const float4& st, const Lds
 
 // Second part; a stopped cone has its final state written to the caller-order arrays and
 // the sign bit of its id set.
-__device__ __forceinline__ void tile_cone_advance(float4& st, float2 g, const ConeRules& rules,
-                                                  uint32_t step, const TileContact& contact,
+__device__ __forceinline__ void tile_cone_advance(float4& st, float2& sc, float2 g,
+                                                  const ConeRules& rules, uint32_t step,
+                                                  const TileContact& contact,
                                                   const ConeArrays& cones) {
     int id = __float_as_int(st.w);
     if (id < 0) return;
     float x = st.x, y = st.y, th = st.z;
-    const ConeEvent ev = cone_step_2d(rules, g.x, g.y, (uint32_t)id, step, x, y, th, contact);
+    const ConeEvent ev =
+        cone_step_2d(rules, g.x, g.y, (uint32_t)id, step, x, y, th, sc.x, sc.y, contact);
     if (ev.status != kActive) {
         cones.pos[2 * id] = x;
         cones.pos[2 * id + 1] = y;
@@ -351,13 +366,17 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     const TileContact contact{tile_targets, n_tt, n_tt <= kMaxTileTargets, &a.rules.targets};
     if (contact.staged)
         for (int k = threadIdx.x; k < n_tt; k += kThreads) tile_targets[k] = a.tgt_pts[t_lo + k];
-    // the first kConeSlots * kThreads cones stay in registers for the whole launch; cone
-    // i sits in thread i % kThreads, slot i / kThreads
+    // every cone of the part stays in registers for the whole launch: cone i sits in
+    // thread i % kThreads, slot i / kThreads (a part holds at most kPartCones =
+    // kConeSlots * kThreads cones), with sincosf of its heading alongside
     float4 mine[kConeSlots];
+    float2 trig[kConeSlots];
 #pragma unroll
     for (int k = 0; k < kConeSlots; ++k) {
         const int i = threadIdx.x + k * kThreads;
         mine[k] = i < n_cones ? live[i] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+        trig[k] = make_float2(0.0f, 1.0f);
+        if (i < n_cones) sincosf(mine[k].z, &trig[k].x, &trig[k].y);
     }
     if (threadIdx.x < 9) {
         dest_count[threadIdx.x] = 0;
@@ -405,25 +424,18 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
             }
             __syncthreads();
         }
-        // 4. cones against the updated field.  Every read of the field happens before the
-        //    barrier (gradients of the register-held cones; whole steps of any further
-        //    cones); the register-held cones then finish their step after it, overlapping
-        //    the next sub-step's in-place stencil, which they no longer read.
+        // 4. cones against the updated field.  Every read of the field (the gradients)
+        //    happens before the barrier; the cones then finish their step after it,
+        //    overlapping the next sub-step's in-place stencil, which they no longer read.
         const uint32_t step = first_step + (uint32_t)b;
         if (n_cones > 0) {
             float2 g[kConeSlots];
 #pragma unroll
             for (int k = 0; k < kConeSlots; ++k) g[k] = tile_cone_gradient<NS>(mine[k], f0, f1, rules);
-            for (int i = threadIdx.x + kConeSlots * kThreads; i < n_cones; i += kThreads) {
-                float4 st = live[i];
-                tile_cone_advance(st, tile_cone_gradient<NS>(st, f0, f1, rules), rules, step,
-                                  contact, a.cones);
-                live[i] = st;
-            }
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < kConeSlots; ++k)
-                tile_cone_advance(mine[k], g[k], rules, step, contact, a.cones);
+                tile_cone_advance(mine[k], trig[k], g[k], rules, step, contact, a.cones);
         }
     }
 

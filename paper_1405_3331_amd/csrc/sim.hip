@@ -26,6 +26,21 @@ bool finite(double v) { return std::isfinite(v); }
 
 }  // namespace
 
+// Record of the last sim_adjoint_run: checkpoints every `every` steps of the forward run
+// (fields and caller-order cone state), the loss's per-cone target tips and weights.
+struct AdjointRun {
+    int64_t n0 = 0, n_steps = 0;
+    int every = 1, n_ckpt = 0;
+    float* ckpt_field = nullptr;        // [n_ckpt][n_species][n_cells]
+    float* ckpt_pos = nullptr;          // [n_ckpt][M][2]
+    float* ckpt_dir = nullptr;          // [n_ckpt][M]
+    int32_t* ckpt_int = nullptr;        // [n_ckpt][3][M]: status, target, event_step
+    float* tip_target = nullptr;        // [M][2]: t_a(i)
+    float* weight = nullptr;            // [M]
+    float* acone = nullptr;             // [M][3]
+    double* loss_partial = nullptr;     // [cone workgroups]
+};
+
 struct sim_handle {
     // geometry and coefficients
     int dim = 2, nx = 0, ny = 0, nz = 1;
@@ -61,6 +76,13 @@ struct sim_handle {
     int64_t step = 0;
     bool poisoned = false;
     std::string err;
+
+    // caller-order inputs the adjoint needs
+    std::vector<float> target_host;                          // [T][dim]
+    std::vector<int32_t> src_caller_cell[SIM_MAX_SPECIES];   // per source, caller order
+    AdjointRun* adj = nullptr;
+    GraphBuffers graph = {};                                 // last sim_connectivity
+    int graph_cones = 0;
 
     // timing of the step kernel
     bool timing = false;
@@ -122,7 +144,41 @@ void drop_events(sim_handle* h) {
     h->events.clear();
 }
 
+void adjoint_release(sim_handle* h) {
+    AdjointRun* a = h->adj;
+    if (!a) return;
+    dfree(a->ckpt_field);
+    dfree(a->ckpt_pos);
+    dfree(a->ckpt_dir);
+    dfree(a->ckpt_int);
+    dfree(a->tip_target);
+    dfree(a->weight);
+    dfree(a->acone);
+    dfree(a->loss_partial);
+    delete a;
+    h->adj = nullptr;
+}
+
+void graph_release(sim_handle* h) {
+    GraphBuffers& g = h->graph;
+    dfree(g.owner);
+    dfree(g.target_owner);
+    dfree(g.key);
+    dfree(g.cone);
+    dfree(g.key_sorted);
+    dfree(g.cone_sorted);
+    dfree(g.degree);
+    dfree(g.row_start);
+    dfree(g.edges);
+    dfree(g.level);
+    dfree(g.grew);
+    if (g.temp) (void)hipFree(g.temp);
+    g = GraphBuffers{};
+}
+
 void release(sim_handle* h) {
+    adjoint_release(h);
+    graph_release(h);
     for (int s = 0; s < SIM_MAX_SPECIES; ++s) {
         for (int b = 0; b < 2; ++b) dfree(h->field[s][b]);
         dfree(h->src_cell[s]);
@@ -476,6 +532,7 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
         if (e != hipSuccess) return bail(device_fail(h, e, "field upload"));
         st = upload_sources(h, p, s);
         if (st != SIM_OK) return bail(st);
+        h->src_caller_cell[s].assign(p->source_cell[s], p->source_cell[s] + p->n_sources[s]);
     }
     // cones (caller order)
     const size_t M = (size_t)p->n_cones;
@@ -498,6 +555,7 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
     }
     st = build_targets(h, p);
     if (st != SIM_OK) return bail(st);
+    h->target_host.assign(p->target_pos, p->target_pos + (size_t)p->n_targets * p->dim);
     if ((e = dalloc(&h->mass_partial, kMassPartials)) != hipSuccess ||
         (e = dalloc(&h->mass_out, SIM_MAX_SPECIES)) != hipSuccess)
         return bail(device_fail(h, e, "mass buffers"));
@@ -829,6 +887,346 @@ sim_status sim_destroy(sim_handle* h) {
 
 const char* sim_last_error(const sim_handle* h) {
     return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+// ------------------------------------------------------------------------------------
+// Trajectory-loss gradient (2D)
+// ------------------------------------------------------------------------------------
+namespace {
+
+int64_t cone_blocks(const sim_handle* h) { return adjoint_cone_blocks(std::max(h->n_cones, 1)); }
+
+// Loss seed from the current (final) cone state: a_p = 2 w (p - t), a_theta = 0; the
+// per-workgroup loss partials are left in adj->loss_partial.
+sim_status adjoint_seed(sim_handle* h) {
+    sim_status st = unbucket(h);
+    if (st != SIM_OK) return st;
+    AdjointRun* a = h->adj;
+    HIP_TRY(h, launch_adjoint_seed2d(h->cones.pos, a->tip_target, a->weight, a->acone,
+                                     a->loss_partial, h->n_cones, h->stream));
+    return SIM_OK;
+}
+
+}  // namespace
+
+sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_every,
+                           const int32_t* assign, const float* weight, double* loss) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    if (h->dim != 2) return fail(h, SIM_EINVAL, "the trajectory-loss gradient is 2D only");
+    if (n_steps < 0 || checkpoint_every < 1)
+        return fail(h, SIM_EINVAL, "n_steps < 0 or checkpoint_every < 1");
+    if (h->step + n_steps > 2147483647LL)
+        return fail(h, SIM_EINVAL, "step count would exceed 2^31-1");
+    if (!loss) return fail(h, SIM_EINVAL, "loss is NULL");
+    const int M = h->n_cones;
+    const int T = h->n_targets;
+    if (M > 0 && (!assign || !weight)) return fail(h, SIM_EINVAL, "assign or weight is NULL");
+    std::vector<float> tips((size_t)2 * M);
+    for (int i = 0; i < M; ++i) {
+        if (assign[i] < 0 || assign[i] >= T)
+            return fail(h, SIM_EINVAL, "assign[%d] = %d is not a target index", i, assign[i]);
+        if (!std::isfinite(weight[i])) return fail(h, SIM_EINVAL, "weight[%d] not finite", i);
+        tips[2 * i] = h->target_host[(size_t)assign[i] * 2];
+        tips[2 * i + 1] = h->target_host[(size_t)assign[i] * 2 + 1];
+    }
+    adjoint_release(h);
+    AdjointRun* a = new (std::nothrow) AdjointRun();
+    if (!a) return fail(h, SIM_ENOMEM, "adjoint record");
+    h->adj = a;
+    a->n0 = h->step;
+    a->n_steps = n_steps;
+    a->every = checkpoint_every;
+    a->n_ckpt = (int)((n_steps + checkpoint_every - 1) / checkpoint_every);
+    const size_t ns = (size_t)h->n_species, cells = (size_t)h->n_cells, Ms = (size_t)M;
+    const size_t nck = (size_t)a->n_ckpt;
+    hipError_t e;
+    if ((e = dalloc(&a->ckpt_field, nck * ns * cells)) != hipSuccess ||
+        (e = dalloc(&a->ckpt_pos, nck * Ms * 2)) != hipSuccess ||
+        (e = dalloc(&a->ckpt_dir, nck * Ms)) != hipSuccess ||
+        (e = dalloc(&a->ckpt_int, nck * 3 * Ms)) != hipSuccess ||
+        (e = dalloc(&a->tip_target, Ms * 2)) != hipSuccess ||
+        (e = dalloc(&a->weight, Ms)) != hipSuccess ||
+        (e = dalloc(&a->acone, Ms * 3)) != hipSuccess ||
+        (e = dalloc(&a->loss_partial, (size_t)cone_blocks(h))) != hipSuccess) {
+        adjoint_release(h);
+        if (e == hipErrorOutOfMemory)
+            return fail(h, SIM_ENOMEM, "adjoint checkpoints: out of device memory");
+        return device_fail(h, e, "adjoint allocation");
+    }
+    if (M > 0) {
+        HIP_TRY(h, hipMemcpyAsync(a->tip_target, tips.data(), Ms * 2 * 4, hipMemcpyHostToDevice,
+                                  h->stream));
+        HIP_TRY(h, hipMemcpyAsync(a->weight, weight, Ms * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    for (int j = 0; j < a->n_ckpt; ++j) {
+        sim_status st = unbucket(h);
+        if (st != SIM_OK) return st;
+        for (size_t s = 0; s < ns; ++s)
+            HIP_TRY(h, hipMemcpyAsync(a->ckpt_field + ((size_t)j * ns + s) * cells,
+                                      h->field[s][h->cur[s]], cells * 4,
+                                      hipMemcpyDeviceToDevice, h->stream));
+        if (M > 0) {
+            HIP_TRY(h, hipMemcpyAsync(a->ckpt_pos + (size_t)j * Ms * 2, h->cones.pos, Ms * 8,
+                                      hipMemcpyDeviceToDevice, h->stream));
+            HIP_TRY(h, hipMemcpyAsync(a->ckpt_dir + (size_t)j * Ms, h->cones.dir, Ms * 4,
+                                      hipMemcpyDeviceToDevice, h->stream));
+            int32_t* ci = a->ckpt_int + (size_t)j * 3 * Ms;
+            HIP_TRY(h, hipMemcpyAsync(ci, h->cones.status, Ms * 4, hipMemcpyDeviceToDevice,
+                                      h->stream));
+            HIP_TRY(h, hipMemcpyAsync(ci + Ms, h->cones.target, Ms * 4, hipMemcpyDeviceToDevice,
+                                      h->stream));
+            HIP_TRY(h, hipMemcpyAsync(ci + 2 * Ms, h->cones.event_step, Ms * 4,
+                                      hipMemcpyDeviceToDevice, h->stream));
+        }
+        const int64_t len = std::min<int64_t>(checkpoint_every, n_steps - (int64_t)j * checkpoint_every);
+        st = sim_step(h, len);
+        if (st != SIM_OK) return st;
+    }
+    sim_status st = adjoint_seed(h);
+    if (st != SIM_OK) return st;
+    std::vector<double> part((size_t)cone_blocks(h), 0.0);
+    if (M > 0)
+        HIP_TRY(h, hipMemcpyAsync(part.data(), a->loss_partial, part.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    double L = 0.0;
+    for (double v : part) L += v;
+    *loss = M > 0 ? L : 0.0;
+    return SIM_OK;
+}
+
+sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, double* dL_dk) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    AdjointRun* a = h->adj;
+    if (!a) return fail(h, SIM_ESTATE, "no sim_adjoint_run to differentiate");
+    if (h->step != a->n0 + a->n_steps)
+        return fail(h, SIM_ESTATE, "the simulation was stepped after sim_adjoint_run");
+    if (!dL_dq || !dL_dD || !dL_dk) return fail(h, SIM_EINVAL, "output pointer is NULL");
+    const int ns = h->n_species, M = h->n_cones, nx = h->nx, ny = h->ny;
+    const size_t cells = (size_t)h->n_cells, Ms = (size_t)M;
+    const int K = (int)std::min<int64_t>(a->every, std::max<int64_t>(a->n_steps, 1));
+    const int fb = adjoint_field_blocks(nx, ny);
+    int n_q[SIM_MAX_SPECIES] = {0, 0}, q_off[SIM_MAX_SPECIES] = {0, 0};
+    for (int s = 0; s < ns; ++s) n_q[s] = (int)h->src_caller_cell[s].size();
+    q_off[1] = n_q[0];
+    const int nq_all = n_q[0] + (ns > 1 ? n_q[1] : 0);
+
+    // workspace: one segment of fields and cone states, the recompute's cones, the field
+    // adjoint (ping-pong per species), FP64 accumulators
+    float* tape = nullptr;
+    float4* tape_cones = nullptr;
+    ConeArrays work = {};
+    float* afield = nullptr;
+    double* acc = nullptr;
+    int32_t* q_cell = nullptr;
+    auto free_all = [&]() {
+        dfree(tape);
+        dfree(tape_cones);
+        dfree(work.pos);
+        dfree(work.dir);
+        dfree(work.status);
+        dfree(work.target);
+        dfree(work.event_step);
+        dfree(afield);
+        dfree(acc);
+        dfree(q_cell);
+    };
+    hipError_t e;
+    const size_t acc_n = (size_t)2 * ns * fb + (size_t)std::max(nq_all, 1);
+    if ((e = dalloc(&tape, (size_t)(K + 1) * ns * cells)) != hipSuccess ||
+        (e = dalloc(&tape_cones, (size_t)K * std::max<size_t>(Ms, 1))) != hipSuccess ||
+        (e = dalloc(&work.pos, Ms * 2)) != hipSuccess ||
+        (e = dalloc(&work.dir, Ms)) != hipSuccess ||
+        (e = dalloc(&work.status, Ms)) != hipSuccess ||
+        (e = dalloc(&work.target, Ms)) != hipSuccess ||
+        (e = dalloc(&work.event_step, Ms)) != hipSuccess ||
+        (e = dalloc(&afield, (size_t)2 * ns * cells)) != hipSuccess ||
+        (e = dalloc(&acc, acc_n)) != hipSuccess ||
+        (e = dalloc(&q_cell, (size_t)std::max(nq_all, 1))) != hipSuccess) {
+        free_all();
+        if (e == hipErrorOutOfMemory)
+            return fail(h, SIM_ENOMEM, "adjoint workspace: out of device memory");
+        return device_fail(h, e, "adjoint workspace");
+    }
+    work.n = M;
+#define ADJ_TRY(expr)                                                       \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) {                                             \
+            free_all();                                                     \
+            return device_fail(h, e_, #expr);                               \
+        }                                                                   \
+    } while (0)
+    for (int s = 0; s < ns; ++s)
+        if (n_q[s] > 0)
+            ADJ_TRY(hipMemcpyAsync(q_cell + q_off[s], h->src_caller_cell[s].data(), n_q[s] * 4,
+                                   hipMemcpyHostToDevice, h->stream));
+    ADJ_TRY(hipMemsetAsync(afield, 0, (size_t)2 * ns * cells * sizeof(float), h->stream));
+    ADJ_TRY(hipMemsetAsync(acc, 0, acc_n * sizeof(double), h->stream));
+    double* acc_D = acc;
+    double* acc_k = acc + (size_t)ns * fb;
+    double* acc_q = acc + (size_t)2 * ns * fb;
+    sim_status st = adjoint_seed(h);   // final statuses now in h->cones (caller order)
+    if (st != SIM_OK) {
+        free_all();
+        return st;
+    }
+    auto field_at = [&](int t, int s) { return tape + ((size_t)t * ns + s) * cells; };
+    int cur = 0;
+    auto afield_at = [&](int s, int half) { return afield + ((size_t)s * 2 + half) * cells; };
+    for (int j = a->n_ckpt - 1; j >= 0; --j) {
+        const int64_t seg0 = a->n0 + (int64_t)j * a->every;
+        const int len = (int)std::min<int64_t>(a->every, a->n_steps - (int64_t)j * a->every);
+        // restore the checkpoint and recompute the segment, recording every step
+        ADJ_TRY(hipMemcpyAsync(tape, a->ckpt_field + (size_t)j * ns * cells,
+                               (size_t)ns * cells * 4, hipMemcpyDeviceToDevice, h->stream));
+        if (M > 0) {
+            const int32_t* ci = a->ckpt_int + (size_t)j * 3 * Ms;
+            ADJ_TRY(hipMemcpyAsync(work.pos, a->ckpt_pos + (size_t)j * Ms * 2, Ms * 8,
+                                   hipMemcpyDeviceToDevice, h->stream));
+            ADJ_TRY(hipMemcpyAsync(work.dir, a->ckpt_dir + (size_t)j * Ms, Ms * 4,
+                                   hipMemcpyDeviceToDevice, h->stream));
+            ADJ_TRY(hipMemcpyAsync(work.status, ci, Ms * 4, hipMemcpyDeviceToDevice, h->stream));
+            ADJ_TRY(hipMemcpyAsync(work.target, ci + Ms, Ms * 4, hipMemcpyDeviceToDevice,
+                                   h->stream));
+            ADJ_TRY(hipMemcpyAsync(work.event_step, ci + 2 * Ms, Ms * 4,
+                                   hipMemcpyDeviceToDevice, h->stream));
+        }
+        for (int t = 0; t < len; ++t) {
+            ADJ_TRY(launch_record_cones2d(work, tape_cones + (size_t)t * Ms, h->stream));
+            for (int s = 0; s < ns; ++s) {
+                ADJ_TRY(launch_field_plain(2, nx, ny, 1, field_at(t, s), field_at(t + 1, s),
+                                           h->coef[s], h->stream));
+                ADJ_TRY(launch_sources(field_at(t + 1, s),
+                                       SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
+                                       h->stream));
+            }
+            ADJ_TRY(launch_cones_plain(2, h->rules, field_at(t + 1, 0),
+                                       field_at(t + 1, ns > 1 ? 1 : 0), work,
+                                       (uint32_t)(seg0 + t), h->stream));
+        }
+        // reverse the segment's steps
+        for (int t = len - 1; t >= 0; --t) {
+            ADJ_TRY(launch_cone_adjoint2d(ns, h->rules, field_at(t + 1, 0),
+                                          field_at(t + 1, ns > 1 ? 1 : 0), afield_at(0, cur),
+                                          afield_at(ns > 1 ? 1 : 0, cur),
+                                          tape_cones + (size_t)t * Ms, h->cones.status,
+                                          h->cones.event_step, (uint32_t)(seg0 + t), a->acone,
+                                          M, h->stream));
+            for (int s = 0; s < ns; ++s)
+                ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), field_at(t, s),
+                                               afield_at(s, cur ^ 1), h->coef[s],
+                                               acc_D + (size_t)s * fb, acc_k + (size_t)s * fb,
+                                               q_cell + q_off[s], n_q[s], acc_q + q_off[s],
+                                               h->stream));
+            cur ^= 1;
+        }
+    }
+    std::vector<double> host(acc_n);
+    ADJ_TRY(hipMemcpyAsync(host.data(), acc, acc_n * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    ADJ_TRY(hipStreamSynchronize(h->stream));
+#undef ADJ_TRY
+    free_all();
+    const double dx2 = h->dx * h->dx;
+    for (int s = 0; s < ns; ++s) {
+        double sD = 0.0, sk = 0.0;
+        for (int b = 0; b < fb; ++b) {
+            sD += host[(size_t)s * fb + b];
+            sk += host[(size_t)(ns + s) * fb + b];
+        }
+        dL_dD[s] = sD * h->dt / dx2;
+        dL_dk[s] = -h->dt * sk;
+    }
+    for (int m = 0; m < nq_all; ++m) dL_dq[m] = host[(size_t)2 * ns * fb + m] / dx2;
+    return SIM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Connectivity: adjacency list of the contacts and breadth-first levels
+// ------------------------------------------------------------------------------------
+sim_status sim_connectivity(sim_handle* h, int32_t n_neurons, const int32_t* cone_owner,
+                            const int32_t* target_owner, int32_t* row_start, int32_t* edges,
+                            int64_t edge_capacity, int64_t* n_edges) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    const int M = h->n_cones, T = h->n_targets;
+    if (n_neurons < 1) return fail(h, SIM_EINVAL, "n_neurons < 1");
+    if (!row_start || !n_edges || edge_capacity < 0 || (edge_capacity > 0 && !edges) ||
+        (M > 0 && !cone_owner) || (T > 0 && !target_owner))
+        return fail(h, SIM_EINVAL, "NULL pointer or negative capacity");
+    for (int i = 0; i < M; ++i)
+        if (cone_owner[i] < 0 || cone_owner[i] >= n_neurons)
+            return fail(h, SIM_EINVAL, "cone_owner[%d] = %d out of range", i, cone_owner[i]);
+    for (int t = 0; t < T; ++t)
+        if (target_owner[t] < 0 || target_owner[t] >= n_neurons)
+            return fail(h, SIM_EINVAL, "target_owner[%d] = %d out of range", t, target_owner[t]);
+    graph_release(h);
+    GraphBuffers& g = h->graph;
+    const size_t Ms = (size_t)std::max(M, 1), N = (size_t)n_neurons;
+    g.n_neurons = n_neurons;
+    g.temp_bytes = graph_sort_temp_bytes(M, n_neurons);
+    hipError_t e;
+    if ((e = dalloc(&g.owner, Ms)) != hipSuccess ||
+        (e = dalloc(&g.target_owner, (size_t)std::max(T, 1))) != hipSuccess ||
+        (e = dalloc(&g.key, Ms)) != hipSuccess || (e = dalloc(&g.cone, Ms)) != hipSuccess ||
+        (e = dalloc(&g.key_sorted, Ms)) != hipSuccess ||
+        (e = dalloc(&g.cone_sorted, Ms)) != hipSuccess ||
+        (e = dalloc(&g.degree, N)) != hipSuccess || (e = dalloc(&g.row_start, N + 1)) != hipSuccess ||
+        (e = dalloc(&g.edges, Ms)) != hipSuccess || (e = dalloc(&g.level, N)) != hipSuccess ||
+        (e = dalloc(&g.grew, 1)) != hipSuccess ||
+        (g.temp_bytes > 0 && (e = hipMalloc(&g.temp, g.temp_bytes)) != hipSuccess)) {
+        graph_release(h);
+        if (e == hipErrorOutOfMemory) return fail(h, SIM_ENOMEM, "connectivity buffers");
+        return device_fail(h, e, "connectivity allocation");
+    }
+    if (M > 0)
+        HIP_TRY(h, hipMemcpyAsync(g.owner, cone_owner, (size_t)M * 4, hipMemcpyHostToDevice,
+                                  h->stream));
+    if (T > 0)
+        HIP_TRY(h, hipMemcpyAsync(g.target_owner, target_owner, (size_t)T * 4,
+                                  hipMemcpyHostToDevice, h->stream));
+    // stopped cones keep their final status and target in the caller-order arrays
+    HIP_TRY(h, launch_adjacency(g, h->cones.status, h->cones.target, M, n_neurons, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(row_start, g.row_start, (N + 1) * 4, hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const int64_t E = row_start[n_neurons];
+    *n_edges = E;
+    h->graph_cones = M;
+    if (E > edge_capacity)
+        return fail(h, SIM_ERANGE, "edge buffer holds %lld edges, %lld needed",
+                    (long long)edge_capacity, (long long)E);
+    if (E > 0) {
+        HIP_TRY(h, hipMemcpyAsync(edges, g.edges, (size_t)E * 4, hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return SIM_OK;
+}
+
+sim_status sim_bfs_levels(sim_handle* h, int32_t root, int32_t* level) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    GraphBuffers& g = h->graph;
+    if (!g.row_start) return fail(h, SIM_ESTATE, "no sim_connectivity graph to traverse");
+    if (!level) return fail(h, SIM_EINVAL, "level is NULL");
+    const int N = g.n_neurons;
+    if (root < 0 || root >= N) return fail(h, SIM_EINVAL, "root %d out of range", root);
+    HIP_TRY(h, launch_bfs_init(g.level, N, root, h->stream));
+    for (int depth = 0; depth < N; ++depth) {
+        int32_t grew = 0;
+        HIP_TRY(h, hipMemsetAsync(g.grew, 0, sizeof(int32_t), h->stream));
+        HIP_TRY(h, launch_bfs_level(g.row_start, g.edges, N, depth, g.level, g.grew, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(&grew, g.grew, sizeof grew, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        if (!grew) break;
+    }
+    HIP_TRY(h, hipMemcpyAsync(level, g.level, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return SIM_OK;
 }
 
 sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hip_stream,

@@ -699,6 +699,46 @@ def pin_adjoint_no_coupling(lib_path=LIB):
     assert abs(loss - float((d * d).sum())) <= 1e-12 * loss
 
 
+# ---------------------------------------------------------------------------------------
+# Connectivity (Sec. 3.4, Figs. 4-5): the adjacency list against its definition written out
+# as Python lists, the breadth-first levels against scipy's unweighted shortest paths and a
+# hand-built graph.
+# ---------------------------------------------------------------------------------------
+def pin_connectivity(lib_path=LIB):
+    import scipy.sparse
+    import scipy.sparse.csgraph
+    lib = oracle.load(lib_path)
+    # hand-built: edges 0->1, 0->3, 1->2, 2->0 (cycle), 3->3 (self loop), 4 isolated
+    status = np.array([1, 1, 1, 1, 0, 1, 2], dtype=np.int32)
+    target = np.array([0, 1, 2, 3, -1, 4, -1], dtype=np.int32)
+    owner = np.array([0, 1, 2, 0, 4, 3, 4], dtype=np.int32)
+    towner = np.array([1, 2, 0, 3, 3], dtype=np.int32)
+    row, edges = oracle.connectivity(5, status, target, owner, towner, lib=lib)
+    assert row.tolist() == [0, 2, 3, 4, 5, 5] and edges.tolist() == [1, 3, 2, 0, 3]
+    assert oracle.bfs_levels(row, edges, 0, lib=lib).tolist() == [0, 1, 2, 1, -1]
+    assert oracle.bfs_levels(row, edges, 2, lib=lib).tolist() == [1, 2, 0, 2, -1]
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        N = int(rng.integers(1, 60))
+        M = int(rng.integers(0, 400))
+        T = int(rng.integers(1, 50))
+        status = rng.integers(0, 3, M).astype(np.int32)
+        target = np.where(status == 1, rng.integers(0, T, M), -1).astype(np.int32)
+        owner = rng.integers(0, N, M).astype(np.int32)
+        towner = rng.integers(0, N, T).astype(np.int32)
+        row, edges = oracle.connectivity(N, status, target, owner, towner, lib=lib)
+        lists = [[int(towner[target[i]]) for i in range(M) if status[i] == 1 and owner[i] == v]
+                 for v in range(N)]
+        assert row.tolist() == [0] + list(np.cumsum([len(x) for x in lists]))
+        assert edges.tolist() == [u for x in lists for u in x]
+        adj = scipy.sparse.csr_matrix((np.ones(len(edges)), edges, row), shape=(N, N))
+        root = int(rng.integers(0, N))
+        dist = scipy.sparse.csgraph.shortest_path(adj, directed=True, unweighted=True,
+                                                  indices=root)
+        want = np.where(np.isinf(dist), -1, dist).astype(np.int32)
+        assert oracle.bfs_levels(row, edges, root, lib=lib).tolist() == want.tolist(), trial
+
+
 ALL_PINS = {
     "mass2d": lambda p: pin_mass_recursion(p, 2),
     "mass3d": lambda p: pin_mass_recursion(p, 3),
@@ -720,4 +760,5 @@ ALL_PINS = {
     "normals": lambda p: pin_normal_statistics(p, 20_000),
     "adjoint": lambda p: pin_adjoint_fd(p, 1, 40),
     "adjoint2": lambda p: pin_adjoint_fd(p, 2, 40),
+    "graph": pin_connectivity,
 }

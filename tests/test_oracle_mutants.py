@@ -67,6 +67,11 @@ MUTANTS = [
      ["adjoint"]),
     ("adjoint_source_units", "dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]] / vol;",
      "dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]];", ["adjoint"]),
+    ("bfs_level_step", "level[u] = level[v] + 1;", "level[u] = level[v] + 2;", ["graph"]),
+    ("adjacency_by_target_owner", "row_start[cone_owner[i] + 1] += 1;",
+     "row_start[target_owner[target[i]] + 1] += 1;", ["graph"]),
+    ("adjacency_counts_exits", "        if (status[i] == ORACLE_CONTACT)\n            row_start",
+     "        if (status[i] != ORACLE_ACTIVE)\n            row_start", ["graph"]),
 ]
 
 

@@ -99,3 +99,7 @@ def test_adjoint_matches_finite_differences(n_species):
 
 def test_adjoint_zero_without_coupling():
     pins.pin_adjoint_no_coupling()
+
+
+def test_connectivity_and_bfs():
+    pins.pin_connectivity()
