@@ -11,7 +11,8 @@
 // Halo: a cone bucketed to the core at block start is at most ceil((B-1) s / dx) cells away
 // from the core before its last sub-step and samples cells up to 2 away from its own cell,
 // while the valid region after sub-step b is the core grown by H - b; so
-// H = B + ceil((B-1) s / dx) + 2 keeps every sample inside valid cells.
+// H = B + ceil((B-1) s / dx) + 2 keeps every sample inside valid cells.  H is rounded up to
+// a multiple of the per-lane segment width so that segments stay aligned to the grid.
 //
 // Layout of a tile row in LDS: one wavefront spans the loaded width W = 64 * CPL, lane l
 // owning columns CPL*l .. CPL*l + CPL-1.  The eight wavefronts of a workgroup own
@@ -38,7 +39,7 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxTileTargets = 256;        // targets staged in LDS per tile
 constexpr size_t kLdsBudget = 154 * 1024;   // dynamic LDS; the rest is static (targets,
                                             // re-bucketing counters)
-constexpr int kLoadBatch = 4;               // tile rows a wavefront has in flight at load
+constexpr int kLoadBatch = 10;              // tile rows a wavefront has in flight at load
 constexpr int kConeSlots = 2;               // cones per thread held in registers
 constexpr int kPartCones = kConeSlots * kThreads;   // cones one work item steps
 constexpr size_t kStaticLds = kMaxTileTargets * 16 + 3 * 9 * 4 + 16;   // static LDS per tile
@@ -91,6 +92,62 @@ __device__ __forceinline__ void set_comp(float2& v, int k, float x) {
 }
 __device__ __forceinline__ void set_comp(float4& v, int k, float x) {
     if (k == 0) v.x = x; else if (k == 1) v.y = x; else if (k == 2) v.z = x; else v.w = x;
+}
+
+// Global-address-space view of a pointer held in a table: loads and stores through it are
+// global (vector-memory only) rather than flat accesses, which would also count against
+// the LDS wait counter.
+template <class T>
+using GlobalPtr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ GlobalPtr<T> gbl(T* p) {
+    return (GlobalPtr<T>)p;
+}
+// HIP's vector structs do not bind to address-space-qualified references: move them as
+// clang vectors.
+using f4v = float __attribute__((ext_vector_type(4)));
+using i2v = int __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 gload(GlobalPtr<const float4> p) {
+    const f4v v = *(GlobalPtr<const f4v>)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int2 gload(GlobalPtr<const int2> p) {
+    const i2v v = *(GlobalPtr<const i2v>)p;
+    return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(GlobalPtr<float4> p, float4 v) {
+    *(GlobalPtr<f4v>)p = f4v{v.x, v.y, v.z, v.w};
+}
+
+// One tile row segment of CPL floats per lane: row gy, columns gx0 .. gx0 + CPL - 1 of the
+// field.  Every load is issued (indices clamped into the grid, so no lane branches around
+// it) and a cell outside the grid is replaced by zero afterwards.  With `aligned` (the
+// segment starts at a multiple of CPL and the row length is one) the segment lies wholly
+// inside or wholly outside the grid's columns and is one naturally aligned vector load.
+template <int CPL>
+using RowVec = float __attribute__((ext_vector_type(CPL)));
+
+template <int CPL>
+__device__ __forceinline__ typename Row<CPL>::T load_row(GlobalPtr<const float> f, int nx,
+                                                         int ny, int gy, int gx0,
+                                                         const bool (&col_in)[CPL],
+                                                         bool aligned) {
+    typename Row<CPL>::T v;
+    const bool row_in = (unsigned)gy < (unsigned)ny;
+    const size_t at = (size_t)min(max(gy, 0), ny - 1) * nx;
+    if (aligned) {
+        const RowVec<CPL> x = *(GlobalPtr<const RowVec<CPL>>)(f + at + min(max(gx0, 0), nx - CPL));
+        const bool in = row_in && col_in[0];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) set_comp(v, k, in ? x[k] : 0.0f);
+        return v;
+    }
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const float x = f[at + min(max(gx0 + k, 0), nx - 1)];
+        set_comp(v, k, row_in && col_in[k] ? x : 0.0f);
+    }
+    return v;
 }
 
 // LDS view of one species with tile-origin offset; indices are clamped to the tile so a
@@ -332,25 +389,43 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     const int cx = CPL * lane;
     const int gx0 = x0 + cx;
 
+    // 0. this part's cones and the tile's targets, fetched first so that their latency
+    //    overlaps the tile load.  Every cone of the part stays in registers for the whole
+    //    launch: cone i sits in thread i % kThreads, slot i / kThreads (a part holds at
+    //    most kPartCones = kConeSlots * kThreads cones).
+    const int first_cone = part * kPartCones;
+    const int n_cones = max(0, min(gbl(count_in)[tile] - first_cone, kPartCones));
+    const GlobalPtr<const float4> live = gbl(bucket_in) + (size_t)tile * a.capacity + first_cone;
+    const int t_lo = gbl(a.tgt_start)[tile], n_tt = gbl(a.tgt_start)[tile + 1] - t_lo;
+    const TileContact contact{tile_targets, n_tt, n_tt <= kMaxTileTargets, &a.rules.targets};
+    if (contact.staged)
+        for (int k = threadIdx.x; k < n_tt; k += kThreads)
+            tile_targets[k] = gload(gbl(a.tgt_pts) + t_lo + k);
+    float4 mine[kConeSlots];
+#pragma unroll
+    for (int k = 0; k < kConeSlots; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        mine[k] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+        if (i < n_cones) mine[k] = gload(live + i);
+    }
+
     // 1. load the tile, kLoadBatch rows in flight per wavefront; cells outside the grid
     //    read as zero and are never used by cells inside it, which take their own value
     //    for out-of-grid neighbours
+    bool col_in[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) col_in[k] = (unsigned)(gx0 + k) < (unsigned)a.nx;
+    // whole-segment vector loads and stores when segments cannot straddle the grid edge
+    const bool aligned = (x0 % CPL) == 0 && (a.nx % CPL) == 0 && (a.tx_core % CPL) == 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+        const GlobalPtr<const float> f = gbl((const float*)in[s]);
         for (int ly0 = wave; ly0 < HL; ly0 += kLoadBatch * kWaves) {
             V v[kLoadBatch];
 #pragma unroll
             for (int r = 0; r < kLoadBatch; ++r) {
                 const int ly = ly0 + r * kWaves;
-                const int gy = y0 + ly;
-                const bool row_in = ly < HL && (unsigned)gy < (unsigned)a.ny;
-                const size_t at = row_in ? (size_t)gy * a.nx : 0;
-#pragma unroll
-                for (int k = 0; k < CPL; ++k) {
-                    const int gx = gx0 + k;
-                    set_comp(v[r], k, row_in && (unsigned)gx < (unsigned)a.nx ? in[s][at + gx]
-                                                                              : 0.0f);
-                }
+                if (ly < HL) v[r] = load_row<CPL>(f, a.nx, a.ny, y0 + ly, gx0, col_in, aligned);
             }
 #pragma unroll
             for (int r = 0; r < kLoadBatch; ++r) {
@@ -359,24 +434,12 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
             }
         }
     }
-    const int first_cone = part * kPartCones;
-    const int n_cones = max(0, min(count_in[tile] - first_cone, kPartCones));
-    float4* live = bucket_in + (size_t)tile * a.capacity + first_cone;
-    const int t_lo = a.tgt_start[tile], n_tt = a.tgt_start[tile + 1] - t_lo;
-    const TileContact contact{tile_targets, n_tt, n_tt <= kMaxTileTargets, &a.rules.targets};
-    if (contact.staged)
-        for (int k = threadIdx.x; k < n_tt; k += kThreads) tile_targets[k] = a.tgt_pts[t_lo + k];
-    // every cone of the part stays in registers for the whole launch: cone i sits in
-    // thread i % kThreads, slot i / kThreads (a part holds at most kPartCones =
-    // kConeSlots * kThreads cones), with sincosf of its heading alongside
-    float4 mine[kConeSlots];
+    // sincosf of every heading, carried alongside the cone from sub-step to sub-step
     float2 trig[kConeSlots];
 #pragma unroll
     for (int k = 0; k < kConeSlots; ++k) {
-        const int i = threadIdx.x + k * kThreads;
-        mine[k] = i < n_cones ? live[i] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
         trig[k] = make_float2(0.0f, 1.0f);
-        if (i < n_cones) sincosf(mine[k].z, &trig[k].x, &trig[k].y);
+        if (threadIdx.x + k * kThreads < n_cones) sincosf(mine[k].z, &trig[k].x, &trig[k].y);
     }
     if (threadIdx.x < 9) {
         dest_count[threadIdx.x] = 0;
@@ -386,7 +449,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
 
     const int R = (HL + kWaves - 1) / kWaves;
     const int ybeg = min(wave * R, HL), yend = min(ybeg + R, HL);
-    const int src_lo = a.src_start[tile], src_hi = a.src_start[tile + 1];
+    const int src_lo = gbl(a.src_start)[tile], src_hi = gbl(a.src_start)[tile + 1];
     const ConeRules& rules = a.rules;
     const bool walls = x0 <= 0 || x0 + W >= a.nx || y0 <= 0 || y0 + HL >= a.ny;
     const LdsField2D f0{lds + W, x0, y0, W, HL};
@@ -419,8 +482,8 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
         // 3. sources inside the tile (entries are unique cells per species)
         if (src_hi > src_lo) {
             for (int e = src_lo + threadIdx.x; e < src_hi; e += kThreads) {
-                const int2 ent = a.src_entry[e];
-                lds[ent.y * plane + W + ent.x] += a.src_amount[e];
+                const int2 ent = gload(gbl(a.src_entry) + e);
+                lds[ent.y * plane + W + ent.x] += gbl(a.src_amount)[e];
             }
             __syncthreads();
         }
@@ -439,7 +502,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
         }
     }
 
-    // 5. write the core back (one part per tile does)
+    // 5. write the core back (one part per tile does), through global-address-space stores
     const int cx0 = tx * a.tx_core, cy0 = ty * a.ty_core;
     for (int ly = wave; part == 0 && ly < a.ty_core; ly += kWaves) {
         const int gy = cy0 + ly;
@@ -447,27 +510,37 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const V v = *(const V*)&lds[s * plane + (ly + H + 1) * W + cx];
+            const GlobalPtr<float> row = gbl(out[s]) + (size_t)gy * a.nx + cx0;
+            if (aligned) {
+                const int lx = cx - H;   // the segment is wholly inside or outside the core
+                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx) {
+                    RowVec<CPL> x;
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) x[k] = comp(v, k);
+                    *(GlobalPtr<RowVec<CPL>>)(row + lx) = x;
+                }
+                continue;
+            }
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
                 const int lx = cx + k - H;   // core column of this lane's k-th cell
-                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx)
-                    out[s][(size_t)gy * a.nx + cx0 + lx] = comp(v, k);
+                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx) row[lx] = comp(v, k);
             }
         }
     }
 
-    // 6. re-bucket surviving cones into the tile that now holds their tip
+    // 6. re-bucket surviving cones, straight from registers, into the tile that now holds
+    //    their tip (one of the 3 x 3 tiles around this one)
+    int dest[kConeSlots];
 #pragma unroll
     for (int k = 0; k < kConeSlots; ++k) {
-        const int i = threadIdx.x + k * kThreads;
-        if (i < n_cones) live[i] = mine[k];
-    }
-    for (int i = threadIdx.x; i < n_cones; i += kThreads) {
-        const float4 st = live[i];
-        if (__float_as_int(st.w) < 0) continue;
-        const int2 nt = next_tile(st, tx, ty, a.tiles_x, tiles_y, rules.inv_dx, a.nx, a.ny,
-                                  a.tx_core, a.ty_core);
-        atomicAdd(&dest_count[(nt.y - ty + 1) * 3 + (nt.x - tx + 1)], 1);
+        dest[k] = -1;
+        if (threadIdx.x + k * kThreads < n_cones && __float_as_int(mine[k].w) >= 0) {
+            const int2 nt = next_tile(mine[k], tx, ty, a.tiles_x, tiles_y, rules.inv_dx, a.nx,
+                                      a.ny, a.tx_core, a.ty_core);
+            dest[k] = (nt.y - ty + 1) * 3 + (nt.x - tx + 1);
+            atomicAdd(&dest_count[dest[k]], 1);
+        }
     }
     __syncthreads();
     if (threadIdx.x < 9 && dest_count[threadIdx.x] > 0) {
@@ -476,14 +549,13 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
                                            dest_count[threadIdx.x]);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n_cones; i += kThreads) {
-        const float4 st = live[i];
-        if (__float_as_int(st.w) < 0) continue;
-        const int2 nt = next_tile(st, tx, ty, a.tiles_x, tiles_y, rules.inv_dx, a.nx, a.ny,
-                                  a.tx_core, a.ty_core);
-        const int d = (nt.y - ty + 1) * 3 + (nt.x - tx + 1);
+#pragma unroll
+    for (int k = 0; k < kConeSlots; ++k) {
+        const int d = dest[k];
+        if (d < 0) continue;
+        const int ntx = tx + d % 3 - 1, nty = ty + d / 3 - 1;
         const int slot = dest_base[d] + atomicAdd(&dest_fill[d], 1);
-        bucket_out[(size_t)(nt.y * a.tiles_x + nt.x) * a.capacity + slot] = st;
+        gstore(gbl(bucket_out) + (size_t)(nty * a.tiles_x + ntx) * a.capacity + slot, mine[k]);
     }
 }
 
@@ -541,10 +613,11 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
     const int par = ls->parity;
     const int n_items = ls->n_items;
     if (!persistent) {
-        if ((int)blockIdx.x < n_items) {
-            const int4 it = items[blockIdx.x];
+        // the item list has one entry per workgroup of the grid: fetch it alongside the
+        // launch state (an entry past n_items is not used)
+        const int4 it = items[blockIdx.x];
+        if ((int)blockIdx.x < n_items)
             tile_body<NS, CPL>(table[it.x], it.y, it.z, steps, first_step, par);
-        }
     } else {
         for (;;) {
             __syncthreads();   // the previous item is done with LDS and item_idx
@@ -640,10 +713,13 @@ TiledPlan plan_search(int dim, int nx, int ny, int nz, int n_species, double ste
         // halo: B sub-steps of shrinkage + cone travel before the last sub-step + the
         // gradient footprint (two cells); the small epsilon covers FP32 rounding of travel
         const int travel = (int)std::ceil((B - 1) * step_cells + 1e-3);
-        const int H = B + travel + 2;
+        const int H_min = B + travel + 2;
         const int move = (int)std::ceil(B * step_cells + 1e-3);
         for (int cpl : {2, 4}) {
             if (only_cpl && cpl != only_cpl) continue;
+            // a halo (and so a core) that is a multiple of the lane segment keeps every
+            // segment aligned: whole-segment vector loads and stores
+            const int H = (H_min + cpl - 1) / cpl * cpl;
             const int W = 64 * cpl;
             const int TX = W - 2 * H;
             if (TX < 16 || TX <= move) continue;
