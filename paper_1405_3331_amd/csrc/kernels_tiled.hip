@@ -66,6 +66,7 @@ struct TiledArgs2D {
     int32_t* count[2];         // the input counts are zeroed by each workgroup for reuse as
                                // the next launch's output
     int capacity;
+    int cone_rows;             // stencil rows a wavefront gives up per cone slot it steps
     ConeArrays cones;
     ConeRules rules;
 };
@@ -447,8 +448,25 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     }
     __syncthreads();
 
-    const int R = (HL + kWaves - 1) / kWaves;
-    const int ybeg = min(wave * R, HL), yend = min(ybeg + R, HL);
+    // Strips of rows per wavefront, balanced against the cone work: a wavefront stepping
+    // cones in k register slots gives up k * cone_rows rows to the others, so that every
+    // wavefront does about the same work between two barriers.  Boundaries are computed
+    // for every wavefront in scalar registers and kept monotone.
+    int ybeg = 0, yend = 0;
+    {
+        const int c0 = min(kWaves, (n_cones + 63) / 64);                 // slot-0 waves
+        const int c1 = min(kWaves, (max(n_cones - kThreads, 0) + 63) / 64);   // slot-1 waves
+        const float per = (float)(HL + a.cone_rows * (c0 + c1)) / kWaves;
+        int prev = 0;
+        for (int w = 1; w <= kWaves; ++w) {
+            const int used = a.cone_rows * (min(w, c0) + min(w, c1));
+            const int b = w == kWaves ? HL : min(max((int)rintf(w * per) - used, prev), HL);
+            if (w == wave) ybeg = b;       // wavefront w's strip is [b(w), b(w + 1))
+            if (w == wave + 1) yend = b;
+            prev = b;
+        }
+        if (wave == 0) ybeg = 0;
+    }
     const int src_lo = gbl(a.src_start)[tile], src_hi = gbl(a.src_start)[tile + 1];
     const ConeRules& rules = a.rules;
     const bool walls = x0 <= 0 || x0 + W >= a.nx || y0 <= 0 || y0 + HL >= a.ny;
@@ -752,6 +770,9 @@ TiledPlan plan_search(int dim, int nx, int ny, int nz, int n_species, double ste
                     best.n_tiles = best.tiles_x * best.tiles_y;
                     best.lds_bytes = lds;
                     best.height = HL;
+                    // one cone step costs about as much as a stencil row of ~30 cells per
+                    // lane-slot pair: 15 rows of two-cell segments for one species
+                    best.cone_rows = std::max(1, 30 / (cpl * n_species));
                 }
             }
         }
@@ -897,6 +918,7 @@ hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
     a.count[0] = st.count[0];
     a.count[1] = st.count[1];
     a.capacity = st.capacity;
+    a.cone_rows = plan.cone_rows;
     a.cones = cones;
     a.rules = rules;
     if ((e = hipMalloc(&st.table, sizeof(TiledArgs2D))) != hipSuccess) return e;

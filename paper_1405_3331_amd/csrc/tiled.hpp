@@ -22,6 +22,7 @@ struct TiledPlan {
     int height = 0;          // loaded tile height (rows), core_y + 2 * halo
     int move = 0;            // cells a tip can travel in one launch, ceil(B * s / dx)
     int cpl = 2;             // columns per lane: loaded tile width is 64 * cpl
+    int cone_rows = 15;      // strip rows traded per occupied cone slot (load balance)
     int n_species = 1;
     int nx = 0, ny = 0, nz = 1;
     float inv_dx = 1.0f;
