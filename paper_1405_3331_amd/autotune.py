@@ -1,7 +1,8 @@
 """Empirical autotuner for the tiled step kernel.
 
 The library's planner picks the blocking depth B and the tile shape from a cost model.  This
-module measures instead: for a scenario it times a few full-depth launches of candidate
+module measures instead: for a scenario it times whole runs (the scenario's step count, so
+that the late phase, when cones crowd around sources and targets, weighs in) of candidate
 (B, row width, tile height) settings on the GPU through the C ABI -- on fresh copies of the
 scenario, so nothing the caller holds is advanced -- and caches the fastest setting per size
 class in ``tile_cache.json`` next to this file.  For a batch (one shared B and row width) it
@@ -33,10 +34,13 @@ def size_class(sc) -> str:
 
 
 def default_candidates():
-    return [(b, cpl, 0) for b in (4, 6, 8, 10, 12, 14, 16) for cpl in (2, 4)]
+    """(block_steps, cols_per_lane, height) triples; height 0 = the planner's choice.  The
+    explicit heights keep two tiles resident per compute unit (LDS) at either row width."""
+    return ([(b, 2, h) for b in (6, 8, 10, 12, 14, 16) for h in (0, 110, 130, 150)] +
+            [(b, 4, h) for b in (6, 8, 12, 16) for h in (0, 70)])
 
 
-def _time_single(sc, block, cpl, height, launches):
+def _time_single(sc, block, cpl, height, steps):
     trial = copy.copy(sc)
     trial.tile = (cpl, height)
     sim = B.Simulation(trial, block_steps=block)
@@ -47,19 +51,21 @@ def _time_single(sc, block, cpl, height, launches):
     sim.step(block)                      # warm-up launch
     sim.synchronize()
     t0 = time.perf_counter()
-    sim.step(block * launches)
+    sim.step(steps)
     sim.synchronize()
-    dt = (time.perf_counter() - t0) / (block * launches)
+    dt = (time.perf_counter() - t0) / steps
     sim.close()
     return dt, tiling
 
 
-def tune(sc, candidates=None, launches=12, verbose=False) -> dict:
-    """Time every candidate (block_steps, cols_per_lane, height; 0 = planner's height) and
-    return {"best": (block, cpl, height), "seconds_per_step": ..., "trials": [...]}."""
+def tune(sc, candidates=None, steps=None, verbose=False) -> dict:
+    """Time every candidate (block_steps, cols_per_lane, height; 0 = planner's height) over
+    `steps` steps (default: the scenario's run length) and return
+    {"best": (block, cpl, height), "seconds_per_step": ..., "trials": [...]}."""
+    steps = int(steps or getattr(sc, "n_steps", 0) or 2000)
     trials = []
     for block, cpl, height in candidates or default_candidates():
-        dt, tiling = _time_single(sc, block, cpl, height, launches)
+        dt, tiling = _time_single(sc, block, cpl, height, steps)
         trials.append({"block_steps": block, "cols_per_lane": cpl, "height": tiling["height"],
                        "seconds_per_step": dt})
         if verbose:

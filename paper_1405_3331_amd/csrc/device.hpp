@@ -141,6 +141,7 @@ struct ConeRules {
     float inv_dx, half_inv_dx;
     float Lx, Ly, Lz;            // domain extent n_a * dx
     float step_len, gain, max_turn, sigma;
+    float tan_max;               // tan(max_turn) when max_turn <= kSmallCap, else 0
     float sign0, sign1;          // species weights in g
     int n_species;
     NoiseKey key;
@@ -246,6 +247,36 @@ struct GridContact {
     __device__ int find(float x, float y, float z) const { return contact_target<dim>(*tg, x, y, z); }
 };
 
+// Caps up to this angle take the small-angle path of capped_turn (tan(0.19) < 0.2).
+constexpr float kSmallCap = 0.19f;
+
+// The capped turn toward h + gain*g: atan2(cross, along) clamped to +-max_turn, with
+// cross = gain (h x g) and along = 1 + gain (h . g) (cross = -0 already replaced by +0).
+// For a small cap the clamp is decided first: the angle exceeds the cap exactly when
+// along <= 0 or |cross| >= along tan(max_turn); otherwise t = cross / along is below
+// tan(max_turn) < 0.2 and atan(t) is its Taylor series to t^11 (truncation below 2e-9 t,
+// under FP32 rounding).  *capped tells whether the clamp was applied.
+__device__ __forceinline__ float capped_turn(const ConeRules& r, float cross, float along,
+                                             bool* capped) {
+    if (r.tan_max > 0.0f) {
+        if (along > 0.0f && fabsf(cross) < along * r.tan_max) {
+            *capped = false;
+            const float t = cross / along;
+            const float t2 = t * t;
+            float p = fmaf(t2, -1.0f / 11.0f, 1.0f / 9.0f);
+            p = fmaf(t2, p, -1.0f / 7.0f);
+            p = fmaf(t2, p, 1.0f / 5.0f);
+            p = fmaf(t2, p, -1.0f / 3.0f);
+            return fmaf(t * t2, p, t);
+        }
+        *capped = true;
+        return cross >= 0.0f ? r.max_turn : -r.max_turn;
+    }
+    const float turn = atan2f(cross, along);
+    *capped = turn > r.max_turn || turn < -r.max_turn;
+    return fminf(fmaxf(turn, -r.max_turn), r.max_turn);
+}
+
 // One step of an active 2D cone: turn toward h + gain*g (capped), noise, advance, exit,
 // contact.  `step` is the number of completed steps n before this one.  `contact` finds
 // the nearest target in range (GridContact, or a list staged in LDS).  (s, c) carry
@@ -259,8 +290,8 @@ __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, 
     float cross = r.gain * (c * gy - s * gx);
     const float along = 1.0f + r.gain * (c * gx + s * gy);
     if (cross == 0.0f) cross = 0.0f;   // -0 -> +0: an anti-parallel pull turns by +cap
-    float turn = atan2f(cross, along);
-    turn = fminf(fmaxf(turn, -r.max_turn), r.max_turn);
+    bool capped;
+    const float turn = capped_turn(r, cross, along, &capped);
     float z[1];
     normals<1>(r.key, id, step, z);
     float th = theta + turn;

@@ -36,8 +36,10 @@ struct ConeArrays {
 
 // One step without temporal blocking: stencil of every species (HBM in -> HBM out), then
 // sources, then one thread per cone.  `in`/`out` index species.
+// start/stop (may be null): events the launch itself records around the stencil kernel.
 hipError_t launch_field_plain(int dim, int nx, int ny, int nz, const float* in, float* out,
-                              StencilCoef coef, hipStream_t stream);
+                              StencilCoef coef, hipStream_t stream,
+                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_sources(float* field, SourceList src, hipStream_t stream);
 hipError_t launch_cones_plain(int dim, const ConeRules& rules, const float* f0,
                               const float* f1, ConeArrays cones, uint32_t step,

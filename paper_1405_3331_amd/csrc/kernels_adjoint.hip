@@ -125,9 +125,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_cone_adjoint2d(
     float cross = r.gain * (c * gy - s * gx);
     const float along = 1.0f + r.gain * (c * gx + s * gy);
     if (cross == 0.0f) cross = 0.0f;
-    float turn = atan2f(cross, along);
-    const bool capped = turn > r.max_turn || turn < -r.max_turn;
-    turn = fminf(fmaxf(turn, -r.max_turn), r.max_turn);
+    bool capped;
+    const float turn = capped_turn(r, cross, along, &capped);
     float z[1];
     normals<1>(r.key, (uint32_t)i, step, z);
     float thn = th + turn;

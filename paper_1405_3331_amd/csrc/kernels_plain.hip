@@ -4,6 +4,8 @@
 // 8 algorithmic bytes per cell-update (one FP32 read, one FP32 write), the HBM-bound
 // baseline the tiled kernel improves on.  Cones run one thread each, in the caller's order,
 // against the just-updated field.
+#include <hip/hip_ext.h>
+
 #include "internal.hpp"
 
 namespace cuesim {
@@ -181,16 +183,19 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_final(const double* __res
 }  // namespace
 
 hipError_t launch_field_plain(int dim, int nx, int ny, int nz, const float* in, float* out,
-                              StencilCoef coef, hipStream_t stream) {
+                              StencilCoef coef, hipStream_t stream, hipEvent_t start,
+                              hipEvent_t stop) {
     const int bx = (nx + kRowThreads - 1) / kRowThreads;
     if (dim == 2)
-        hipLaunchKernelGGL(k_field2d, dim3(bx, ny), dim3(kRowThreads), 0, stream, in, out, nx,
-                           ny, coef);
+        hipExtLaunchKernelGGL(k_field2d, dim3(bx, ny), dim3(kRowThreads), 0, stream, start,
+                              stop, 0, in, out, nx, ny, coef);
     else
-        hipLaunchKernelGGL(k_field3d_stream,
-                           dim3((nx + kStreamX - 1) / kStreamX, (ny + kStreamY - 1) / kStreamY,
-                                (nz + kStreamZ - 1) / kStreamZ),
-                           dim3(kStreamX * kStreamY), 0, stream, in, out, nx, ny, nz, coef);
+        hipExtLaunchKernelGGL(k_field3d_stream,
+                              dim3((nx + kStreamX - 1) / kStreamX,
+                                   (ny + kStreamY - 1) / kStreamY,
+                                   (nz + kStreamZ - 1) / kStreamZ),
+                              dim3(kStreamX * kStreamY), 0, stream, start, stop, 0, in, out,
+                              nx, ny, nz, coef);
     return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@
 //
 // HBM traffic per launch: the tile with its halo is read once and the core written once,
 // instead of B reads and B writes of every cell.
+#include <hip/hip_ext.h>
+
 #include "tiled.hpp"
 
 #include <algorithm>
@@ -1014,7 +1016,8 @@ hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cone
     return hipSuccess;
 }
 
-hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream) {
+hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream,
+                        hipEvent_t start, hipEvent_t stop) {
     const TiledArgs2D* table = st.table;
     int4* items = st.items;
     const int2* base = st.base;
@@ -1023,9 +1026,9 @@ hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStr
     LaunchState* ls = st.launch;
     int persistent = 0;
     void* args[] = {&table, &items, &base, &n_base, &item_cap, &steps, &ls, &persistent};
-    const hipError_t e = hipLaunchKernel(kernel_for(plan.n_species, plan.cpl),
-                                         dim3(item_cap), dim3(kThreads), args,
-                                         plan.lds_bytes, stream);
+    const hipError_t e = hipExtLaunchKernel(kernel_for(plan.n_species, plan.cpl),
+                                            dim3(item_cap), dim3(kThreads), args,
+                                            plan.lds_bytes, stream, start, stop, 0);
     if (e == hipSuccess) st.cur ^= 1;
     return e;
 }

@@ -387,22 +387,15 @@ sim_status unbucket(sim_handle* h) {
     return SIM_OK;
 }
 
-sim_status record_start(sim_handle* h, hipEvent_t* start) {
-    *start = nullptr;
+// A start/stop event pair for the next timed launch (both null when timing is off).  The
+// launch records them itself (hipExtLaunchKernel: the dispatch packet carries the
+// timestamps), so timing adds no commands between launches.
+sim_status timing_events(sim_handle* h, hipEvent_t* start, hipEvent_t* stop) {
+    *start = *stop = nullptr;
     if (!h->timing) return SIM_OK;
-    hipEvent_t a;
-    HIP_TRY(h, hipEventCreate(&a));
-    HIP_TRY(h, hipEventRecord(a, h->stream));
-    *start = a;
-    return SIM_OK;
-}
-
-sim_status record_stop(sim_handle* h, hipEvent_t start) {
-    if (!h->timing || !start) return SIM_OK;
-    hipEvent_t b;
-    HIP_TRY(h, hipEventCreate(&b));
-    HIP_TRY(h, hipEventRecord(b, h->stream));
-    h->events.emplace_back(start, b);
+    HIP_TRY(h, hipEventCreate(start));
+    HIP_TRY(h, hipEventCreate(stop));
+    h->events.emplace_back(*start, *stop);
     return SIM_OK;
 }
 
@@ -423,12 +416,11 @@ sim_status plain_step(sim_handle* h) {
     for (int s = 0; s < h->n_species; ++s) {
         const float* in = h->field[s][h->cur[s]];
         float* out = h->field[s][h->cur[s] ^ 1];
-        hipEvent_t t0;
-        sim_status st = record_start(h, &t0);
+        hipEvent_t t0, t1;
+        sim_status st = timing_events(h, &t0, &t1);
         if (st != SIM_OK) return st;
-        HIP_TRY(h, launch_field_plain(h->dim, h->nx, h->ny, h->nz, in, out, h->coef[s], h->stream));
-        st = record_stop(h, t0);
-        if (st != SIM_OK) return st;
+        HIP_TRY(h, launch_field_plain(h->dim, h->nx, h->ny, h->nz, in, out, h->coef[s], h->stream,
+                                      t0, t1));
         HIP_TRY(h, launch_sources(out, SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
                                   h->stream));
         h->cur[s] ^= 1;
@@ -447,12 +439,10 @@ sim_status tiled_steps(sim_handle* h, int64_t n) {
     }
     while (n > 0) {
         const int b = (int)std::min<int64_t>(n, h->plan.block_steps);
-        hipEvent_t t0;
-        sim_status st = record_start(h, &t0);
+        hipEvent_t t0, t1;
+        sim_status st = timing_events(h, &t0, &t1);
         if (st != SIM_OK) return st;
-        HIP_TRY(h, tiled_launch(h->plan, h->tiled, b, h->stream));
-        st = record_stop(h, t0);
-        if (st != SIM_OK) return st;
+        HIP_TRY(h, tiled_launch(h->plan, h->tiled, b, h->stream, t0, t1));
         for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
         h->step += b;
         n -= b;
@@ -510,6 +500,7 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
     R.step_len = (float)p->step_len;
     R.gain = (float)p->turn_gain;
     R.max_turn = (float)p->max_turn;
+    R.tan_max = p->max_turn <= kSmallCap ? (float)std::tan(p->max_turn) : 0.0f;
     R.sigma = (float)p->noise_sigma;
     R.sign0 = (float)p->sign[0];
     R.sign1 = p->n_species > 1 ? (float)p->sign[1] : 0.0f;

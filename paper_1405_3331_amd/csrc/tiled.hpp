@@ -82,7 +82,9 @@ hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cone
                           hipStream_t stream);
 // Advance `steps` (<= plan.block_steps) steps in one launch; flips st.cur like the device
 // parity.
-hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream);
+// start/stop (may be null): events the launch records around the kernel (timing).
+hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream,
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 // Size in bytes of one argument-table entry (for batching several simulations).
 size_t tiled_table_entry_bytes();
