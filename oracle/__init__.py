@@ -37,6 +37,8 @@ class _Params(C.Structure):
         ("noise_sigma", C.c_double),
         ("seed", C.c_uint64), ("sim_index", C.c_uint32),
         ("noise_sign", C.c_double), ("flag_tol", C.c_double),
+        ("turn_law", C.c_int32), ("snr_scale", C.c_double), ("cone_width", C.c_double),
+        ("kd", C.c_double), ("c_min", C.c_double), ("c_max", C.c_double),
     ]
 
 
@@ -178,6 +180,10 @@ class OracleSim:
         p.seed, p.sim_index = sc.seed, sc.sim_index
         p.noise_sign = noise_sign
         p.flag_tol = 1e-4 * sc.side if flag_tol is None else flag_tol
+        law = getattr(sc, "snr_law", None)   # (snr_scale, cone_width, kd, c_min, c_max)
+        if law is not None:
+            p.turn_law = 1
+            p.snr_scale, p.cone_width, p.kd, p.c_min, p.c_max = (float(v) for v in law)
         self.params = p
         self.flag_tol = p.flag_tol
 

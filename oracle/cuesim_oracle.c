@@ -177,13 +177,16 @@ static double centre_gradient(const oracle_params* p, const double* c, const int
     return (neighbour(p, c, idx, a, +1) - neighbour(p, c, idx, a, -1)) / (2.0 * p->dx);
 }
 
-void oracle_sample_gradient(const oracle_params* p, const double* field, const double* point,
-                            double g[3])
+/* The 2^dim cell centres around point p: the lower corner `base` and the fractions along
+ * each axis.  Cell centres sit at (i + 1/2) dx: u is the tip in units of cell-centre
+ * spacing, clamped to the outermost centres. */
+static void tip_corners(const oracle_params* p, const double* point, int base[3], double frac[3])
 {
-    int base[3] = {0, 0, 0};
-    double frac[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        base[a] = 0;
+        frac[a] = 0.0;
+    }
     for (int a = 0; a < p->dim; ++a) {
-        /* Cell centres sit at (i + 1/2) dx: u is the tip in units of cell-centre spacing. */
         int n = axis_size(p, a);
         double u = point[a] / p->dx - 0.5;
         if (u < 0.0) u = 0.0;
@@ -193,16 +196,32 @@ void oracle_sample_gradient(const oracle_params* p, const double* field, const d
         base[a] = i0;
         frac[a] = u - (double)i0;
     }
+}
+
+/* Cell and multilinear weight of one corner (bit a of `corner` = upper along axis a). */
+static double corner_cell(const oracle_params* p, const int base[3], const double frac[3],
+                          int corner, int idx[3])
+{
+    double weight = 1.0;
+    idx[0] = idx[1] = idx[2] = 0;
+    for (int a = 0; a < p->dim; ++a) {
+        int upper = (corner >> a) & 1;
+        idx[a] = base[a] + upper;
+        weight *= upper ? frac[a] : (1.0 - frac[a]);
+    }
+    return weight;
+}
+
+void oracle_sample_gradient(const oracle_params* p, const double* field, const double* point,
+                            double g[3])
+{
+    int base[3];
+    double frac[3];
+    tip_corners(p, point, base, frac);
     g[0] = g[1] = g[2] = 0.0;
-    int corners = 1 << p->dim;
-    for (int corner = 0; corner < corners; ++corner) {
-        int idx[3] = {0, 0, 0};
-        double weight = 1.0;
-        for (int a = 0; a < p->dim; ++a) {
-            int upper = (corner >> a) & 1;
-            idx[a] = base[a] + upper;
-            weight *= upper ? frac[a] : (1.0 - frac[a]);
-        }
+    for (int corner = 0; corner < (1 << p->dim); ++corner) {
+        int idx[3];
+        double weight = corner_cell(p, base, frac, corner, idx);
         for (int a = 0; a < p->dim; ++a)
             g[a] += weight * centre_gradient(p, field, idx, a);
     }
@@ -249,6 +268,44 @@ static void turn_3d(const oracle_params* p, double h[3], const double g[3], int*
         h[a] = c * h[a] + s * perp[a] / perp_norm;
 }
 
+/* Interpolated concentration of one field at point p: the multilinear interpolation of
+ * cell-centre values with the same corners and weights as the gradient sample. */
+static double sample_value(const oracle_params* p, const double* field, const double* point)
+{
+    int base[3];
+    double frac[3];
+    tip_corners(p, point, base, frac);
+    double v = 0.0;
+    for (int corner = 0; corner < (1 << p->dim); ++corner) {
+        int idx[3];
+        double weight = corner_cell(p, base, frac, corner, idx);
+        v += weight * field[cell_index(p, idx)];
+    }
+    return v;
+}
+
+/* C2 under the SNR law (Sec. 3.5, Eq. 5; 2D): the growth cone compares the cue across its
+ * width and turns by the fixed angle to the right (clockwise) when a normal deviate with
+ * mean SNR and unit variance is positive, else to the left.  Outside the detection window
+ * [c_min, c_max], or with no gradient, it does not turn.  sin(theta - theta_g) |g| equals
+ * sin(theta) g_x - cos(theta) g_y, so theta_g itself is never formed. */
+static double turn_snr_2d(const oracle_params* p, double theta, const double g[3], double c,
+                          double z0, int* ambiguous)
+{
+    const double tol = 1e-4;
+    if (fabs(c - p->c_min) <= tol * p->c_min || fabs(c - p->c_max) <= tol * p->c_max)
+        *ambiguous = 1;
+    if (c < p->c_min || c > p->c_max || (g[0] == 0.0 && g[1] == 0.0))
+        return theta;
+    double gamma = c / p->kd;
+    double side = sin(theta) * g[0] - cos(theta) * g[1];      /* |g| sin(theta - theta_g) */
+    double snr = p->snr_scale * (p->cone_width / c) * sqrt(gamma / pow(1.0 + gamma, 3.0)) * side;
+    double x = snr + z0;
+    if (fabs(x) <= tol)
+        *ambiguous = 1;
+    return x > 0.0 ? theta - p->max_turn : theta + p->max_turn;
+}
+
 /* C3 (3D): tangent-plane Gaussian rotation of h, then renormalisation. */
 static void noise_3d(const oracle_params* p, double h[3], const double z[4])
 {
@@ -291,8 +348,15 @@ static void step_one_cone(const oracle_params* p, oracle_state* s, int i,
         z[q] *= p->noise_sign;
     double h[3];
     if (dim == 2) {
-        double theta = turn_2d(p, s->dir[i], g, &ambiguous);
-        theta += p->noise_sigma * z[0];
+        double theta;
+        if (p->turn_law == 1) {
+            double c = sample_value(p, fields[0], pos);
+            theta = turn_snr_2d(p, s->dir[i], g, c, z[0], &ambiguous);
+            theta += p->noise_sigma * z[1];
+        } else {
+            theta = turn_2d(p, s->dir[i], g, &ambiguous);
+            theta += p->noise_sigma * z[0];
+        }
         theta -= 2.0 * ORACLE_PI * floor((theta + ORACLE_PI) / (2.0 * ORACLE_PI));
         s->dir[i] = theta;
         h[0] = cos(theta);

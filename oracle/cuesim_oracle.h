@@ -39,6 +39,14 @@ typedef struct oracle_params {
     uint32_t sim_index;
     double noise_sign;           /* +1 normally; -1 negates every normal deviate (mirror test) */
     double flag_tol;             /* near-tie margin tau for the flag record */
+    /* Turn law: 0 = vector addition (the default), 1 = the SNR decision of Sec. 3.5, Eq. 5
+     * (2D): inside the detection window c_min <= c <= c_max (c: species 0 at the tip), turn
+     * by max_turn to the right when SNR + Z0 > 0, else to the left, where
+     * SNR = snr_scale * mu * sqrt(gamma / (1 + gamma)^3) * sin(theta - theta_g),
+     * gamma = c / kd, mu = cone_width * |g| / c, theta_g the direction of g; the angular
+     * noise is then noise_sigma * Z1. */
+    int32_t turn_law;
+    double snr_scale, cone_width, kd, c_min, c_max;
 } oracle_params;
 
 typedef struct oracle_state {

@@ -84,6 +84,9 @@ class Scenario:
     sim_index: int
     n_steps: int
     init_field: Optional[List[np.ndarray]] = None
+    # SNR turn law of Sec. 3.5, Eq. 5 (2D) instead of vector addition: (snr_scale,
+    # cone_width, kd, c_min, c_max); None = vector addition
+    snr_law: Optional[tuple] = None
 
     @property
     def shape(self):

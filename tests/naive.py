@@ -140,6 +140,24 @@ class NaiveSim:
                 g[a] += w * d
         return g
 
+    def _value_at(self, c, p):
+        """Multilinear interpolation of cell-centre values at p (same corners as _gradient)."""
+        base, frac = [], []
+        for a in range(self.dim):
+            u = min(max(p[a] / self.sc.dx - 0.5, 0.0), float(self.n[a] - 1))
+            i0 = min(int(math.floor(u)), self.n[a] - 2)
+            base.append(i0)
+            frac.append(u - i0)
+        v = 0.0
+        for corner in range(2 ** self.dim):
+            idx, w = [], 1.0
+            for a in range(self.dim):
+                up = (corner >> a) & 1
+                idx.append(base[a] + up)
+                w *= frac[a] if up else 1.0 - frac[a]
+            v += w * c[self._lin(idx)]
+        return v
+
     def step(self, n_steps: int = 1):
         sc = self.sc
         for _ in range(n_steps):
@@ -159,7 +177,22 @@ class NaiveSim:
             gs = self._gradient(self.fields[s], p)
             for a in range(self.dim):
                 g[a] += spc.sign * gs[a]
-        if self.dim == 2:
+        if self.dim == 2 and getattr(sc, "snr_law", None) is not None:
+            # Sec. 3.5, Eq. 5: turn right when N(SNR, 1) > 0, inside the detection window
+            A, width, kd, cmin, cmax = sc.snr_law
+            th = self.dir[i]
+            c = self._value_at(self.fields[0], p)
+            if cmin <= c <= cmax and (g[0] != 0.0 or g[1] != 0.0):
+                theta_g = math.atan2(g[1], g[0])
+                mu = width * math.hypot(g[0], g[1]) / c
+                gamma = c / kd
+                snr = A * mu * math.sqrt(gamma / (1.0 + gamma) ** 3) * math.sin(th - theta_g)
+                th = th - sc.max_turn if snr + z[0] > 0.0 else th + sc.max_turn
+            th = th + sc.noise_sigma * z[1]
+            th = th - 2.0 * math.pi * math.floor((th + math.pi) / (2.0 * math.pi))
+            self.dir[i] = th
+            h = [math.cos(th), math.sin(th)]
+        elif self.dim == 2:
             th = self.dir[i]
             hx, hy = math.cos(th), math.sin(th)
             cross = sc.turn_gain * (hx * g[1] - hy * g[0])

@@ -739,6 +739,59 @@ def pin_connectivity(lib_path=LIB):
         assert oracle.bfs_levels(row, edges, root, lib=lib).tolist() == want.tolist(), trial
 
 
+# ---------------------------------------------------------------------------------------
+# SNR turn law (Sec. 3.5, Eq. 5).  In a frozen linear field (D = k = 0, no sources) every
+# cone placed at the same interior point with the same heading sees the same concentration
+# c and gradient (G, 0), so SNR is a closed form and each cone turns right (by -max_turn)
+# with probability Phi(SNR), independently (its own Philox stream).  Outside the detection
+# window no cone turns.
+# ---------------------------------------------------------------------------------------
+def _snr_case(theta0, law, n_cones=20000, c0=0.4, G=0.02, x0=20.3, y0=15.6):
+    sc = make_scenario("snr pin", 2, (48, 32), 1.0, 0.2, ((0.0, 0.0, 1.0),), 0, (1.0, 1.0),
+                       n_cones, 0, 1.0, 0.1, 10.0, math.pi / 30.0, 0.0, seed=7)
+    xs = (np.arange(sc.nx) + 0.5) * sc.dx
+    field = np.tile(c0 + G * xs, (sc.ny, 1))
+    sc.init_field = [np.asarray(field, dtype=np.float32).astype(np.float64)]
+    sc.cone_pos = np.tile([x0, y0], (n_cones, 1)).astype(np.float64)
+    sc.cone_dir = np.full(n_cones, theta0)
+    sc.snr_law = law
+    return sc, c0 + G * x0, G   # interpolation of a linear field is exact
+
+
+def pin_snr_law(lib_path=LIB):
+    law = (40.0, 1.5, 0.6, 0.05, 5.0)     # snr_scale, cone_width, kd, c_min, c_max
+    A, w, kd, cmin, cmax = law
+    for theta0 in (math.pi / 3, -math.pi / 4, 0.0, 2.5):
+        sc, c, G = _snr_case(theta0, law)
+        gamma = c / kd
+        snr = A * (w / c) * math.sqrt(gamma / (1.0 + gamma) ** 3) * (math.sin(theta0) * G)
+        o = OracleSim(sc, lib_path=lib_path).step(1)
+        d = np.angle(np.exp(1j * (o.dir - theta0)))
+        assert np.all(np.abs(np.abs(d) - sc.max_turn) < 1e-12), "every cone turns by the cap"
+        right = float(np.mean(d < 0))
+        p = float(scipy.stats.norm.cdf(snr))
+        sd = math.sqrt(max(p * (1 - p), 1e-12) / sc.n_cones)
+        assert abs(right - p) <= 5 * sd + 1e-9, (theta0, right, p, snr)
+    # below the window: no turn at all
+    sc, c, G = _snr_case(1.0, (40.0, 1.5, 0.6, 2.0, 5.0), n_cones=500)
+    o = OracleSim(sc, lib_path=lib_path).step(3)
+    assert np.all(np.abs(o.dir - 1.0) < 1e-12)
+
+
+def pin_snr_bruteforce(lib_path=LIB):
+    """The SNR law's whole step against the naive implementation (its deviates from
+    PyTorch's Philox): angular noise included, two species, 30 steps."""
+    import naive
+    sc = make_scenario("snr brute force", 2, (8, 6), 1.0, 0.2,
+                       ((1.0, 0.01, 1.0), (0.5, 0.02, -1.0)), 3, (5.0, 20.0), 4, 3, 1.0, 0.2,
+                       10.0, math.pi / 30.0, 0.3, seed=9)
+    sc.snr_law = (30.0, 1.0, 2.0, 0.05, 50.0)
+    a = OracleSim(sc, lib_path=lib_path).step(30)
+    b = naive.NaiveSim(sc).step(30)
+    assert np.abs(a.pos - np.array(b.pos)).max() <= 1e-10 * sc.side
+    assert np.abs(np.angle(np.exp(1j * (a.dir - np.array(b.dir))))).max() <= 1e-10
+
+
 ALL_PINS = {
     "mass2d": lambda p: pin_mass_recursion(p, 2),
     "mass3d": lambda p: pin_mass_recursion(p, 3),
@@ -761,4 +814,6 @@ ALL_PINS = {
     "adjoint": lambda p: pin_adjoint_fd(p, 1, 40),
     "adjoint2": lambda p: pin_adjoint_fd(p, 2, 40),
     "graph": pin_connectivity,
+    "snr": pin_snr_law,
+    "snr_noise": pin_snr_bruteforce,
 }

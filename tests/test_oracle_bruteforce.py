@@ -75,3 +75,11 @@ def test_bruteforce_hypothesis(seed, dim, two, gain, sigma):
     n = (7, 5) if dim == 2 else (4, 4, 3)
     sc = _tiny(dim, n, species, 3, 3, seed=seed, gain=gain, sigma=sigma)
     _compare(sc, 20)
+
+
+@pytest.mark.parametrize("seed", [2, 9])
+def test_bruteforce_snr_law(seed):
+    sc = _tiny(2, (8, 6), ((1.0, 0.01, 1.0), (0.5, 0.02, -1.0)), 4, 3, seed=seed, sigma=0.05)
+    sc.snr_law = (30.0, 1.0, 2.0, 0.05, 50.0)
+    a = _compare(sc, 40)
+    assert np.ptp(a.pos) > 0.5

@@ -67,6 +67,15 @@ MUTANTS = [
      ["adjoint"]),
     ("adjoint_source_units", "dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]] / vol;",
      "dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]];", ["adjoint"]),
+    ("snr_turn_left", "return x > 0.0 ? theta - p->max_turn : theta + p->max_turn;",
+     "return x > 0.0 ? theta + p->max_turn : theta - p->max_turn;", ["snr"]),
+    ("snr_no_width", "double snr = p->snr_scale * (p->cone_width / c) *",
+     "double snr = p->snr_scale * (1.0 / c) *", ["snr"]),
+    ("snr_gamma_power", "sqrt(gamma / pow(1.0 + gamma, 3.0))", "sqrt(gamma / pow(1.0 + gamma, 2.0))",
+     ["snr"]),
+    ("snr_window_ignored", "if (c < p->c_min || c > p->c_max ||", "if (", ["snr"]),
+    ("snr_noise_word", "theta += p->noise_sigma * z[1];", "theta += p->noise_sigma * z[0];",
+     ["snr_noise"]),
     ("bfs_level_step", "level[u] = level[v] + 1;", "level[u] = level[v] + 2;", ["graph"]),
     ("adjacency_by_target_owner", "row_start[cone_owner[i] + 1] += 1;",
      "row_start[target_owner[target[i]] + 1] += 1;", ["graph"]),

@@ -103,3 +103,7 @@ def test_adjoint_zero_without_coupling():
 
 def test_connectivity_and_bfs():
     pins.pin_connectivity()
+
+
+def test_snr_turn_law():
+    pins.pin_snr_law()
