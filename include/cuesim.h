@@ -116,7 +116,22 @@ typedef struct sim_params {
                                           0 = chosen by the library's planner */
     int32_t tile_height;               /* loaded tile height in rows; 0 = planner's choice.
                                           A hint that does not fit is ignored */
+    /* Turn law (2D): SIM_TURN_VECTOR (0) is step 4 above.  SIM_TURN_SNR (1) is the
+     * decision of Sec. 3.5, Eq. 5: with c the concentration of species 0 at the tip
+     * (interpolated from the cell centres like the gradient) inside the detection window
+     * [c_min, c_max] and g != 0, the heading turns by max_turn to the right (clockwise)
+     * when SNR + Z0 > 0 and to the left otherwise, where
+     *   SNR = snr_scale * mu * sqrt(gamma / (1 + gamma)^3) * sin(theta - theta_g),
+     *   gamma = c / kd, mu = cone_width * |g| / c, theta_g = the direction of g;
+     * outside the window it does not turn.  The angular noise is then noise_sigma * Z1
+     * (Z0 decided the turn).  turn_gain is unused.  Requires dim = 2, kd > 0,
+     * 0 < c_min <= c_max, cone_width >= 0, all finite.  The trajectory-loss gradient
+     * (sim_adjoint_run) is defined for SIM_TURN_VECTOR only. */
+    int32_t turn_law;
+    double snr_scale, cone_width, kd, c_min, c_max;
 } sim_params;
+
+enum { SIM_TURN_VECTOR = 0, SIM_TURN_SNR = 1 };
 
 typedef struct sim_handle sim_handle;
 

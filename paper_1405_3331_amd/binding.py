@@ -22,6 +22,7 @@ SIM_OK, SIM_EINVAL, SIM_ECFL, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE, SIM_ESTATE = 
 STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ECFL", -3: "SIM_ENOMEM",
                 -4: "SIM_EDEVICE", -5: "SIM_ERANGE", -6: "SIM_ESTATE"}
 ACTIVE, CONTACT, EXITED = 0, 1, 2
+SIM_TURN_VECTOR, SIM_TURN_SNR = 0, 1
 
 FIELD, CONE_POS, CONE_DIR, CONE_STATUS, CONE_TARGET, CONE_EVENT_STEP, EVENTS, MASS, STEP, \
     COUNTS, KERNEL_TIME, TILING = range(12)
@@ -58,6 +59,8 @@ class SimParams(C.Structure):
         ("noise_sigma", C.c_double),
         ("seed", C.c_uint64), ("sim_index", C.c_uint32), ("block_steps", C.c_int32),
         ("tile_cols_per_lane", C.c_int32), ("tile_height", C.c_int32),
+        ("turn_law", C.c_int32), ("snr_scale", C.c_double), ("cone_width", C.c_double),
+        ("kd", C.c_double), ("c_min", C.c_double), ("c_max", C.c_double),
     ]
 
 
@@ -161,6 +164,10 @@ def make_params(sc, block_steps: int = 0):
     p.block_steps = block_steps
     tile = getattr(sc, "tile", None) or (0, 0)   # (cols per lane, height) hint, 0 = planner
     p.tile_cols_per_lane, p.tile_height = int(tile[0]), int(tile[1])
+    law = getattr(sc, "snr_law", None)   # (snr_scale, cone_width, kd, c_min, c_max)
+    if law is not None:
+        p.turn_law = SIM_TURN_SNR
+        p.snr_scale, p.cone_width, p.kd, p.c_min, p.c_max = (float(v) for v in law)
     return p, keep
 
 

@@ -142,6 +142,9 @@ struct ConeRules {
     float Lx, Ly, Lz;            // domain extent n_a * dx
     float step_len, gain, max_turn, sigma;
     float tan_max;               // tan(max_turn) when max_turn <= kSmallCap, else 0
+    int turn_law;                // 0 vector addition, 1 SNR decision (2D)
+    float snr_coef;              // SNR law: snr_scale * cone_width
+    float inv_kd, c_min, c_max;  // SNR law: 1 / kd and the detection window
     float sign0, sign1;          // species weights in g
     int n_species;
     NoiseKey key;
@@ -163,7 +166,7 @@ __device__ __forceinline__ void corner(float p, float inv_dx, int n, int& i0, fl
 // Interpolated central-difference gradient of one species at (x, y).
 template <class F>
 __device__ __forceinline__ void gradient_2d(const F& f, const ConeRules& r, float x, float y,
-                                            float& gx, float& gy) {
+                                            float& gx, float& gy, float* value = nullptr) {
     int i0, j0;
     float fx, fy;
     corner(x, r.inv_dx, r.nx, i0, fx);
@@ -185,6 +188,8 @@ __device__ __forceinline__ void gradient_2d(const F& f, const ConeRules& r, floa
     const float w01 = (1.0f - fx) * fy, w11 = fx * fy;
     gx = w00 * gx00 + w10 * gx10 + w01 * gx01 + w11 * gx11;
     gy = w00 * gy00 + w10 * gy10 + w01 * gy01 + w11 * gy11;
+    // the interpolated concentration itself, from the same corners and weights
+    if (value) *value = w00 * a1 + w10 * a2 + w01 * b1 + w11 * b2;
 }
 
 template <class F>
@@ -277,25 +282,48 @@ __device__ __forceinline__ float capped_turn(const ConeRules& r, float cross, fl
     return fminf(fmaxf(turn, -r.max_turn), r.max_turn);
 }
 
-// One step of an active 2D cone: turn toward h + gain*g (capped), noise, advance, exit,
-// contact.  `step` is the number of completed steps n before this one.  `contact` finds
-// the nearest target in range (GridContact, or a list staged in LDS).  (s, c) carry
-// sincosf(theta) in and sincosf of the new heading out, so a caller stepping a cone
-// repeatedly evaluates it once per step.
+// The SNR turn law (Sec. 3.5, Eq. 5): inside the detection window [c_min, c_max] of the
+// concentration c at the tip, turn by max_turn to the right (clockwise) when SNR + z0 > 0,
+// else to the left, with SNR = A w / c * sqrt(gamma / (1 + gamma)^3) * |g| sin(theta -
+// theta_g), gamma = c / kd; |g| sin(theta - theta_g) = sin(theta) g_x - cos(theta) g_y.
+// Outside the window, or with no gradient, no turn.
+__device__ __forceinline__ float snr_turn(const ConeRules& r, float s, float c, float gx,
+                                          float gy, float conc, float z0) {
+    if (!(conc >= r.c_min && conc <= r.c_max) || (gx == 0.0f && gy == 0.0f)) return 0.0f;
+    const float gamma = conc * r.inv_kd;
+    const float one = 1.0f + gamma;
+    const float snr = r.snr_coef / conc * sqrtf(gamma / (one * one * one)) * (s * gx - c * gy);
+    return snr + z0 > 0.0f ? -r.max_turn : r.max_turn;
+}
+
+// One step of an active 2D cone: turn toward h + gain*g (capped) -- or by the SNR law's
+// decision, which also needs the concentration `conc` of species 0 at the tip -- noise,
+// advance, exit, contact.  `step` is the number of completed steps n before this one.
+// `contact` finds the nearest target in range (GridContact, or a list staged in LDS).
+// (s, c) carry sincosf(theta) in and sincosf of the new heading out, so a caller stepping a
+// cone repeatedly evaluates it once per step.
 template <class Contact>
 __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, float gy,
-                                                  uint32_t id, uint32_t step, float& x,
-                                                  float& y, float& theta, float& s, float& c,
-                                                  const Contact& contact) {
-    float cross = r.gain * (c * gy - s * gx);
-    const float along = 1.0f + r.gain * (c * gx + s * gy);
-    if (cross == 0.0f) cross = 0.0f;   // -0 -> +0: an anti-parallel pull turns by +cap
-    bool capped;
-    const float turn = capped_turn(r, cross, along, &capped);
-    float z[1];
-    normals<1>(r.key, id, step, z);
-    float th = theta + turn;
-    th = th + r.sigma * z[0];
+                                                  float conc, uint32_t id, uint32_t step,
+                                                  float& x, float& y, float& theta, float& s,
+                                                  float& c, const Contact& contact) {
+    float th;
+    if (r.turn_law == 1) {
+        float z[2];
+        normals<2>(r.key, id, step, z);
+        th = theta + snr_turn(r, s, c, gx, gy, conc, z[0]);
+        th = th + r.sigma * z[1];
+    } else {
+        float cross = r.gain * (c * gy - s * gx);
+        const float along = 1.0f + r.gain * (c * gx + s * gy);
+        if (cross == 0.0f) cross = 0.0f;   // -0 -> +0: an anti-parallel pull turns by +cap
+        bool capped;
+        const float turn = capped_turn(r, cross, along, &capped);
+        float z[1];
+        normals<1>(r.key, id, step, z);
+        th = theta + turn;
+        th = th + r.sigma * z[0];
+    }
     const float two_pi = 6.28318530717958647692f;
     th = th - two_pi * floorf((th + 3.14159265358979323846f) * (1.0f / two_pi));
     theta = th;

@@ -87,8 +87,8 @@ __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __res
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= c.n || c.status[i] != kActive) return;
     float x = c.pos[2 * i], y = c.pos[2 * i + 1], th = c.dir[i];
-    float gx, gy;
-    gradient_2d(Global2D{f0, r.nx}, r, x, y, gx, gy);
+    float gx, gy, conc = 0.0f;
+    gradient_2d(Global2D{f0, r.nx}, r, x, y, gx, gy, r.turn_law == 1 ? &conc : nullptr);
     gx *= r.sign0;
     gy *= r.sign0;
     if (r.n_species > 1) {
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __res
     }
     float sn, cs;
     sincosf(th, &sn, &cs);
-    const ConeEvent ev = cone_step_2d(r, gx, gy, (uint32_t)i, step, x, y, th, sn, cs,
+    const ConeEvent ev = cone_step_2d(r, gx, gy, conc, (uint32_t)i, step, x, y, th, sn, cs,
                                       GridContact{&r.targets});
     c.pos[2 * i] = x;
     c.pos[2 * i + 1] = y;

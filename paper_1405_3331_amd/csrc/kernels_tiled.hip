@@ -300,13 +300,14 @@ struct TileContact {
 // LDS field (the only part that reads the field); the second turns, adds noise, advances
 // and tests exit and contact using g and registers only, so it may run while the next
 // sub-step already overwrites the field.
+// The sample is (g_x, g_y, concentration of species 0; the last only under the SNR law).
 template <int NS>
-__device__ __forceinline__ float2 tile_cone_gradient(const float4& st, const LdsField2D& f0,
+__device__ __forceinline__ float3 tile_cone_gradient(const float4& st, const LdsField2D& f0,
                                                      const LdsField2D& f1,
                                                      const ConeRules& rules) {
-    float gxv = 0.0f, gyv = 0.0f;
-    if (__float_as_int(st.w) < 0) return make_float2(gxv, gyv);
-    gradient_2d(f0, rules, st.x, st.y, gxv, gyv);
+    float gxv = 0.0f, gyv = 0.0f, conc = 0.0f;
+    if (__float_as_int(st.w) < 0) return make_float3(gxv, gyv, conc);
+    gradient_2d(f0, rules, st.x, st.y, gxv, gyv, rules.turn_law == 1 ? &conc : nullptr);
     gxv *= rules.sign0;
     gyv *= rules.sign0;
     if (NS > 1) {
@@ -315,12 +316,12 @@ __device__ __forceinline__ float2 tile_cone_gradient(const float4& st, const Lds
         gxv = fmaf(rules.sign1, hx, gxv);
         gyv = fmaf(rules.sign1, hy, gyv);
     }
-    return make_float2(gxv, gyv);
+    return make_float3(gxv, gyv, conc);
 }
 
 // Second part; a stopped cone has its final state written to the caller-order arrays and
 // the sign bit of its id set.
-__device__ __forceinline__ void tile_cone_advance(float4& st, float2& sc, float2 g,
+__device__ __forceinline__ void tile_cone_advance(float4& st, float2& sc, float3 g,
                                                   const ConeRules& rules, uint32_t step,
                                                   const TileContact& contact,
                                                   const ConeArrays& cones) {
@@ -328,7 +329,7 @@ __device__ __forceinline__ void tile_cone_advance(float4& st, float2& sc, float2
     if (id < 0) return;
     float x = st.x, y = st.y, th = st.z;
     const ConeEvent ev =
-        cone_step_2d(rules, g.x, g.y, (uint32_t)id, step, x, y, th, sc.x, sc.y, contact);
+        cone_step_2d(rules, g.x, g.y, g.z, (uint32_t)id, step, x, y, th, sc.x, sc.y, contact);
     if (ev.status != kActive) {
         cones.pos[2 * id] = x;
         cones.pos[2 * id + 1] = y;
@@ -512,7 +513,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
         //    overlapping the next sub-step's in-place stencil, which they no longer read.
         const uint32_t step = first_step + (uint32_t)b;
         if (n_cones > 0) {
-            float2 g[kConeSlots];
+            float3 g[kConeSlots];
 #pragma unroll
             for (int k = 0; k < kConeSlots; ++k) g[k] = tile_cone_gradient<NS>(mine[k], f0, f1, rules);
             __syncthreads();

@@ -277,6 +277,15 @@ sim_status validate(const sim_params* p) {
         return fail(nullptr, SIM_EINVAL, "tile_cols_per_lane must be 0, 2 or 4");
     if (p->tile_height < 0 || p->tile_height > 4096)
         return fail(nullptr, SIM_EINVAL, "tile_height must be in [0, 4096]");
+    if (p->turn_law != SIM_TURN_VECTOR && p->turn_law != SIM_TURN_SNR)
+        return fail(nullptr, SIM_EINVAL, "turn_law must be SIM_TURN_VECTOR or SIM_TURN_SNR");
+    if (p->turn_law == SIM_TURN_SNR &&
+        (p->dim != 2 || !finite(p->snr_scale) || !finite(p->cone_width) || p->cone_width < 0 ||
+         !finite(p->kd) || !(p->kd > 0) || !finite(p->c_min) || !finite(p->c_max) ||
+         !(p->c_min > 0) || p->c_max < p->c_min))
+        return fail(nullptr, SIM_EINVAL,
+                    "SNR turn law: 2D only; finite snr_scale, cone_width >= 0, kd > 0, "
+                    "0 < c_min <= c_max");
     return SIM_OK;
 }
 
@@ -500,6 +509,11 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
     R.step_len = (float)p->step_len;
     R.gain = (float)p->turn_gain;
     R.max_turn = (float)p->max_turn;
+    R.turn_law = p->turn_law;
+    R.snr_coef = (float)(p->snr_scale * p->cone_width);
+    R.inv_kd = p->turn_law == SIM_TURN_SNR ? (float)(1.0 / p->kd) : 0.0f;
+    R.c_min = (float)p->c_min;
+    R.c_max = (float)p->c_max;
     R.tan_max = p->max_turn <= kSmallCap ? (float)std::tan(p->max_turn) : 0.0f;
     R.sigma = (float)p->noise_sigma;
     R.sign0 = (float)p->sign[0];
@@ -905,6 +919,8 @@ sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_ev
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
     if (h->dim != 2) return fail(h, SIM_EINVAL, "the trajectory-loss gradient is 2D only");
+    if (h->rules.turn_law != SIM_TURN_VECTOR)
+        return fail(h, SIM_EINVAL, "the trajectory-loss gradient needs the vector turn law");
     if (n_steps < 0 || checkpoint_every < 1)
         return fail(h, SIM_EINVAL, "n_steps < 0 or checkpoint_every < 1");
     if (h->step + n_steps > 2147483647LL)
