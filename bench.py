@@ -294,17 +294,24 @@ def main():
     print(f"[bench] {sc.name}: {sc.n_cells} cells, {sc.n_cones} cones, "
           f"warmup {args.warmup}, timed {args.steps}, block_steps {block or 'default'}",
           file=sys.stderr, flush=True)
-    sim = B.Simulation(sc, block_steps=block)
+    # The library's launches go on a stream of ours, so that one pair of HIP events on it
+    # brackets exactly the timed launches (no event between launches perturbs them).
+    import torch
+    stream = torch.cuda.Stream()
+    sim = B.Simulation(sc, stream=stream, block_steps=block)
     tiling = sim.tiling()
     sim.step(args.warmup)
     sim.synchronize()
-    if not args.no_kernel_timing:
-        B.sim_set_timing(sim.h, True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
     t0 = time.perf_counter()
     sim.step(args.steps)
+    ev1.record(stream)
     sim.synchronize()
     elapsed = time.perf_counter() - t0
-    ktime = B.sim_read_state(sim.h, B.KERNEL_TIME) if not args.no_kernel_timing else None
+    ev1.synchronize()
+    gpu_ms = ev0.elapsed_time(ev1)
     c = sim.cones()
     cone_steps = active_cone_steps(c["event_step"], args.warmup, args.warmup + args.steps)
     sim.close()
@@ -312,9 +319,12 @@ def main():
     cells = sc.n_cells
     value = cells * args.steps / elapsed
     roofline = None
-    if ktime is not None and ktime[1] > 0:
-        launches = int(ktime[1])
-        avg_ms = ktime[0] / launches
+    block_used = max(1, tiling["block_steps"])
+    launches = -(-args.steps // block_used)   # the tiled kernel's launches in the region
+    if not args.no_kernel_timing and tiling["block_steps"] > 1:
+        # the timed region holds only the step kernel's launches: their average duration
+        # (back-to-back dispatch gaps included) is the region's event time over the count
+        avg_ms = gpu_ms / launches
         steps_per_launch = args.steps / launches
         algo_bytes = BYTES_PER_CELL_UPDATE * cells * steps_per_launch
         achieved = algo_bytes / (avg_ms * 1e-3) / 1e9

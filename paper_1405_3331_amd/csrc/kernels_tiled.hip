@@ -214,13 +214,14 @@ __device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CP
 // One stencil + decay sub-step of one species over a wavefront's strip of rows
 // [ybeg, yend), in place.  L points at tile row 0; rows -1 and HL .. HL+2 are guard rows
 // (never meaningful) so reads, which reach at most two rows past the strip, need no
-// clamping.  Within a wavefront every LDS read of a row
-// is issued before that row's write, so interior rows are overwritten as soon as they are
-// computed; the strip's first and last rows are read by the neighbouring wavefronts and
-// are returned for writing after a barrier.  Four row registers cycle through their roles
-// (above / at / below / prefetched), so rows are prefetched two ahead with no register
-// moves: a prefetched row is either this strip's, still unmodified, or a neighbour's first
-// row, written only after the barrier (or is never used).
+// clamping.  Within a wavefront every LDS read of a row is issued before that row's write,
+// so interior rows are overwritten as soon as they are computed; the strip's first and
+// last rows are read by the neighbouring wavefronts and are returned for writing after a
+// barrier.  Four row registers cycle through their roles (above / at / below /
+// prefetched), so rows are prefetched two ahead with no register moves: a prefetched row
+// is either this strip's, still unmodified, or a neighbour's first row, written only after
+// the barrier (or is never used).  The first and last rows are peeled off, so the loop body
+// has no branches and the LDS wait counter can let prefetches stay in flight.
 template <int CPL>
 struct StripEdges {
     typename Row<CPL>::T first, last;
@@ -231,54 +232,63 @@ __device__ __forceinline__ StripEdges<CPL> strip_update(float* L, int ybeg, int 
                                                         int gx0, int y0, int nx, int ny,
                                                         StencilCoef cf) {
     using V = typename Row<CPL>::T;
-    V first = {}, last = {};
     constexpr int W = 64 * CPL;
     const float* rd = L + cx;
     float* wr = L + cx;
-    V A = *(const V*)&rd[(ybeg - 1) * W];
-    V Bv = *(const V*)&rd[ybeg * W];
-    V C = *(const V*)&rd[(ybeg + 1) * W];
-    V D = *(const V*)&rd[(ybeg + 2) * W];
-#define CUESIM_PUT(yy, nv)                  \
-    do {                                    \
-        if ((yy) == ybeg)                   \
-            first = (nv);                   \
-        else if ((yy) == yend - 1)          \
-            last = (nv);                    \
-        else                                \
-            *(V*)&wr[(yy) * W] = (nv);      \
-    } while (0)
-    int y = ybeg;
-    for (; y + 4 <= yend; y += 4) {
-        V nv = row_update<CPL, WALLS>(A, Bv, C, y0 + y, gx0, nx, ny, cf);
-        A = *(const V*)&rd[(y + 3) * W];
-        CUESIM_PUT(y, nv);
-        nv = row_update<CPL, WALLS>(Bv, C, D, y0 + y + 1, gx0, nx, ny, cf);
-        Bv = *(const V*)&rd[(y + 4) * W];
-        CUESIM_PUT(y + 1, nv);
-        nv = row_update<CPL, WALLS>(C, D, A, y0 + y + 2, gx0, nx, ny, cf);
-        C = *(const V*)&rd[(y + 5) * W];
-        CUESIM_PUT(y + 2, nv);
-        nv = row_update<CPL, WALLS>(D, A, Bv, y0 + y + 3, gx0, nx, ny, cf);
-        D = *(const V*)&rd[(y + 6) * W];
-        CUESIM_PUT(y + 3, nv);
+    auto load = [&](int yy) { return *(const V*)&rd[yy * W]; };
+    auto store = [&](int yy, const V& v) { *(V*)&wr[yy * W] = v; };
+    auto upd = [&](const V& s, const V& c, const V& n, int yy) {
+        return row_update<CPL, WALLS>(s, c, n, y0 + yy, gx0, nx, ny, cf);
+    };
+    StripEdges<CPL> out;
+    V A = load(ybeg - 1), Bv = load(ybeg), C = load(ybeg + 1), D = load(ybeg + 2);
+    // the strip's first row (returned, written after the barrier)
+    out.first = upd(A, Bv, C, ybeg);
+    out.last = out.first;
+    if (yend - ybeg == 1) return out;
+    A = load(ybeg + 3);
+    // interior rows [ybeg + 1, yend - 1), written in place: a branch-free body of four rows,
+    // the registers (Bv, C, D, A) holding rows y - 1 .. y + 2 at its top
+    int y = ybeg + 1;
+    const int yin = yend - 1;
+    for (; y + 4 <= yin; y += 4) {
+        V nv = upd(Bv, C, D, y);
+        Bv = load(y + 3);
+        store(y, nv);
+        nv = upd(C, D, A, y + 1);
+        C = load(y + 4);
+        store(y + 1, nv);
+        nv = upd(D, A, Bv, y + 2);
+        D = load(y + 5);
+        store(y + 2, nv);
+        nv = upd(A, Bv, C, y + 3);
+        A = load(y + 6);
+        store(y + 3, nv);
     }
-    // remaining 0..3 rows, same register roles as at the top of a group
-    if (y < yend) {
-        V nv = row_update<CPL, WALLS>(A, Bv, C, y0 + y, gx0, nx, ny, cf);
-        A = *(const V*)&rd[(y + 3) * W];
-        CUESIM_PUT(y, nv);
-        if (y + 1 < yend) {
-            nv = row_update<CPL, WALLS>(Bv, C, D, y0 + y + 1, gx0, nx, ny, cf);
-            CUESIM_PUT(y + 1, nv);
-            if (y + 2 < yend) {
-                nv = row_update<CPL, WALLS>(C, D, A, y0 + y + 2, gx0, nx, ny, cf);
-                CUESIM_PUT(y + 2, nv);
-            }
-        }
+    // 0..3 remaining interior rows, then the last row (returned)
+    const int r = yin - y;
+    if (r == 0) {
+        out.last = upd(Bv, C, D, y);
+    } else if (r == 1) {
+        store(y, upd(Bv, C, D, y));
+        out.last = upd(C, D, A, y + 1);
+    } else if (r == 2) {
+        const V v0 = upd(Bv, C, D, y);
+        Bv = load(y + 3);
+        store(y, v0);
+        store(y + 1, upd(C, D, A, y + 1));
+        out.last = upd(D, A, Bv, y + 2);
+    } else {
+        const V v0 = upd(Bv, C, D, y);
+        Bv = load(y + 3);
+        store(y, v0);
+        const V v1 = upd(C, D, A, y + 1);
+        C = load(y + 4);
+        store(y + 1, v1);
+        store(y + 2, upd(D, A, Bv, y + 2));
+        out.last = upd(A, Bv, C, y + 3);
     }
-#undef CUESIM_PUT
-    return StripEdges<CPL>{first, last};
+    return out;
 }
 
 // Contact test against the targets staged for this tile (a superset of every target within
