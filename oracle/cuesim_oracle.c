@@ -341,9 +341,20 @@ static void step_one_cone(const oracle_params* p, oracle_state* s, int i,
             g[a] += p->sign[sp] * gs[a];
     }
 
-    /* C2 + C3: turn, then noise keyed by (cone, step, tag 0, simulation). */
+    /* C2 + C3: turn, then noise.  3D draws a block keyed by (cone, step, tag 0, simulation)
+     * and uses three of its deviates.  2D needs at most two per step, so one block keyed by
+     * (cone, step / 2, tag 0, simulation) serves two steps: its first Box-Muller pair for
+     * the even step, its second for the odd one (z[0], z[1] below). */
     double z[4];
-    oracle_normals4(p->seed, (uint32_t)i, (uint32_t)n, 0u, p->sim_index, z);
+    if (dim == 2) {
+        double zz[4];
+        oracle_normals4(p->seed, (uint32_t)i, (uint32_t)(n >> 1), 0u, p->sim_index, zz);
+        z[0] = zz[2 * (n & 1)];
+        z[1] = zz[2 * (n & 1) + 1];
+        z[2] = z[3] = 0.0;
+    } else {
+        oracle_normals4(p->seed, (uint32_t)i, (uint32_t)n, 0u, p->sim_index, z);
+    }
     for (int q = 0; q < 4; ++q)
         z[q] *= p->noise_sign;
     double h[3];
@@ -667,11 +678,12 @@ int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
             if (s->status[i] != ORACLE_ACTIVE && e <= n0 + n)
                 continue;
             double z[4];
-            oracle_normals4(p->seed, (uint32_t)i, (uint32_t)(n0 + n), 0u, p->sim_index, z);
+            const int64_t m = n0 + n;
+            oracle_normals4(p->seed, (uint32_t)i, (uint32_t)(m >> 1), 0u, p->sim_index, z);
             const double* st = tape_cone + ((size_t)n * M + i) * 3;
             double pos[2] = {st[0], st[1]};
-            cone_reverse_2d(p, fnext, af, pos, st[2], z[0] * p->noise_sign, acone + 3 * i,
-                            acone + 3 * i + 2);
+            cone_reverse_2d(p, fnext, af, pos, st[2], z[2 * (m & 1)] * p->noise_sign,
+                            acone + 3 * i, acone + 3 * i + 2);
         }
         /* field of step n: parameters, then a^n = A a^{n+1} */
         for (int sp = 0; sp < ns; ++sp) {

@@ -42,8 +42,34 @@ struct NoiseKey {
     uint32_t sim_index;    // fourth counter word
 };
 
-// Box-Muller pairs (Z0, Z1) from (u0, u1) and (Z2, Z3) from (u2, u3).  count selects how
-// many deviates are needed (1 in 2D, 3 in 3D).
+// One Box-Muller pair from two Philox words: radius from the first uniform, angle from
+// the second.
+__device__ __forceinline__ void normal_pair(uint32_t w0, uint32_t w1, float* z) {
+    float s, c;
+    const float r = sqrtf(-2.0f * logf(unit_open(w0)));
+    sincospif(2.0f * unit_open(w1), &s, &c);
+    z[0] = r * c;
+    z[1] = r * s;
+}
+
+// 2D draws at most two deviates per step, so one Philox block, counter
+// (cone, step / 2, 0, sim_index), serves two steps: its words (x, y) for the even step and
+// (z, w) for the odd one.
+__device__ __forceinline__ uint4 noise_block_2d(const NoiseKey& key, uint32_t cone,
+                                                uint32_t step) {
+    return philox4x32_10(make_uint4(cone, step >> 1, 0u, key.sim_index), key.k0, key.k1);
+}
+__device__ __forceinline__ void noise_2d(const NoiseKey& key, uint32_t cone, uint32_t step,
+                                         float* z) {
+    const uint4 x = noise_block_2d(key, cone, step);
+    if (step & 1u)
+        normal_pair(x.z, x.w, z);
+    else
+        normal_pair(x.x, x.y, z);
+}
+
+// Box-Muller pairs (Z0, Z1) from (u0, u1) and (Z2, Z3) from (u2, u3) of the block with
+// counter (cone, step, 0, sim_index).  count selects how many deviates are needed (3D: 3).
 template <int count>
 __device__ __forceinline__ void normals(const NoiseKey& key, uint32_t cone, uint32_t step,
                                         float* z) {
@@ -298,19 +324,17 @@ __device__ __forceinline__ float snr_turn(const ConeRules& r, float s, float c, 
 
 // One step of an active 2D cone: turn toward h + gain*g (capped) -- or by the SNR law's
 // decision, which also needs the concentration `conc` of species 0 at the tip -- noise,
-// advance, exit, contact.  `step` is the number of completed steps n before this one.
-// `contact` finds the nearest target in range (GridContact, or a list staged in LDS).
-// (s, c) carry sincosf(theta) in and sincosf of the new heading out, so a caller stepping a
-// cone repeatedly evaluates it once per step.
+// advance, exit, contact.  z is the step's normal pair (noise_2d).  `contact` finds the
+// nearest target in range (GridContact, or a list staged in LDS).  (s, c) carry
+// sincosf(theta) in and sincosf of the new heading out, so a caller stepping a cone
+// repeatedly evaluates it once per step.
 template <class Contact>
 __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, float gy,
-                                                  float conc, uint32_t id, uint32_t step,
-                                                  float& x, float& y, float& theta, float& s,
-                                                  float& c, const Contact& contact) {
+                                                  float conc, const float* z, float& x,
+                                                  float& y, float& theta, float& s, float& c,
+                                                  const Contact& contact) {
     float th;
     if (r.turn_law == 1) {
-        float z[2];
-        normals<2>(r.key, id, step, z);
         th = theta + snr_turn(r, s, c, gx, gy, conc, z[0]);
         th = th + r.sigma * z[1];
     } else {
@@ -319,8 +343,6 @@ __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, 
         if (cross == 0.0f) cross = 0.0f;   // -0 -> +0: an anti-parallel pull turns by +cap
         bool capped;
         const float turn = capped_turn(r, cross, along, &capped);
-        float z[1];
-        normals<1>(r.key, id, step, z);
         th = theta + turn;
         th = th + r.sigma * z[0];
     }

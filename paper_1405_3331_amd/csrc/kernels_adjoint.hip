@@ -127,8 +127,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_cone_adjoint2d(
     if (cross == 0.0f) cross = 0.0f;
     bool capped;
     const float turn = capped_turn(r, cross, along, &capped);
-    float z[1];
-    normals<1>(r.key, (uint32_t)i, step, z);
+    float z[2];
+    noise_2d(r.key, (uint32_t)i, step, z);
     float thn = th + turn;
     thn = thn + r.sigma * z[0];
     const float two_pi = 6.28318530717958647692f;

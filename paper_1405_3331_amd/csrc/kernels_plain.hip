@@ -99,7 +99,9 @@ __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __res
     }
     float sn, cs;
     sincosf(th, &sn, &cs);
-    const ConeEvent ev = cone_step_2d(r, gx, gy, conc, (uint32_t)i, step, x, y, th, sn, cs,
+    float z[2];
+    noise_2d(r.key, (uint32_t)i, step, z);
+    const ConeEvent ev = cone_step_2d(r, gx, gy, conc, z, x, y, th, sn, cs,
                                       GridContact{&r.targets});
     c.pos[2 * i] = x;
     c.pos[2 * i + 1] = y;

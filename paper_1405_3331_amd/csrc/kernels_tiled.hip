@@ -330,16 +330,31 @@ __device__ __forceinline__ float3 tile_cone_gradient(const float4& st, const Lds
 }
 
 // Second part; a stopped cone has its final state written to the caller-order arrays and
-// the sign bit of its id set.
-__device__ __forceinline__ void tile_cone_advance(float4& st, float2& sc, float3 g,
-                                                  const ConeRules& rules, uint32_t step,
+// the sign bit of its id set.  One Philox block serves an even step and the next odd one:
+// the odd step's two words wait in `spare` (`fresh`: no even step of this launch has
+// filled them yet).
+__device__ __forceinline__ void tile_cone_advance(float4& st, float2& sc, uint2& spare,
+                                                  float3 g, const ConeRules& rules,
+                                                  uint32_t step, bool fresh,
                                                   const TileContact& contact,
                                                   const ConeArrays& cones) {
     int id = __float_as_int(st.w);
     if (id < 0) return;
+    float z[2];
+    if ((step & 1u) == 0u || fresh) {
+        const uint4 blk = noise_block_2d(rules.key, (uint32_t)id, step);
+        if (step & 1u) {
+            normal_pair(blk.z, blk.w, z);
+        } else {
+            normal_pair(blk.x, blk.y, z);
+            spare = make_uint2(blk.z, blk.w);
+        }
+    } else {
+        normal_pair(spare.x, spare.y, z);
+    }
     float x = st.x, y = st.y, th = st.z;
     const ConeEvent ev =
-        cone_step_2d(rules, g.x, g.y, g.z, (uint32_t)id, step, x, y, th, sc.x, sc.y, contact);
+        cone_step_2d(rules, g.x, g.y, g.z, z, x, y, th, sc.x, sc.y, contact);
     if (ev.status != kActive) {
         cones.pos[2 * id] = x;
         cones.pos[2 * id + 1] = y;
@@ -448,11 +463,14 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
             }
         }
     }
-    // sincosf of every heading, carried alongside the cone from sub-step to sub-step
+    // sincosf of every heading, carried alongside the cone from sub-step to sub-step, and
+    // the second half of the current Philox block
     float2 trig[kConeSlots];
+    uint2 spare[kConeSlots];
 #pragma unroll
     for (int k = 0; k < kConeSlots; ++k) {
         trig[k] = make_float2(0.0f, 1.0f);
+        spare[k] = make_uint2(0u, 0u);
         if (threadIdx.x + k * kThreads < n_cones) sincosf(mine[k].z, &trig[k].x, &trig[k].y);
     }
     if (threadIdx.x < 9) {
@@ -529,7 +547,8 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < kConeSlots; ++k)
-                tile_cone_advance(mine[k], trig[k], g[k], rules, step, contact, a.cones);
+                tile_cone_advance(mine[k], trig[k], spare[k], g[k], rules, step, b == 0,
+                                  contact, a.cones);
         }
     }
 

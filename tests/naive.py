@@ -15,9 +15,10 @@ explicit finite-difference diffusion with first-order decay and point sources):
   multilinearly at u = p / dx - 1/2 (clamped), summed over species with their signs;
 * turn: toward h + gain * g by at most max_turn (2D: atan2 of cross and 1 + dot; 3D: in
   the plane of h and g);
-* noise: Box-Muller deviates from Philox(key = seed, counter = (cone, n, 0, sim)); 2D adds
-  sigma * Z0 to the angle and wraps it to [-pi, pi); 3D rotates h about the tangent-plane
-  vector sigma * (z - (z.h) h) and renormalises;
+* noise: Box-Muller deviates from Philox(key = seed); 3D: counter (cone, n, 0, sim), rotate h
+  about the tangent-plane vector sigma * (z - (z.h) h) and renormalise; 2D: counter
+  (cone, n // 2, 0, sim), the block's first pair for even n and second for odd n, sigma
+  times the pair's first deviate added to the angle, wrapped to [-pi, pi);
 * advance by step_len along h; exit (outside [0, n dx) on any axis) before contact; contact
   when the squared distance to a target is strictly below R^2, nearest (lowest index on a
   tie) wins.
@@ -163,9 +164,20 @@ class NaiveSim:
         for _ in range(n_steps):
             self._field_step()
             active = [i for i in range(sc.n_cones) if self.status[i] == 0]
-            words = philox_words(sc.seed, [(i, self.step_count, 0, sc.sim_index) for i in active])
-            for i, wd in zip(active, words):
-                self._cone(i, _deviates(wd))
+            n = self.step_count
+            if not active:
+                self.step_count += 1
+                continue
+            if self.dim == 2:
+                # one block per two steps: the first Box-Muller pair for even n, the second
+                # for odd n
+                words = philox_words(sc.seed, [(i, n // 2, 0, sc.sim_index) for i in active])
+                zs = [_deviates(wd)[2 * (n % 2):2 * (n % 2) + 2] for wd in words]
+            else:
+                words = philox_words(sc.seed, [(i, n, 0, sc.sim_index) for i in active])
+                zs = [_deviates(wd) for wd in words]
+            for i, z in zip(active, zs):
+                self._cone(i, z)
             self.step_count += 1
         return self
 

@@ -8,6 +8,14 @@ Tolerances (FP32 device arithmetic against the FP64 oracle):
 A cone is flagged from the first step at which the oracle saw a near-tie (distance to a wall
 or to a contact sphere within tau = 1e-4 L, two in-range targets within tau, or an almost
 exactly anti-parallel pull); flagged cones are excluded from the exact event comparison.
+
+Full runs (no restarts) additionally meet cones whose tip error grows by the dynamics, not
+by the implementation: a cone steered around a source can amplify FP32 rounding
+differences by orders of magnitude within a hundred steps.  `FullRun` classifies a cone
+over the tip bound as amplified only if the same cone, restarted on the GPU from the
+oracle's state WINDOW steps earlier, stays within the bound over that window (the windowed
+check that is the hard gate); otherwise the comparison fails.  Amplified cones are then
+left out of the tip and event comparisons, like flagged ones.
 """
 from __future__ import annotations
 
@@ -73,3 +81,65 @@ def assert_parity(m, field_tol=FIELD_TOL, tip_tol=TIP_TOL, where=""):
     assert max(m["field"]) <= field_tol, (where, m["field"])
     assert m["tip_max"] <= tip_tol, (where, m["tip_max"])
     assert len(m["event_mismatch"]) == 0, (where, m["event_mismatch"][:10])
+
+
+WINDOW = 20
+
+
+def _snapshot(ref):
+    return dict(fields=[f.copy() for f in ref.fields], pos=ref.pos.copy(), dir=ref.dir.copy(),
+                status=ref.status.copy(), target=ref.target.copy(),
+                event_step=ref.event_step.copy(), step=ref.step_count)
+
+
+class FullRun:
+    """Oracle and GPU side by side without restarts, checked after every `advance`, with
+    the amplification classification described above."""
+
+    def __init__(self, sc, block_steps=0):
+        self.sc = sc
+        self.block_steps = block_steps
+        self.ref = oracle.OracleSim(sc)
+        self.sim = B.Simulation(sc, block_steps=block_steps)
+        self.amplified = np.zeros(sc.n_cones, dtype=bool)
+        self.worst = {"field": 0.0, "tip": 0.0}
+
+    def _windowed_error(self, snap, cones, steps):
+        """Tip error of `cones` after `steps` steps from the oracle state `snap`."""
+        ref = oracle.OracleSim(self.sc)
+        ref.set_state(**snap)
+        sim = B.Simulation(self.sc, block_steps=self.block_steps)
+        restart_from_oracle(sim, ref)
+        ref.step(steps)
+        sim.step(steps)
+        pos = sim.cones()["pos"].astype(np.float64)
+        sim.close()
+        return np.abs(pos[cones] - ref.pos[cones]).max(axis=1) / self.sc.side
+
+    def advance(self, steps, where=""):
+        snap, last = None, 0
+        while steps > 0:   # in windows of at most WINDOW steps, remembering the last start
+            last = min(WINDOW, steps)
+            snap = _snapshot(self.ref)
+            self.ref.step(last)
+            self.sim.step(last)
+            steps -= last
+        m = compare(self.sim, self.ref, self.sc)
+        assert max(m["field"]) <= FIELD_TOL, (where, m["field"])
+        ok = (self.ref.flag_step < 0) & ~self.amplified
+        over = np.nonzero(ok & (m["tip_all"] > TIP_TOL))[0] if self.sc.n_cones else []
+        if len(over):
+            werr = self._windowed_error(snap, over, last)
+            assert np.all(werr <= TIP_TOL), (where, "windowed", over[werr > TIP_TOL], werr.max())
+            self.amplified[over] = True
+            ok[over] = False
+        if self.sc.n_cones:
+            assert (m["tip_all"][ok].max() if ok.any() else 0.0) <= TIP_TOL, where
+            mismatch = np.setdiff1d(m["event_mismatch"], np.nonzero(self.amplified)[0])
+            assert len(mismatch) == 0, (where, mismatch[:10])
+        self.worst["field"] = max(self.worst["field"], max(m["field"]))
+        self.worst["tip"] = max(self.worst["tip"], float(m["tip_all"][ok].max()) if ok.any() else 0.0)
+        return m
+
+    def close(self):
+        self.sim.close()

@@ -488,8 +488,9 @@ def pin_noise_plumbing(lib_path=LIB):
         theta = sc.cone_dir[i]
         p = sc.cone_pos[i].copy()
         for k in range(steps):
-            z = oracle.normals4(seed, i, k, 0, 3, lib=lib)
-            theta = theta + sc.noise_sigma * z[0]
+            # 2D: one Philox block per two steps, first pair for even k, second for odd k
+            z = oracle.normals4(seed, i, k // 2, 0, 3, lib=lib)
+            theta = theta + sc.noise_sigma * z[2 * (k % 2)]
             p = p + sc.step_len * np.array([math.cos(theta), math.sin(theta)])
         d = (o.dir[i] - theta + math.pi) % (2 * math.pi) - math.pi
         assert abs(d) < 1e-12, (i, o.dir[i], theta)
@@ -792,6 +793,19 @@ def pin_snr_bruteforce(lib_path=LIB):
     assert np.abs(np.angle(np.exp(1j * (a.dir - np.array(b.dir))))).max() <= 1e-10
 
 
+def pin_bruteforce_3d(lib_path=LIB):
+    """The whole 3D step against the naive implementation (deviates from PyTorch's
+    Philox): two species, noise, 20 steps."""
+    import naive
+    sc = make_scenario("3d brute force", 3, (4, 5, 3), 1.0, 0.12,
+                       ((1.0, 0.01, 1.0), (0.5, 0.02, -1.0)), 3, (5.0, 20.0), 3, 3, 1.0, 0.15,
+                       10.0, math.pi / 30.0, 0.2, seed=5)
+    a = OracleSim(sc, lib_path=lib_path).step(20)
+    b = naive.NaiveSim(sc).step(20)
+    assert np.abs(a.pos - np.array(b.pos)).max() <= 1e-10 * sc.side
+    assert np.abs(a.dir - np.array(b.dir)).max() <= 1e-10
+
+
 ALL_PINS = {
     "mass2d": lambda p: pin_mass_recursion(p, 2),
     "mass3d": lambda p: pin_mass_recursion(p, 3),
@@ -816,4 +830,5 @@ ALL_PINS = {
     "graph": pin_connectivity,
     "snr": pin_snr_law,
     "snr_noise": pin_snr_bruteforce,
+    "bruteforce3d": pin_bruteforce_3d,
 }

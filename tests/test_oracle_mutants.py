@@ -36,8 +36,11 @@ MUTANTS = [
     ("no_turn_cap", "if (delta > p->max_turn) delta = p->max_turn;", "", ["turn2d"]),
     ("turn_3d_away", "h[a] = c * h[a] + s * perp[a] / perp_norm;",
      "h[a] = c * h[a] - s * perp[a] / perp_norm;", ["turn3d"]),
-    ("noise_counter_swapped", "(uint32_t)i, (uint32_t)n, 0u, p->sim_index", "(uint32_t)n, (uint32_t)i, 0u, p->sim_index",
-     ["noise"]),
+    ("noise_counter_swapped", "(uint32_t)i, (uint32_t)(n >> 1), 0u, p->sim_index",
+     "(uint32_t)(n >> 1), (uint32_t)i, 0u, p->sim_index", ["noise"]),
+    ("noise_pair_ignored", "z[0] = zz[2 * (n & 1)];", "z[0] = zz[0];", ["noise"]),
+    ("noise_3d_counter_swapped", "(uint32_t)i, (uint32_t)n, 0u, p->sim_index",
+     "(uint32_t)n, (uint32_t)i, 0u, p->sim_index", ["noise3d", "bruteforce3d"]),
     ("noise_not_tangent", "w[a] = p->noise_sigma * (z[a] - along * h[a]);",
      "w[a] = p->noise_sigma * z[a];", ["noise3d"]),
     ("exit_closed_interval", "if (pos[a] < 0.0 || pos[a] >= domain_length(p, a))",
