@@ -98,6 +98,7 @@ struct TargetGrid {
     const int32_t* cell_start;   // [gx*gy*gz + 1]
     int gx, gy, gz;
     float inv_cell;
+    float r;                     // contact radius (FP32)
     float r2;                    // contact radius squared (FP32)
 };
 
@@ -129,22 +130,32 @@ __device__ __forceinline__ int contact_in_list(const float4* pts, int n, float r
     return best;
 }
 
+// Target cells along one axis that can hold a target within the contact radius of p: a
+// target closer than R differs from p by less than R on every axis, so its cell lies between
+// those of p - R and p + R.  The bounds are widened by kCellSlack cells to absorb the FP32
+// rounding of (p +- R) / cell, so the search stays exact; usually one or two cells per axis.
+constexpr float kCellSlack = 1e-3f;
+__device__ __forceinline__ void target_cell_range(float p, const TargetGrid& tg, int n, int& lo,
+                                                  int& hi) {
+    lo = max((int)floorf(fmaf(p - tg.r, tg.inv_cell, -kCellSlack)), 0);
+    hi = min((int)floorf(fmaf(p + tg.r, tg.inv_cell, kCellSlack)), n - 1);
+}
+
 // Nearest target with squared distance strictly below r2; ties on the squared distance go
 // to the lowest original index.  Returns -1 when none is in range.
 template <int dim>
 __device__ __forceinline__ int contact_target(const TargetGrid& tg, float x, float y, float z) {
-    const int cx = min(max((int)floorf(x * tg.inv_cell), 0), tg.gx - 1);
-    const int cy = min(max((int)floorf(y * tg.inv_cell), 0), tg.gy - 1);
-    const int cz = dim == 3 ? min(max((int)floorf(z * tg.inv_cell), 0), tg.gz - 1) : 0;
+    int x_lo, x_hi, y_lo, y_hi, z_lo = 0, z_hi = 0;
+    target_cell_range(x, tg, tg.gx, x_lo, x_hi);
+    target_cell_range(y, tg, tg.gy, y_lo, y_hi);
+    if (dim == 3) target_cell_range(z, tg, tg.gz, z_lo, z_hi);
     float best_d2 = tg.r2;
     int best = -1;
-    const int z_lo = dim == 3 ? max(cz - 1, 0) : 0;
-    const int z_hi = dim == 3 ? min(cz + 1, tg.gz - 1) : 0;
     for (int zz = z_lo; zz <= z_hi; ++zz)
-        for (int yy = max(cy - 1, 0); yy <= min(cy + 1, tg.gy - 1); ++yy) {
+        for (int yy = y_lo; yy <= y_hi; ++yy) {
             const int row = (zz * tg.gy + yy) * tg.gx;
-            const int lo = tg.cell_start[row + max(cx - 1, 0)];
-            const int hi = tg.cell_start[row + min(cx + 1, tg.gx - 1) + 1];
+            const int lo = tg.cell_start[row + x_lo];
+            const int hi = tg.cell_start[row + x_hi + 1];
             for (int k = lo; k < hi; ++k) {
                 const float4 t = tg.pts[k];
                 const float ddx = x - t.x, ddy = y - t.y;

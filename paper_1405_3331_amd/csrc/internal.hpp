@@ -45,6 +45,37 @@ hipError_t launch_cones_plain(int dim, const ConeRules& rules, const float* f0,
                               const float* f1, ConeArrays cones, uint32_t step,
                               hipStream_t stream);
 
+// Active 3D cones in spatial order (kernels_cones3d.hip): per cone the tip (x, y, z, id)
+// and heading (hx, hy, hz, 0), ping-pong halves, with the radix-sort keys, slots and scratch.
+// Keys are Morton codes of the tip cell coarsened by `shift` bits per axis; stopped cones
+// carry id -1 and the key `inactive`, past every active one.
+struct ConeOrder3D {
+    float4* tip[2] = {};
+    float4* dir[2] = {};
+    uint32_t* key[2] = {};
+    int32_t* slot[2] = {};
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    int cur = 0;
+    int n = 0;
+    int shift = 2;
+    uint32_t inactive = 0;
+    int end_bit = 1;
+};
+hipError_t order3d_allocate(ConeOrder3D& o, int n, int nx, int ny, int nz);
+void order3d_release(ConeOrder3D& o);
+// Caller-order arrays -> ordered state (pack, sort, gather).
+hipError_t order3d_begin(ConeOrder3D& o, const ConeRules& r, ConeArrays cones,
+                         hipStream_t stream);
+// Re-sort the ordered state by the current tips.
+hipError_t order3d_refresh(ConeOrder3D& o, const ConeRules& r, hipStream_t stream);
+// One step of the ordered cones; stopping cones are written to `cones` at once.
+hipError_t launch_cones3d_ordered(const ConeRules& r, const float* f0, const float* f1,
+                                  ConeOrder3D& o, ConeArrays cones, uint32_t step,
+                                  hipStream_t stream);
+// Tips and headings of the still-active ordered cones back into the caller-order arrays.
+hipError_t order3d_end(const ConeOrder3D& o, ConeArrays cones, hipStream_t stream);
+
 // Reverse pass of the 2D step (kernels_adjoint.hip).  Field adjoint grids have
 // adjoint_field_blocks(nx, ny) workgroups, each owning one slot of acc_D / acc_k.
 int adjoint_field_blocks(int nx, int ny);

@@ -1,0 +1,254 @@
+// kernels_cones3d.hip -- the 3D cone step over cones held in spatial order.
+//
+// A 3D cone samples 32 cells per species around its tip (Sec. 3.4 gradient, trilinear).  In
+// the caller's order neighbouring threads sit anywhere in the volume, so a wavefront touches
+// a separate set of cache lines per cone and uses a few bytes of each.  Here the active
+// cones are kept sorted by the Morton code of their tip cell (coarsened by `shift` bits per
+// axis): a workgroup then covers one compact region, its gathers share lines in L1/L2, and
+// the cone state itself streams as two aligned float4 per cone (tip x, y, z, id; heading).
+// Cones move at most step_len per step, so the order is refreshed every few steps (radix
+// sort of the keys, then a gather of the state), not every step.
+//
+// Stopped cones leave the order: the step writes their final tip, heading, status, target
+// and event step straight into the caller-order arrays and marks the ordered copy id = -1;
+// a refresh moves them behind the active ones.  The caller-order tips and headings of the
+// active cones are brought up to date only when the state is read (order3d_end).
+#include <hipcub/hipcub.hpp>
+
+#include "internal.hpp"
+
+namespace cuesim {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kXcds = 8;   // workgroups are dealt to the accelerator dies round-robin
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t cell_coord(float p, float inv_dx, int n) {
+    const int c = (int)floorf(p * inv_dx);
+    return (uint32_t)min(max(c, 0), n - 1);
+}
+
+__device__ __forceinline__ uint32_t order_key(const ConeRules& r, float x, float y, float z,
+                                              int shift) {
+    return spread3(cell_coord(x, r.inv_dx, r.nx) >> shift) |
+           (spread3(cell_coord(y, r.inv_dx, r.ny) >> shift) << 1) |
+           (spread3(cell_coord(z, r.inv_dx, r.nz) >> shift) << 2);
+}
+
+// Caller order -> (tip, heading) with keys; inactive cones get id -1 and the key past every
+// active one.
+__global__ __launch_bounds__(kThreads) void k_pack3d(ConeRules r, ConeArrays c, float4* tip,
+                                                     float4* dir, uint32_t* key, int32_t* slot,
+                                                     int shift, uint32_t inactive) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= c.n) return;
+    const float x = c.pos[3 * i], y = c.pos[3 * i + 1], z = c.pos[3 * i + 2];
+    const bool active = c.status[i] == kActive;
+    tip[i] = make_float4(x, y, z, __int_as_float(active ? i : -1));
+    dir[i] = make_float4(c.dir[3 * i], c.dir[3 * i + 1], c.dir[3 * i + 2], 0.0f);
+    key[i] = active ? order_key(r, x, y, z, shift) : inactive;
+    slot[i] = i;
+}
+
+__global__ __launch_bounds__(kThreads) void k_keys3d(ConeRules r, const float4* __restrict__ tip,
+                                                     int n, uint32_t* key, int32_t* slot,
+                                                     int shift, uint32_t inactive) {
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const float4 p = tip[t];
+    key[t] = __float_as_int(p.w) >= 0 ? order_key(r, p.x, p.y, p.z, shift) : inactive;
+    slot[t] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather3d(const int32_t* __restrict__ slot, int n,
+                                                       const float4* __restrict__ tip_in,
+                                                       const float4* __restrict__ dir_in,
+                                                       float4* __restrict__ tip_out,
+                                                       float4* __restrict__ dir_out) {
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const int s = slot[t];
+    tip_out[t] = tip_in[s];
+    dir_out[t] = dir_in[s];
+}
+
+struct Global3D {
+    const float* f;
+    int nx, ny;
+    __device__ float operator()(int i, int j, int l) const { return f[(l * ny + j) * nx + i]; }
+};
+
+// One step of every ordered cone against the updated fields.  Workgroup w of the launch
+// takes the w-th block of kThreads cones counted die by die, so each die works through one
+// contiguous stretch of the order and its L2 holds that region of the fields.
+__global__ __launch_bounds__(kThreads) void k_cones3d_ordered(ConeRules r,
+                                                              const float* __restrict__ f0,
+                                                              const float* __restrict__ f1,
+                                                              float4* tip, float4* dir, int n,
+                                                              int per_xcd, ConeArrays c,
+                                                              uint32_t step) {
+    const int block = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    const int t = block * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const float4 p = tip[t];
+    const int id = __float_as_int(p.w);
+    if (id < 0) return;
+    const float4 h = dir[t];
+    float x = p.x, y = p.y, z = p.z, hx = h.x, hy = h.y, hz = h.z;
+    float gx, gy, gz;
+    gradient_3d(Global3D{f0, r.nx, r.ny}, r, x, y, z, gx, gy, gz);
+    gx *= r.sign0;
+    gy *= r.sign0;
+    gz *= r.sign0;
+    if (r.n_species > 1) {
+        float ax, ay, az;
+        gradient_3d(Global3D{f1, r.nx, r.ny}, r, x, y, z, ax, ay, az);
+        gx = fmaf(r.sign1, ax, gx);
+        gy = fmaf(r.sign1, ay, gy);
+        gz = fmaf(r.sign1, az, gz);
+    }
+    const ConeEvent ev = cone_step_3d(r, gx, gy, gz, (uint32_t)id, step, x, y, z, hx, hy, hz,
+                                      GridContact{&r.targets});
+    dir[t] = make_float4(hx, hy, hz, 0.0f);
+    if (ev.status == kActive) {
+        tip[t] = make_float4(x, y, z, p.w);
+        return;
+    }
+    tip[t] = make_float4(x, y, z, __int_as_float(-1));
+    c.pos[3 * id] = x;
+    c.pos[3 * id + 1] = y;
+    c.pos[3 * id + 2] = z;
+    c.dir[3 * id] = hx;
+    c.dir[3 * id + 1] = hy;
+    c.dir[3 * id + 2] = hz;
+    c.status[id] = ev.status;
+    c.target[id] = ev.target;
+    c.event_step[id] = (int32_t)(step + 1);
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpack3d(const float4* __restrict__ tip,
+                                                       const float4* __restrict__ dir, int n,
+                                                       ConeArrays c) {
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const float4 p = tip[t];
+    const int id = __float_as_int(p.w);
+    if (id < 0) return;
+    const float4 h = dir[t];
+    c.pos[3 * id] = p.x;
+    c.pos[3 * id + 1] = p.y;
+    c.pos[3 * id + 2] = p.z;
+    c.dir[3 * id] = h.x;
+    c.dir[3 * id + 1] = h.y;
+    c.dir[3 * id + 2] = h.z;
+}
+
+int blocks_for(int n) { return (n + kThreads - 1) / kThreads; }
+
+int axis_bits(int n, int shift) {
+    int bits = 1;
+    while (bits < 10 && ((n - 1) >> shift) >= (1 << bits)) ++bits;
+    return bits;
+}
+
+// Radix sort of (key, slot) from buffer 0 into buffer 1, then the state gather into the
+// other half of the ping-pong.
+hipError_t sort_and_gather(ConeOrder3D& o, hipStream_t stream) {
+    size_t bytes = o.temp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(o.temp, bytes, o.key[0], o.key[1],
+                                                      o.slot[0], o.slot[1], o.n, 0,
+                                                      o.end_bit, stream);
+    if (e != hipSuccess) return e;
+    const int nxt = o.cur ^ 1;
+    hipLaunchKernelGGL(k_gather3d, dim3(blocks_for(o.n)), dim3(kThreads), 0, stream, o.slot[1],
+                       o.n, o.tip[o.cur], o.dir[o.cur], o.tip[nxt], o.dir[nxt]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    o.cur = nxt;
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t order3d_allocate(ConeOrder3D& o, int n, int nx, int ny, int nz) {
+    o = ConeOrder3D{};
+    o.n = n;
+    const int bits = std::max(axis_bits(nx, o.shift), std::max(axis_bits(ny, o.shift),
+                                                               axis_bits(nz, o.shift)));
+    o.inactive = 1u << (3 * bits);
+    o.end_bit = 3 * bits + 1;
+    if (n == 0) return hipSuccess;
+    hipError_t e;
+    for (int b = 0; b < 2; ++b) {
+        if ((e = hipMalloc((void**)&o.tip[b], (size_t)n * sizeof(float4))) != hipSuccess ||
+            (e = hipMalloc((void**)&o.dir[b], (size_t)n * sizeof(float4))) != hipSuccess ||
+            (e = hipMalloc((void**)&o.key[b], (size_t)n * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc((void**)&o.slot[b], (size_t)n * sizeof(int32_t))) != hipSuccess)
+            return e;
+    }
+    size_t bytes = 0;
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, o.key[0], o.key[1], o.slot[0],
+                                           o.slot[1], n, 0, o.end_bit);
+    if (e != hipSuccess) return e;
+    o.temp_bytes = std::max<size_t>(bytes, 1);
+    return hipMalloc(&o.temp, o.temp_bytes);
+}
+
+void order3d_release(ConeOrder3D& o) {
+    for (int b = 0; b < 2; ++b) {
+        if (o.tip[b]) (void)hipFree(o.tip[b]);
+        if (o.dir[b]) (void)hipFree(o.dir[b]);
+        if (o.key[b]) (void)hipFree(o.key[b]);
+        if (o.slot[b]) (void)hipFree(o.slot[b]);
+    }
+    if (o.temp) (void)hipFree(o.temp);
+    o = ConeOrder3D{};
+}
+
+hipError_t order3d_begin(ConeOrder3D& o, const ConeRules& r, ConeArrays cones,
+                         hipStream_t stream) {
+    if (o.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack3d, dim3(blocks_for(o.n)), dim3(kThreads), 0, stream, r, cones,
+                       o.tip[o.cur], o.dir[o.cur], o.key[0], o.slot[0], o.shift, o.inactive);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return sort_and_gather(o, stream);
+}
+
+hipError_t order3d_refresh(ConeOrder3D& o, const ConeRules& r, hipStream_t stream) {
+    if (o.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys3d, dim3(blocks_for(o.n)), dim3(kThreads), 0, stream, r,
+                       o.tip[o.cur], o.n, o.key[0], o.slot[0], o.shift, o.inactive);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return sort_and_gather(o, stream);
+}
+
+hipError_t launch_cones3d_ordered(const ConeRules& r, const float* f0, const float* f1,
+                                  ConeOrder3D& o, ConeArrays cones, uint32_t step,
+                                  hipStream_t stream) {
+    if (o.n == 0) return hipSuccess;
+    const int blocks = blocks_for(o.n);
+    const int per_xcd = (blocks + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(k_cones3d_ordered, dim3(per_xcd * kXcds), dim3(kThreads), 0, stream, r,
+                       f0, f1, o.tip[o.cur], o.dir[o.cur], o.n, per_xcd, cones, step);
+    return hipGetLastError();
+}
+
+hipError_t order3d_end(const ConeOrder3D& o, ConeArrays cones, hipStream_t stream) {
+    if (o.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack3d, dim3(blocks_for(o.n)), dim3(kThreads), 0, stream,
+                       o.tip[o.cur], o.dir[o.cur], o.n, cones);
+    return hipGetLastError();
+}
+
+}  // namespace cuesim

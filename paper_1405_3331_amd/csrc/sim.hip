@@ -22,6 +22,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Steps between refreshes of the spatial order of 3D cones (a cone moves step_len per step).
+constexpr int kOrderRefresh = 16;
+
 bool finite(double v) { return std::isfinite(v); }
 
 }  // namespace
@@ -72,6 +75,11 @@ struct sim_handle {
     TiledPlan plan = {};
     TiledState tiled = {};
     bool cones_bucketed = false;   // active cones live in the tile buckets
+
+    // 3D: active cones in spatial order, refreshed every kOrderRefresh steps
+    ConeOrder3D order3d = {};
+    bool cones_ordered = false;    // tips and headings of active cones live in order3d
+    int since_refresh = 0;
 
     int64_t step = 0;
     bool poisoned = false;
@@ -194,6 +202,7 @@ void release(sim_handle* h) {
     dfree(h->mass_partial);
     dfree(h->mass_out);
     tiled_release(h->tiled);
+    order3d_release(h->order3d);
     drop_events(h);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     h->stream = nullptr;
@@ -337,6 +346,7 @@ sim_status build_targets(sim_handle* h, const sim_params* p) {
     tg.gy = g[1];
     tg.gz = g[2];
     tg.inv_cell = (float)(1.0 / cell);
+    tg.r = (float)p->contact_radius;
     tg.r2 = (float)(p->contact_radius * p->contact_radius);
     return SIM_OK;
 }
@@ -390,6 +400,10 @@ sim_status item_size(sim_handle* h, sim_item what, int32_t index, size_t* bytes)
 
 // Bring active cones from the tile buckets back into the caller-order arrays.
 sim_status unbucket(sim_handle* h) {
+    if (h->cones_ordered) {
+        HIP_TRY(h, order3d_end(h->order3d, h->cones, h->stream));
+        h->cones_ordered = false;
+    }
     if (!h->cones_bucketed) return SIM_OK;
     HIP_TRY(h, tiled_unbucket(h->plan, h->tiled, h->cones, h->stream));
     h->cones_bucketed = false;
@@ -436,7 +450,22 @@ sim_status plain_step(sim_handle* h) {
     }
     const float* f0 = h->field[0][h->cur[0]];
     const float* f1 = h->n_species > 1 ? h->field[1][h->cur[1]] : f0;
-    HIP_TRY(h, launch_cones_plain(h->dim, h->rules, f0, f1, h->cones, (uint32_t)h->step, h->stream));
+    if (h->order3d.n > 0) {
+        if (!h->cones_ordered) {
+            HIP_TRY(h, order3d_begin(h->order3d, h->rules, h->cones, h->stream));
+            h->cones_ordered = true;
+            h->since_refresh = 0;
+        } else if (h->since_refresh >= kOrderRefresh) {
+            HIP_TRY(h, order3d_refresh(h->order3d, h->rules, h->stream));
+            h->since_refresh = 0;
+        }
+        HIP_TRY(h, launch_cones3d_ordered(h->rules, f0, f1, h->order3d, h->cones,
+                                          (uint32_t)h->step, h->stream));
+        h->since_refresh += 1;
+    } else {
+        HIP_TRY(h, launch_cones_plain(h->dim, h->rules, f0, f1, h->cones, (uint32_t)h->step,
+                                      h->stream));
+    }
     h->step += 1;
     return SIM_OK;
 }
@@ -557,6 +586,10 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
             (e = hipMemcpy(h->cones.target, minus1.data(), M * 4, hipMemcpyHostToDevice)) ||
             (e = hipMemcpy(h->cones.event_step, minus1.data(), M * 4, hipMemcpyHostToDevice)))
             return bail(device_fail(h, e, "cone upload"));
+    }
+    if (p->dim == 3 && M > 0) {
+        e = order3d_allocate(h->order3d, p->n_cones, h->nx, h->ny, h->nz);
+        if (e != hipSuccess) return bail(device_fail(h, e, "cone order allocation"));
     }
     st = build_targets(h, p);
     if (st != SIM_OK) return bail(st);
