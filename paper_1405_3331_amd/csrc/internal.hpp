@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "device.hpp"
 
 namespace cuesim {
@@ -34,16 +36,44 @@ struct ConeArrays {
     int n;
 };
 
-// One step without temporal blocking: stencil of every species (HBM in -> HBM out), then
-// sources, then one thread per cone.  `in`/`out` index species.
-// start/stop (may be null): events the launch itself records around the stencil kernel.
-hipError_t launch_field_plain(int dim, int nx, int ny, int nz, const float* in, float* out,
-                              StencilCoef coef, hipStream_t stream,
-                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// One 2D step without temporal blocking: stencil of one species (HBM in -> HBM out), then
+// sources, then one thread per cone.  start/stop (may be null): events the launch itself
+// records around the stencil kernel.
+hipError_t launch_field2d(int nx, int ny, const float* in, float* out, StencilCoef coef,
+                          hipStream_t stream, hipEvent_t start = nullptr,
+                          hipEvent_t stop = nullptr);
 hipError_t launch_sources(float* field, SourceList src, hipStream_t stream);
-hipError_t launch_cones_plain(int dim, const ConeRules& rules, const float* f0,
-                              const float* f1, ConeArrays cones, uint32_t step,
-                              hipStream_t stream);
+hipError_t launch_cones2d(const ConeRules& rules, const float* f0, const float* f1,
+                          ConeArrays cones, uint32_t step, hipStream_t stream);
+
+// 3D field step of every species in one launch, sources included (kernels_field3d.hip).
+// Field3D holds the per-box source lists (plane, thread, amount) built once by
+// field3d_prepare from the merged, pre-scaled sources of each species.
+struct Field3D {
+    int nx = 0, ny = 0, nz = 0, n_species = 0, n_boxes = 0;
+    int32_t* src_start = nullptr;    // [n_boxes + 1]
+    int32_t* src_plane = nullptr;    // per entry: plane index l
+    int32_t* src_thread = nullptr;   // per entry: thread of the box owning the cell
+    float* src_q = nullptr;          // per entry: amount / dx^3
+};
+struct Field3DArgs {
+    const float* in[2];
+    float* out[2];
+    StencilCoef coef[2];
+    int nx, ny, nz, n_species;
+    int tx, ty, tz, per_xcd;
+    const int32_t* src_start;
+    const int32_t* src_plane;
+    const int32_t* src_thread;
+    const float* src_q;
+};
+hipError_t field3d_prepare(Field3D& f, int nx, int ny, int nz, int n_species,
+                           const std::vector<int32_t>* cells, const std::vector<float>* q);
+void field3d_release(Field3D& f);
+// start/stop (may be null): events the launch itself records.
+hipError_t launch_field3d(const Field3D& f, const float* const* in, float* const* out,
+                          const StencilCoef* coef, hipStream_t stream,
+                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 // Active 3D cones in spatial order (kernels_cones3d.hip): per cone the tip (x, y, z, id)
 // and heading (hx, hy, hz, 0), ping-pong halves, with the radix-sort keys, slots and scratch.

@@ -1,6 +1,6 @@
 // kernels_plain.hip -- one time step per kernel sequence, no temporal blocking.
 //
-// The stencil reads each cell's 2*dim neighbours from HBM/L2 and writes the new value:
+// The 2D stencil reads each cell's 4 neighbours from HBM/L2 and writes the new value:
 // 8 algorithmic bytes per cell-update (one FP32 read, one FP32 write), the HBM-bound
 // baseline the tiled kernel improves on.  Cones run one thread each, in the caller's order,
 // against the just-updated field.
@@ -30,40 +30,6 @@ __global__ __launch_bounds__(kRowThreads) void k_field2d(const float* __restrict
     out[at] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
 }
 
-// 3D stencil marching along z: a workgroup covers an x-y tile of kStreamX x kStreamY
-// columns and kStreamZ consecutive planes; each thread keeps the planes below, at and above
-// its cell in registers, so every cell is read from HBM about once per step while the
-// in-plane neighbours come from lines the workgroup has just brought into L1.
-constexpr int kStreamX = 64, kStreamY = 4, kStreamZ = 32;
-
-__global__ __launch_bounds__(kStreamX * kStreamY) void k_field3d_stream(
-    const float* __restrict__ in, float* __restrict__ out, int nx, int ny, int nz,
-    StencilCoef coef) {
-    const int i = blockIdx.x * kStreamX + threadIdx.x % kStreamX;
-    const int j = blockIdx.y * kStreamY + threadIdx.x / kStreamX;
-    const int z0 = blockIdx.z * kStreamZ;
-    const int z1 = min(z0 + kStreamZ, nz);
-    if (i >= nx || j >= ny) return;
-    const size_t plane = (size_t)nx * ny;
-    const float* col = in + (size_t)j * nx + i;
-    float* dst = out + (size_t)j * nx + i;
-    const bool west = i > 0, east = i < nx - 1, south = j > 0, north = j < ny - 1;
-    float c = col[z0 * plane];
-    float below = z0 > 0 ? col[(z0 - 1) * plane] : c;
-    for (int l = z0; l < z1; ++l) {
-        const float above = l + 1 < nz ? col[(l + 1) * plane] : c;
-        const float* p = col + l * plane;
-        const float w = west ? p[-1] : c;
-        const float e = east ? p[1] : c;
-        const float s = south ? p[-nx] : c;
-        const float n = north ? p[nx] : c;
-        const float lap = (((w + e) + (s + n)) + (below + above)) - 6.0f * c;
-        dst[l * plane] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
-        below = c;
-        c = above;
-    }
-}
-
 __global__ void k_sources(float* __restrict__ field, SourceList src) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m < src.n) field[src.cell[m]] += src.q[m];   // cells are unique per list
@@ -73,12 +39,6 @@ struct Global2D {
     const float* f;
     int nx;
     __device__ float operator()(int i, int j) const { return f[j * nx + i]; }
-};
-
-struct Global3D {
-    const float* f;
-    int nx, ny;
-    __device__ float operator()(int i, int j, int l) const { return f[(l * ny + j) * nx + i]; }
 };
 
 __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __restrict__ f0,
@@ -106,40 +66,6 @@ __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __res
     c.pos[2 * i] = x;
     c.pos[2 * i + 1] = y;
     c.dir[i] = th;
-    if (ev.status != kActive) {
-        c.status[i] = ev.status;
-        c.target[i] = ev.target;
-        c.event_step[i] = (int32_t)(step + 1);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_cones3d(ConeRules r, const float* __restrict__ f0,
-                                                 const float* __restrict__ f1, ConeArrays c,
-                                                 uint32_t step) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= c.n || c.status[i] != kActive) return;
-    float x = c.pos[3 * i], y = c.pos[3 * i + 1], z = c.pos[3 * i + 2];
-    float hx = c.dir[3 * i], hy = c.dir[3 * i + 1], hz = c.dir[3 * i + 2];
-    float gx, gy, gz;
-    gradient_3d(Global3D{f0, r.nx, r.ny}, r, x, y, z, gx, gy, gz);
-    gx *= r.sign0;
-    gy *= r.sign0;
-    gz *= r.sign0;
-    if (r.n_species > 1) {
-        float ax, ay, az;
-        gradient_3d(Global3D{f1, r.nx, r.ny}, r, x, y, z, ax, ay, az);
-        gx = fmaf(r.sign1, ax, gx);
-        gy = fmaf(r.sign1, ay, gy);
-        gz = fmaf(r.sign1, az, gz);
-    }
-    const ConeEvent ev = cone_step_3d(r, gx, gy, gz, (uint32_t)i, step, x, y, z, hx, hy, hz,
-                                      GridContact{&r.targets});
-    c.pos[3 * i] = x;
-    c.pos[3 * i + 1] = y;
-    c.pos[3 * i + 2] = z;
-    c.dir[3 * i] = hx;
-    c.dir[3 * i + 1] = hy;
-    c.dir[3 * i + 2] = hz;
     if (ev.status != kActive) {
         c.status[i] = ev.status;
         c.target[i] = ev.target;
@@ -184,20 +110,11 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_final(const double* __res
 
 }  // namespace
 
-hipError_t launch_field_plain(int dim, int nx, int ny, int nz, const float* in, float* out,
-                              StencilCoef coef, hipStream_t stream, hipEvent_t start,
-                              hipEvent_t stop) {
+hipError_t launch_field2d(int nx, int ny, const float* in, float* out, StencilCoef coef,
+                          hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
     const int bx = (nx + kRowThreads - 1) / kRowThreads;
-    if (dim == 2)
-        hipExtLaunchKernelGGL(k_field2d, dim3(bx, ny), dim3(kRowThreads), 0, stream, start,
-                              stop, 0, in, out, nx, ny, coef);
-    else
-        hipExtLaunchKernelGGL(k_field3d_stream,
-                              dim3((nx + kStreamX - 1) / kStreamX,
-                                   (ny + kStreamY - 1) / kStreamY,
-                                   (nz + kStreamZ - 1) / kStreamZ),
-                              dim3(kStreamX * kStreamY), 0, stream, start, stop, 0, in, out,
-                              nx, ny, nz, coef);
+    hipExtLaunchKernelGGL(k_field2d, dim3(bx, ny), dim3(kRowThreads), 0, stream, start, stop,
+                          0, in, out, nx, ny, coef);
     return hipGetLastError();
 }
 
@@ -207,17 +124,11 @@ hipError_t launch_sources(float* field, SourceList src, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_cones_plain(int dim, const ConeRules& rules, const float* f0,
-                              const float* f1, ConeArrays cones, uint32_t step,
-                              hipStream_t stream) {
+hipError_t launch_cones2d(const ConeRules& rules, const float* f0, const float* f1,
+                          ConeArrays cones, uint32_t step, hipStream_t stream) {
     if (cones.n == 0) return hipSuccess;
-    const int blocks = (cones.n + 255) / 256;
-    if (dim == 2)
-        hipLaunchKernelGGL(k_cones2d, dim3(blocks), dim3(256), 0, stream, rules, f0, f1, cones,
-                           step);
-    else
-        hipLaunchKernelGGL(k_cones3d, dim3(blocks), dim3(256), 0, stream, rules, f0, f1, cones,
-                           step);
+    hipLaunchKernelGGL(k_cones2d, dim3((cones.n + 255) / 256), dim3(256), 0, stream, rules, f0,
+                       f1, cones, step);
     return hipGetLastError();
 }
 

@@ -76,7 +76,9 @@ struct sim_handle {
     TiledState tiled = {};
     bool cones_bucketed = false;   // active cones live in the tile buckets
 
-    // 3D: active cones in spatial order, refreshed every kOrderRefresh steps
+    // 3D: field step with its per-box source lists; active cones in spatial order,
+    // refreshed every kOrderRefresh steps
+    Field3D field3d = {};
     ConeOrder3D order3d = {};
     bool cones_ordered = false;    // tips and headings of active cones live in order3d
     int since_refresh = 0;
@@ -88,6 +90,8 @@ struct sim_handle {
     // caller-order inputs the adjoint needs
     std::vector<float> target_host;                          // [T][dim]
     std::vector<int32_t> src_caller_cell[SIM_MAX_SPECIES];   // per source, caller order
+    std::vector<int32_t> src_merged_cell[SIM_MAX_SPECIES];   // merged, sorted by cell
+    std::vector<float> src_merged_q[SIM_MAX_SPECIES];        // their amounts / dx^dim
     AdjointRun* adj = nullptr;
     GraphBuffers graph = {};                                 // last sim_connectivity
     int graph_cones = 0;
@@ -203,6 +207,7 @@ void release(sim_handle* h) {
     dfree(h->mass_out);
     tiled_release(h->tiled);
     order3d_release(h->order3d);
+    field3d_release(h->field3d);
     drop_events(h);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     h->stream = nullptr;
@@ -364,6 +369,8 @@ sim_status upload_sources(sim_handle* h, const sim_params* p, int s) {
         q.push_back((float)kv.second);
     }
     h->n_src[s] = (int)cells.size();
+    h->src_merged_cell[s] = cells;
+    h->src_merged_q[s] = q;
     HIP_TRY(h, dalloc(&h->src_cell[s], cells.size()));
     HIP_TRY(h, dalloc(&h->src_q[s], q.size()));
     if (!cells.empty()) {
@@ -434,23 +441,38 @@ sim_status collect_timing(sim_handle* h) {
     return SIM_OK;
 }
 
-// One un-blocked step: stencil, sources, cones.
+// One un-blocked step.  2D: stencil and sources per species, then the cones in caller order.
+// 3D: one launch for the stencil and sources of every species, then the cones in spatial
+// order.
 sim_status plain_step(sim_handle* h) {
-    for (int s = 0; s < h->n_species; ++s) {
-        const float* in = h->field[s][h->cur[s]];
-        float* out = h->field[s][h->cur[s] ^ 1];
-        hipEvent_t t0, t1;
-        sim_status st = timing_events(h, &t0, &t1);
-        if (st != SIM_OK) return st;
-        HIP_TRY(h, launch_field_plain(h->dim, h->nx, h->ny, h->nz, in, out, h->coef[s], h->stream,
-                                      t0, t1));
-        HIP_TRY(h, launch_sources(out, SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
-                                  h->stream));
-        h->cur[s] ^= 1;
+    hipEvent_t t0, t1;
+    sim_status st = SIM_OK;
+    if (h->dim == 3) {
+        const float* in[SIM_MAX_SPECIES] = {};
+        float* out[SIM_MAX_SPECIES] = {};
+        for (int s = 0; s < h->n_species; ++s) {
+            in[s] = h->field[s][h->cur[s]];
+            out[s] = h->field[s][h->cur[s] ^ 1];
+        }
+        if ((st = timing_events(h, &t0, &t1)) != SIM_OK) return st;
+        HIP_TRY(h, launch_field3d(h->field3d, in, out, h->coef, h->stream, t0, t1));
+        for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
+    } else {
+        for (int s = 0; s < h->n_species; ++s) {
+            const float* in = h->field[s][h->cur[s]];
+            float* out = h->field[s][h->cur[s] ^ 1];
+            if ((st = timing_events(h, &t0, &t1)) != SIM_OK) return st;
+            HIP_TRY(h, launch_field2d(h->nx, h->ny, in, out, h->coef[s], h->stream, t0, t1));
+            HIP_TRY(h, launch_sources(out, SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
+                                      h->stream));
+            h->cur[s] ^= 1;
+        }
     }
     const float* f0 = h->field[0][h->cur[0]];
     const float* f1 = h->n_species > 1 ? h->field[1][h->cur[1]] : f0;
-    if (h->order3d.n > 0) {
+    if (h->dim == 2) {
+        HIP_TRY(h, launch_cones2d(h->rules, f0, f1, h->cones, (uint32_t)h->step, h->stream));
+    } else if (h->order3d.n > 0) {
         if (!h->cones_ordered) {
             HIP_TRY(h, order3d_begin(h->order3d, h->rules, h->cones, h->stream));
             h->cones_ordered = true;
@@ -462,9 +484,6 @@ sim_status plain_step(sim_handle* h) {
         HIP_TRY(h, launch_cones3d_ordered(h->rules, f0, f1, h->order3d, h->cones,
                                           (uint32_t)h->step, h->stream));
         h->since_refresh += 1;
-    } else {
-        HIP_TRY(h, launch_cones_plain(h->dim, h->rules, f0, f1, h->cones, (uint32_t)h->step,
-                                      h->stream));
     }
     h->step += 1;
     return SIM_OK;
@@ -586,6 +605,11 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
             (e = hipMemcpy(h->cones.target, minus1.data(), M * 4, hipMemcpyHostToDevice)) ||
             (e = hipMemcpy(h->cones.event_step, minus1.data(), M * 4, hipMemcpyHostToDevice)))
             return bail(device_fail(h, e, "cone upload"));
+    }
+    if (p->dim == 3) {
+        e = field3d_prepare(h->field3d, h->nx, h->ny, h->nz, h->n_species, h->src_merged_cell,
+                            h->src_merged_q);
+        if (e != hipSuccess) return bail(device_fail(h, e, "3D field set-up"));
     }
     if (p->dim == 3 && M > 0) {
         e = order3d_allocate(h->order3d, p->n_cones, h->nx, h->ny, h->nz);
@@ -1137,15 +1161,15 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         for (int t = 0; t < len; ++t) {
             ADJ_TRY(launch_record_cones2d(work, tape_cones + (size_t)t * Ms, h->stream));
             for (int s = 0; s < ns; ++s) {
-                ADJ_TRY(launch_field_plain(2, nx, ny, 1, field_at(t, s), field_at(t + 1, s),
-                                           h->coef[s], h->stream));
+                ADJ_TRY(launch_field2d(nx, ny, field_at(t, s), field_at(t + 1, s), h->coef[s],
+                                       h->stream));
                 ADJ_TRY(launch_sources(field_at(t + 1, s),
                                        SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
                                        h->stream));
             }
-            ADJ_TRY(launch_cones_plain(2, h->rules, field_at(t + 1, 0),
-                                       field_at(t + 1, ns > 1 ? 1 : 0), work,
-                                       (uint32_t)(seg0 + t), h->stream));
+            ADJ_TRY(launch_cones2d(h->rules, field_at(t + 1, 0),
+                                   field_at(t + 1, ns > 1 ? 1 : 0), work, (uint32_t)(seg0 + t),
+                                   h->stream));
         }
         // reverse the segment's steps
         for (int t = len - 1; t >= 0; --t) {

@@ -126,7 +126,7 @@ def test_torch_autograd_function():
     with B.Simulation(sc) as sim:
         L = sim.adjoint(40, assign, w, 16)
         dq, dD, dk = sim.adjoint_backward()
-    assert abs(float(loss) - L) <= 1e-12 * L
+    assert abs(float(loss.detach()) - L) <= 1e-12 * L
     np.testing.assert_allclose(q.grad.numpy(), 2.0 * dq, rtol=1e-5, atol=1e-9 * np.abs(dq).max())
     np.testing.assert_allclose(D.grad.numpy(), 2.0 * dD, rtol=1e-5)
     np.testing.assert_allclose(k.grad.numpy(), 2.0 * dk, rtol=1e-5)

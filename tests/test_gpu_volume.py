@@ -100,3 +100,19 @@ def test_ordered_cones_state_write_restarts_order():
     assert (moved > 0).all()   # the reactivated cones were stepped
     sim.close()
     fresh.close()
+
+
+@pytest.mark.parametrize("shape", [(70, 9, 37), (2, 2, 2), (65, 5, 33)])
+def test_field3d_ragged_boxes_and_dense_sources(shape):
+    """The one-launch 3D field step on grids that end inside a box on every axis (x past a
+    64-column tile, y past a 4-row tile, z past a 32-plane chunk and a 4-plane group), with
+    hundreds of sources per species so that boxes hold many (some cells drawn twice)."""
+    n = shape[0] * shape[1] * shape[2]
+    sc = S.make_scenario("3d field", 3, shape, 1.0, 0.15,
+                         ((1.0, 0.01, 1.0), (0.5, 0.02, -1.0)), [min(300, 2 * n)] * 2,
+                         (0.5, 2.0), 0, 0, seed=21)
+    _say(f"3D field {shape}, {len(sc.species[0].source_q)} sources per species, 40 steps")
+    run = parity.FullRun(sc, 1)
+    run.advance(20, where="step 20")
+    run.advance(20, where="step 40")
+    run.sim.close()
