@@ -229,33 +229,58 @@ __device__ __forceinline__ void gradient_2d(const F& f, const ConeRules& r, floa
     if (value) *value = w00 * a1 + w10 * a2 + w01 * b1 + w11 * b2;
 }
 
-template <class F>
-__device__ __forceinline__ void gradient_3d(const F& f, const ConeRules& r, float x, float y,
-                                            float z, float& gx, float& gy, float& gz) {
-    int i0, j0, l0;
+// The footprint of the interpolated 3D gradient: the lower corner (i0, j0, l0) of the 2x2x2
+// cell-centre block around the tip, the fractions along each axis, and the clamped indices
+// one beyond each face (ghost = own value at a wall).
+struct Corner3D {
+    int i0, j0, l0, im, ip, jm, jp, lm, lp;
     float fx, fy, fz;
-    corner(x, r.inv_dx, r.nx, i0, fx);
-    corner(y, r.inv_dx, r.ny, j0, fy);
-    corner(z, r.inv_dx, r.nz, l0, fz);
-    // The 32 distinct cells of the footprint: the 2x2x2 corner block and, beyond each of its
-    // faces, the 2x2 cells one further out (clamped at walls: ghost = own value).
-    const int im = max(i0 - 1, 0), ip = min(i0 + 2, r.nx - 1);
-    const int jm = max(j0 - 1, 0), jp = min(j0 + 2, r.ny - 1);
-    const int lm = max(l0 - 1, 0), lp = min(l0 + 2, r.nz - 1);
+};
+
+// The 32 distinct cells of the footprint: the 2x2x2 corner block and, beyond each of its
+// faces, the 2x2 cells one further out.
+struct Footprint3D {
     float blk[2][2][2], xm[2][2], xp[2][2], ym[2][2], yp[2][2], zm[2][2], zp[2][2];
+};
+
+__device__ __forceinline__ Corner3D corner_3d(const ConeRules& r, float x, float y, float z) {
+    Corner3D k;
+    corner(x, r.inv_dx, r.nx, k.i0, k.fx);
+    corner(y, r.inv_dx, r.ny, k.j0, k.fy);
+    corner(z, r.inv_dx, r.nz, k.l0, k.fz);
+    k.im = max(k.i0 - 1, 0);
+    k.ip = min(k.i0 + 2, r.nx - 1);
+    k.jm = max(k.j0 - 1, 0);
+    k.jp = min(k.j0 + 2, r.ny - 1);
+    k.lm = max(k.l0 - 1, 0);
+    k.lp = min(k.l0 + 2, r.nz - 1);
+    return k;
+}
+
+template <class F>
+__device__ __forceinline__ Footprint3D load_footprint_3d(const F& f, const Corner3D& k) {
+    Footprint3D p;
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            blk[0][b][c] = f(i0, j0 + b, l0 + c);
-            blk[1][b][c] = f(i0 + 1, j0 + b, l0 + c);
-            xm[b][c] = f(im, j0 + b, l0 + c);
-            xp[b][c] = f(ip, j0 + b, l0 + c);
-            ym[b][c] = f(i0 + b, jm, l0 + c);      // [x offset][z offset]
-            yp[b][c] = f(i0 + b, jp, l0 + c);
-            zm[b][c] = f(i0 + b, j0 + c, lm);      // [x offset][y offset]
-            zp[b][c] = f(i0 + b, j0 + c, lp);
+            p.blk[0][b][c] = f(k.i0, k.j0 + b, k.l0 + c);
+            p.blk[1][b][c] = f(k.i0 + 1, k.j0 + b, k.l0 + c);
+            p.xm[b][c] = f(k.im, k.j0 + b, k.l0 + c);
+            p.xp[b][c] = f(k.ip, k.j0 + b, k.l0 + c);
+            p.ym[b][c] = f(k.i0 + b, k.jm, k.l0 + c);      // [x offset][z offset]
+            p.yp[b][c] = f(k.i0 + b, k.jp, k.l0 + c);
+            p.zm[b][c] = f(k.i0 + b, k.j0 + c, k.lm);      // [x offset][y offset]
+            p.zp[b][c] = f(k.i0 + b, k.j0 + c, k.lp);
         }
+    return p;
+}
+
+// Trilinear interpolation of the central differences at the eight corners.
+__device__ __forceinline__ void gradient_from_3d(const ConeRules& r, const Corner3D& k,
+                                                 const Footprint3D& p, float& gx, float& gy,
+                                                 float& gz) {
+    const float fx = k.fx, fy = k.fy, fz = k.fz;
     gx = gy = gz = 0.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -265,9 +290,9 @@ __device__ __forceinline__ void gradient_3d(const F& f, const ConeRules& r, floa
             for (int c = 0; c < 2; ++c) {
                 const float w = (a ? fx : 1.0f - fx) * (b ? fy : 1.0f - fy) * (c ? fz : 1.0f - fz);
                 // central differences at corner (i0+a, j0+b, l0+c)
-                const float ex = (a ? xp[b][c] : blk[1][b][c]) - (a ? blk[0][b][c] : xm[b][c]);
-                const float ey = (b ? yp[a][c] : blk[a][1][c]) - (b ? blk[a][0][c] : ym[a][c]);
-                const float ez = (c ? zp[a][b] : blk[a][b][1]) - (c ? blk[a][b][0] : zm[a][b]);
+                const float ex = (a ? p.xp[b][c] : p.blk[1][b][c]) - (a ? p.blk[0][b][c] : p.xm[b][c]);
+                const float ey = (b ? p.yp[a][c] : p.blk[a][1][c]) - (b ? p.blk[a][0][c] : p.ym[a][c]);
+                const float ez = (c ? p.zp[a][b] : p.blk[a][b][1]) - (c ? p.blk[a][b][0] : p.zm[a][b]);
                 gx += w * ex;
                 gy += w * ey;
                 gz += w * ez;
@@ -275,6 +300,13 @@ __device__ __forceinline__ void gradient_3d(const F& f, const ConeRules& r, floa
     gx *= r.half_inv_dx;
     gy *= r.half_inv_dx;
     gz *= r.half_inv_dx;
+}
+
+template <class F>
+__device__ __forceinline__ void gradient_3d(const F& f, const ConeRules& r, float x, float y,
+                                            float z, float& gx, float& gy, float& gz) {
+    const Corner3D k = corner_3d(r, x, y, z);
+    gradient_from_3d(r, k, load_footprint_3d(f, k), gx, gy, gz);
 }
 
 struct ConeEvent {

@@ -90,7 +90,10 @@ struct Global3D {
 
 // One step of every ordered cone against the updated fields.  Workgroup w of the launch
 // takes the w-th block of kThreads cones counted die by die, so each die works through one
-// contiguous stretch of the order and its L2 holds that region of the fields.
+// contiguous stretch of the order and its L2 holds that region of the fields.  (Loading
+// both species' footprints before combining either was measured slower: the wider register
+// live range costs more than the extra loads in flight gain.)
+template <int NS>
 __global__ __launch_bounds__(kThreads) void k_cones3d_ordered(ConeRules r,
                                                               const float* __restrict__ f0,
                                                               const float* __restrict__ f1,
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void k_cones3d_ordered(ConeRules r,
     gx *= r.sign0;
     gy *= r.sign0;
     gz *= r.sign0;
-    if (r.n_species > 1) {
+    if (NS > 1) {
         float ax, ay, az;
         gradient_3d(Global3D{f1, r.nx, r.ny}, r, x, y, z, ax, ay, az);
         gx = fmaf(r.sign1, ax, gx);
@@ -239,8 +242,14 @@ hipError_t launch_cones3d_ordered(const ConeRules& r, const float* f0, const flo
     if (o.n == 0) return hipSuccess;
     const int blocks = blocks_for(o.n);
     const int per_xcd = (blocks + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL(k_cones3d_ordered, dim3(per_xcd * kXcds), dim3(kThreads), 0, stream, r,
-                       f0, f1, o.tip[o.cur], o.dir[o.cur], o.n, per_xcd, cones, step);
+    if (r.n_species > 1)
+        hipLaunchKernelGGL(k_cones3d_ordered<2>, dim3(per_xcd * kXcds), dim3(kThreads), 0,
+                           stream, r, f0, f1, o.tip[o.cur], o.dir[o.cur], o.n, per_xcd, cones,
+                           step);
+    else
+        hipLaunchKernelGGL(k_cones3d_ordered<1>, dim3(per_xcd * kXcds), dim3(kThreads), 0,
+                           stream, r, f0, f1, o.tip[o.cur], o.dir[o.cur], o.n, per_xcd, cones,
+                           step);
     return hipGetLastError();
 }
 

@@ -3,13 +3,14 @@
 // 7-point stencil with first-order decay, zero-flux walls (a missing neighbour is the cell
 // itself), then the point sources of the step (c' += q / dx^3).  One launch covers every
 // species.  A workgroup owns a box of kTX x kTY columns and kTZ consecutive planes of one
-// species and marches up the planes; each thread keeps the planes below, at and above its
-// cell in registers and reads the four in-plane neighbours from lines the workgroup has just
-// brought into L1/L2, so a cell is fetched from HBM about once per step: 8 algorithmic bytes
-// per species-cell-update.  Planes are taken kUnroll at a time with every load of the group
-// issued before the arithmetic, which keeps kUnroll times more reads in flight than a
-// plane-by-plane march.  Walls are handled by clamping the neighbour index, which reads the
-// cell itself exactly where the ghost value is the cell's own.
+// species (64 x 8 x 16, the fastest of the shapes measured) and marches up the planes; each
+// thread keeps the planes below, at and above its cell in registers and reads the four
+// in-plane neighbours from lines the workgroup has just brought into L1/L2, so a cell is
+// fetched from HBM about once per step: 8 algorithmic bytes per species-cell-update.
+// Planes are taken kUnroll at a time with every load of the group issued before the
+// arithmetic, which keeps kUnroll times more reads in flight than a plane-by-plane march.
+// Walls are handled by clamping the neighbour index, which reads the cell itself exactly
+// where the ghost value is the cell's own.
 //
 // Boxes are dealt to the accelerator dies in contiguous stretches (workgroups are assigned
 // to dies round-robin), so boxes that share halo rows usually share an L2.
@@ -28,7 +29,7 @@ namespace cuesim {
 
 namespace {
 
-constexpr int kTX = 64, kTY = 4, kTZ = 32, kUnroll = 4;
+constexpr int kTX = 64, kTY = 8, kTZ = 16, kUnroll = 4;
 constexpr int kThreads = kTX * kTY;
 constexpr int kXcds = 8;
 
