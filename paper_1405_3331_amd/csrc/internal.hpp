@@ -108,19 +108,23 @@ hipError_t order3d_end(const ConeOrder3D& o, ConeArrays cones, hipStream_t strea
 
 // Reverse pass of the 2D step (kernels_adjoint.hip).  Field adjoint grids have
 // adjoint_field_blocks(nx, ny) workgroups, each owning one slot of acc_D / acc_k.
+// A segment's fields are `fields + (t * n_species + s) * cells` for t = 0..len.
 int adjoint_field_blocks(int nx, int ny);
 int adjoint_cone_blocks(int n);
-hipError_t launch_cone_adjoint2d(int n_species, const ConeRules& rules, const float* f0,
-                                 const float* f1, float* af0, float* af1, const float4* state,
-                                 const int32_t* status, const int32_t* event_step,
-                                 uint32_t step, float* acone, int n, hipStream_t stream);
-hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* c,
-                                  float* a_out, StencilCoef coef, double* acc_D,
+hipError_t launch_cones_segment2d(const ConeRules& rules, const float* fields, size_t cells,
+                                  int n_species, uint32_t seg0, int len, ConeArrays cones,
+                                  float4* tape, hipStream_t stream);
+hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fields,
+                                         size_t cells, int n_species, uint32_t seg0, int len,
+                                         float* e, const float4* tape, const int32_t* status,
+                                         const int32_t* event_step, float* acone, int n,
+                                         hipStream_t stream);
+hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* e_in,
+                                  const float* c, float* a_out, StencilCoef coef, double* acc_D,
                                   double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
                                   hipStream_t stream);
 hipError_t launch_adjoint_seed2d(const float* pos, const float* tip_target, const float* weight,
                                  float* acone, double* partial, int n, hipStream_t stream);
-hipError_t launch_record_cones2d(ConeArrays cones, float4* out, hipStream_t stream);
 
 // Adjacency list of the connections and its breadth-first levels (kernels_graph.hip).
 struct GraphBuffers {

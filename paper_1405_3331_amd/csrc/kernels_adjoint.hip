@@ -3,16 +3,22 @@
 //
 // The derivative is taken along the forward run's branch: the exit and contact decisions
 // and the active side of the turn cap are held as the forward run took them (the cone
-// rules of Sec. 3.4-3.5 have no derivative at those switches).  One reverse step n
-// (reverse of: fields c^n -> c^{n+1}, then cones against c^{n+1}) is
-//   k_cone_adjoint2d   adjoints of each cone's (p, theta) through advance, capped turn and
-//                      interpolated gradient; the gradient sample's adjoint is scattered
-//                      into a^{n+1}, the field adjoint (12 cells per species per cone);
-//   k_field_adjoint2d  a^n = a^{n+1} + r Lap a^{n+1} - k dt a^{n+1} (the zero-flux
-//                      Laplacian is symmetric, so the adjoint stencil is the stencil), and
-//                      per-workgroup FP64 sums of a^{n+1} Lap c^n (for dL/dD) and
-//                      a^{n+1} c^n (for dL/dk) plus a^{n+1} at every source cell (dL/dq).
-// HBM bytes per cell of the reverse field step: a^{n+1} read, c^n read, a^n written (12 B).
+// rules of Sec. 3.4-3.5 have no derivative at those switches).
+//
+// The fields never depend on the cones, so within a checkpoint segment the cones can be
+// handled apart from the fields, each cone by one thread over all the segment's steps:
+//   k_cones_segment2d         re-runs the segment's cone steps against the re-run fields and
+//                             records (x, y, theta) of every cone at the start of each step;
+//   k_cone_adjoint_segment2d  walks the steps backwards carrying each cone's adjoint of
+//                             (p, theta) through advance, capped turn and interpolated
+//                             gradient; the gradient samples' adjoints are scattered into
+//                             e^{n+1}, one buffer per step (12 cells per species per cone);
+//   k_field_adjoint2d         one launch per step: with b = a^{n+1} + e^{n+1},
+//                             a^n = b + r Lap b - k dt b (the zero-flux Laplacian is
+//                             symmetric, so the adjoint stencil is the stencil), and
+//                             per-workgroup FP64 sums of b Lap c^n (for dL/dD) and b c^n (for
+//                             dL/dk) plus b at every source cell (dL/dq).
+// HBM bytes per cell of the reverse field step: a^{n+1}, e^{n+1} and c^n read, a^n written.
 #include "internal.hpp"
 
 namespace cuesim {
@@ -20,6 +26,7 @@ namespace cuesim {
 namespace {
 
 constexpr int kAdjThreads = 256;
+constexpr int kSegThreads = 64;   // segment kernels: one short wave per CU where possible
 
 __device__ double adj_block_sum(double v) {
     __shared__ double part[kAdjThreads / 64];
@@ -94,20 +101,15 @@ struct Field2D {
     __device__ float operator()(int i, int j) const { return f[j * nx + i]; }
 };
 
-// Reverse of one cone step (step index `step`) for every cone still active at its start;
-// state holds (x, y, theta) at the start of the step, f0/f1 the fields after the step's
-// field update; acone holds (a_x, a_y, a_theta) of the state after the step on entry and
-// of the state before it on exit.
+// Reverse of one cone step (step index `step`) of cone i from its state (x, y, theta) at
+// the start of the step; f0/f1 are the fields after the step's field update and af0/af1
+// receive the adjoints of their sampled values.  (apx, apy, ath) holds the adjoint of the
+// state after the step on entry and of the state before it on exit.
 template <int NS>
-__global__ __launch_bounds__(kAdjThreads) void k_cone_adjoint2d(
-    ConeRules r, const float* __restrict__ f0, const float* __restrict__ f1,
-    float* __restrict__ af0, float* __restrict__ af1, const float4* __restrict__ state,
-    const int32_t* __restrict__ status, const int32_t* __restrict__ event_step,
-    uint32_t step, float* __restrict__ acone, int n) {
-    const int i = blockIdx.x * kAdjThreads + threadIdx.x;
-    if (i >= n) return;
-    if (status[i] != kActive && event_step[i] <= (int32_t)step) return;   // frozen by then
-    const float4 st = state[i];
+__device__ __forceinline__ void cone_adjoint_step(const ConeRules& r, const float* f0,
+                                                  const float* f1, float* af0, float* af1,
+                                                  float4 st, int i, uint32_t step, float& apx,
+                                                  float& apy, float& ath) {
     const float x = st.x, y = st.y, th = st.z;
     // forward quantities, computed exactly as the forward step computes them
     float gx, gy;
@@ -137,10 +139,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_cone_adjoint2d(
     sincosf(thn, &sn, &cn);
 
     // reverse: p' = p + s (cos theta', sin theta')
-    float apx = acone[3 * i], apy = acone[3 * i + 1];
-    const float athn = acone[3 * i + 2] + r.step_len * (cn * apy - sn * apx);
+    const float athn = ath + r.step_len * (cn * apy - sn * apx);
     // theta' = theta + turn(theta, g) + noise
-    float ath = athn;
+    ath = athn;
     float agx = 0.0f, agy = 0.0f;
     if (!capped) {
         const float den = along * along + cross * cross;
@@ -152,6 +153,77 @@ __global__ __launch_bounds__(kAdjThreads) void k_cone_adjoint2d(
     }
     gradient_2d_reverse(f0, af0, r, x, y, r.sign0 * agx, r.sign0 * agy, apx, apy);
     if (NS > 1) gradient_2d_reverse(f1, af1, r, x, y, r.sign1 * agx, r.sign1 * agy, apx, apy);
+}
+
+// A checkpoint segment of `len` steps from step seg0: fields[t] (species-major, `cells`
+// each) is the field state after t steps of the segment, t = 0..len.
+struct Segment2D {
+    const float* fields;
+    size_t cells;
+    int n_species;
+    uint32_t seg0;
+    int len;
+    __device__ const float* field(int t, int s) const {
+        return fields + ((size_t)t * n_species + s) * cells;
+    }
+};
+
+// Forward re-run of one segment's cone steps, one thread per cone over all the steps; the
+// state at the start of step t goes to tape[t][i] whether or not the cone is still active.
+// Same arithmetic as the forward step (gradient, turn, noise, advance, exit, contact).
+template <int NS>
+__global__ __launch_bounds__(kSegThreads) void k_cones_segment2d(ConeRules r, Segment2D seg,
+                                                                 ConeArrays c,
+                                                                 float4* __restrict__ tape) {
+    const int i = blockIdx.x * kSegThreads + threadIdx.x;
+    if (i >= c.n) return;
+    float x = c.pos[2 * i], y = c.pos[2 * i + 1], th = c.dir[i];
+    int status = c.status[i];
+    for (int t = 0; t < seg.len; ++t) {
+        tape[(size_t)t * c.n + i] = make_float4(x, y, th, 0.0f);
+        if (status != kActive) continue;
+        const float* f0 = seg.field(t + 1, 0);
+        float gx, gy;
+        gradient_2d(Field2D{f0, r.nx}, r, x, y, gx, gy);
+        gx *= r.sign0;
+        gy *= r.sign0;
+        if (NS > 1) {
+            float hx, hy;
+            gradient_2d(Field2D{seg.field(t + 1, NS - 1), r.nx}, r, x, y, hx, hy);
+            gx = fmaf(r.sign1, hx, gx);
+            gy = fmaf(r.sign1, hy, gy);
+        }
+        float sn, cs;
+        sincosf(th, &sn, &cs);
+        float z[2];
+        noise_2d(r.key, (uint32_t)i, seg.seg0 + (uint32_t)t, z);
+        const ConeEvent ev = cone_step_2d(r, gx, gy, 0.0f, z, x, y, th, sn, cs,
+                                          GridContact{&r.targets});
+        status = ev.status;
+    }
+}
+
+// Reverse of one segment's cone steps, one thread per cone from the last step to the first.
+// status/event_step are the final ones of the run: a cone stopped at step n takes part in
+// steps < n only.  The adjoint of the sample of step t goes to e + t * n_species * cells.
+template <int NS>
+__global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
+    ConeRules r, Segment2D seg, float* __restrict__ e, const float4* __restrict__ tape,
+    const int32_t* __restrict__ status, const int32_t* __restrict__ event_step,
+    float* __restrict__ acone, int n) {
+    const int i = blockIdx.x * kSegThreads + threadIdx.x;
+    if (i >= n) return;
+    // steps < last take part (all steps when the cone is still active)
+    const int64_t last = status[i] == kActive ? INT64_MAX : (int64_t)event_step[i];
+    float apx = acone[3 * i], apy = acone[3 * i + 1], ath = acone[3 * i + 2];
+    for (int t = seg.len - 1; t >= 0; --t) {
+        const uint32_t step = seg.seg0 + (uint32_t)t;
+        if ((int64_t)step >= last) continue;
+        float* et = e + (size_t)t * seg.n_species * seg.cells;
+        cone_adjoint_step<NS>(r, seg.field(t + 1, 0), seg.field(t + 1, NS - 1), et,
+                              et + (NS - 1) * seg.cells, tape[(size_t)t * n + i], i, step, apx,
+                              apy, ath);
+    }
     acone[3 * i] = apx;
     acone[3 * i + 1] = apy;
     acone[3 * i + 2] = ath;
@@ -160,19 +232,21 @@ __global__ __launch_bounds__(kAdjThreads) void k_cone_adjoint2d(
 // Reverse field step of one species (see the file comment).  The grid is the same every
 // step, so workgroup b owns slots acc_D[b] and acc_k[b] and adds its partial sums there.
 __global__ __launch_bounds__(kAdjThreads) void k_field_adjoint2d(
-    const float* __restrict__ a_in, const float* __restrict__ c, float* __restrict__ a_out,
-    int nx, int ny, StencilCoef coef, double* __restrict__ acc_D, double* __restrict__ acc_k,
-    const int32_t* __restrict__ q_cell, int n_q, double* __restrict__ acc_q) {
+    const float* __restrict__ a_in, const float* __restrict__ e_in, const float* __restrict__ c,
+    float* __restrict__ a_out, int nx, int ny, StencilCoef coef, double* __restrict__ acc_D,
+    double* __restrict__ acc_k, const int32_t* __restrict__ q_cell, int n_q,
+    double* __restrict__ acc_q) {
     const int i = blockIdx.x * kAdjThreads + threadIdx.x;
     const int j = blockIdx.y;
     double pD = 0.0, pk = 0.0;
+    auto total = [&](int at) { return a_in[at] + e_in[at]; };
     if (i < nx) {
         const int at = j * nx + i;
-        const float a = a_in[at];
-        const float aw = i > 0 ? a_in[at - 1] : a;
-        const float ae = i < nx - 1 ? a_in[at + 1] : a;
-        const float as = j > 0 ? a_in[at - nx] : a;
-        const float an = j < ny - 1 ? a_in[at + nx] : a;
+        const float a = total(at);
+        const float aw = i > 0 ? total(at - 1) : a;
+        const float ae = i < nx - 1 ? total(at + 1) : a;
+        const float as = j > 0 ? total(at - nx) : a;
+        const float an = j < ny - 1 ? total(at + nx) : a;
         const float lap_a = ((aw + ae) + (as + an)) - 4.0f * a;
         a_out[at] = fmaf(coef.r, lap_a, fmaf(-coef.kdt, a, a));
         const float v = c[at];
@@ -192,7 +266,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_field_adjoint2d(
         acc_k[b] += sk;
     }
     if (b == 0)
-        for (int m = threadIdx.x; m < n_q; m += kAdjThreads) acc_q[m] += (double)a_in[q_cell[m]];
+        for (int m = threadIdx.x; m < n_q; m += kAdjThreads) acc_q[m] += (double)total(q_cell[m]);
 }
 
 // Loss at the final tips and the seed of the cone adjoints: a_p = 2 w (p - t), a_theta = 0.
@@ -215,12 +289,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_seed2d(
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// (x, y, theta) of every cone at the start of a step, for the reverse pass.
-__global__ __launch_bounds__(kAdjThreads) void k_record_cones2d(ConeArrays c,
-                                                                float4* __restrict__ out) {
-    const int i = blockIdx.x * kAdjThreads + threadIdx.x;
-    if (i < c.n) out[i] = make_float4(c.pos[2 * i], c.pos[2 * i + 1], c.dir[i], 0.0f);
-}
 
 }  // namespace
 
@@ -230,28 +298,45 @@ int adjoint_field_blocks(int nx, int ny) {
 
 int adjoint_cone_blocks(int n) { return (n + kAdjThreads - 1) / kAdjThreads; }
 
-hipError_t launch_cone_adjoint2d(int n_species, const ConeRules& rules, const float* f0,
-                                 const float* f1, float* af0, float* af1, const float4* state,
-                                 const int32_t* status, const int32_t* event_step,
-                                 uint32_t step, float* acone, int n, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    const dim3 grid(adjoint_cone_blocks(n));
+hipError_t launch_cones_segment2d(const ConeRules& rules, const float* fields, size_t cells,
+                                  int n_species, uint32_t seg0, int len, ConeArrays cones,
+                                  float4* tape, hipStream_t stream) {
+    if (cones.n == 0 || len == 0) return hipSuccess;
+    const Segment2D seg{fields, cells, n_species, seg0, len};
+    const dim3 grid((cones.n + kSegThreads - 1) / kSegThreads);
     if (n_species > 1)
-        hipLaunchKernelGGL(k_cone_adjoint2d<2>, grid, dim3(kAdjThreads), 0, stream, rules, f0,
-                           f1, af0, af1, state, status, event_step, step, acone, n);
+        hipLaunchKernelGGL(k_cones_segment2d<2>, grid, dim3(kSegThreads), 0, stream, rules, seg,
+                           cones, tape);
     else
-        hipLaunchKernelGGL(k_cone_adjoint2d<1>, grid, dim3(kAdjThreads), 0, stream, rules, f0,
-                           f0, af0, af0, state, status, event_step, step, acone, n);
+        hipLaunchKernelGGL(k_cones_segment2d<1>, grid, dim3(kSegThreads), 0, stream, rules, seg,
+                           cones, tape);
     return hipGetLastError();
 }
 
-hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* c,
-                                  float* a_out, StencilCoef coef, double* acc_D,
+hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fields,
+                                         size_t cells, int n_species, uint32_t seg0, int len,
+                                         float* e, const float4* tape, const int32_t* status,
+                                         const int32_t* event_step, float* acone, int n,
+                                         hipStream_t stream) {
+    if (n == 0 || len == 0) return hipSuccess;
+    const Segment2D seg{fields, cells, n_species, seg0, len};
+    const dim3 grid((n + kSegThreads - 1) / kSegThreads);
+    if (n_species > 1)
+        hipLaunchKernelGGL(k_cone_adjoint_segment2d<2>, grid, dim3(kSegThreads), 0, stream,
+                           rules, seg, e, tape, status, event_step, acone, n);
+    else
+        hipLaunchKernelGGL(k_cone_adjoint_segment2d<1>, grid, dim3(kSegThreads), 0, stream,
+                           rules, seg, e, tape, status, event_step, acone, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* e_in,
+                                  const float* c, float* a_out, StencilCoef coef, double* acc_D,
                                   double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
                                   hipStream_t stream) {
     const dim3 grid((nx + kAdjThreads - 1) / kAdjThreads, ny);
-    hipLaunchKernelGGL(k_field_adjoint2d, grid, dim3(kAdjThreads), 0, stream, a_in, c, a_out,
-                       nx, ny, coef, acc_D, acc_k, q_cell, n_q, acc_q);
+    hipLaunchKernelGGL(k_field_adjoint2d, grid, dim3(kAdjThreads), 0, stream, a_in, e_in, c,
+                       a_out, nx, ny, coef, acc_D, acc_k, q_cell, n_q, acc_q);
     return hipGetLastError();
 }
 
@@ -263,11 +348,5 @@ hipError_t launch_adjoint_seed2d(const float* pos, const float* tip_target, cons
     return hipGetLastError();
 }
 
-hipError_t launch_record_cones2d(ConeArrays cones, float4* out, hipStream_t stream) {
-    if (cones.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_record_cones2d, dim3(adjoint_cone_blocks(cones.n)), dim3(kAdjThreads),
-                       0, stream, cones, out);
-    return hipGetLastError();
-}
 
 }  // namespace cuesim

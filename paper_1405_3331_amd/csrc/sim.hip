@@ -1077,10 +1077,12 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     q_off[1] = n_q[0];
     const int nq_all = n_q[0] + (ns > 1 ? n_q[1] : 0);
 
-    // workspace: one segment of fields and cone states, the recompute's cones, the field
-    // adjoint (ping-pong per species), FP64 accumulators
+    // workspace: one segment of fields, cone states and per-step sample adjoints, the
+    // re-run's cones (tip, heading, status), the field adjoint (ping-pong per species), FP64
+    // accumulators
     float* tape = nullptr;
     float4* tape_cones = nullptr;
+    float* scatter = nullptr;
     ConeArrays work = {};
     float* afield = nullptr;
     double* acc = nullptr;
@@ -1088,11 +1090,10 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     auto free_all = [&]() {
         dfree(tape);
         dfree(tape_cones);
+        dfree(scatter);
         dfree(work.pos);
         dfree(work.dir);
         dfree(work.status);
-        dfree(work.target);
-        dfree(work.event_step);
         dfree(afield);
         dfree(acc);
         dfree(q_cell);
@@ -1101,11 +1102,10 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     const size_t acc_n = (size_t)2 * ns * fb + (size_t)std::max(nq_all, 1);
     if ((e = dalloc(&tape, (size_t)(K + 1) * ns * cells)) != hipSuccess ||
         (e = dalloc(&tape_cones, (size_t)K * std::max<size_t>(Ms, 1))) != hipSuccess ||
+        (e = dalloc(&scatter, (size_t)K * ns * cells)) != hipSuccess ||
         (e = dalloc(&work.pos, Ms * 2)) != hipSuccess ||
         (e = dalloc(&work.dir, Ms)) != hipSuccess ||
         (e = dalloc(&work.status, Ms)) != hipSuccess ||
-        (e = dalloc(&work.target, Ms)) != hipSuccess ||
-        (e = dalloc(&work.event_step, Ms)) != hipSuccess ||
         (e = dalloc(&afield, (size_t)2 * ns * cells)) != hipSuccess ||
         (e = dalloc(&acc, acc_n)) != hipSuccess ||
         (e = dalloc(&q_cell, (size_t)std::max(nq_all, 1))) != hipSuccess) {
@@ -1138,28 +1138,16 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         return st;
     }
     auto field_at = [&](int t, int s) { return tape + ((size_t)t * ns + s) * cells; };
+    auto scatter_at = [&](int t, int s) { return scatter + ((size_t)t * ns + s) * cells; };
     int cur = 0;
     auto afield_at = [&](int s, int half) { return afield + ((size_t)s * 2 + half) * cells; };
     for (int j = a->n_ckpt - 1; j >= 0; --j) {
         const int64_t seg0 = a->n0 + (int64_t)j * a->every;
         const int len = (int)std::min<int64_t>(a->every, a->n_steps - (int64_t)j * a->every);
-        // restore the checkpoint and recompute the segment, recording every step
+        // restore the checkpoint and re-run the segment's fields, keeping every step
         ADJ_TRY(hipMemcpyAsync(tape, a->ckpt_field + (size_t)j * ns * cells,
                                (size_t)ns * cells * 4, hipMemcpyDeviceToDevice, h->stream));
-        if (M > 0) {
-            const int32_t* ci = a->ckpt_int + (size_t)j * 3 * Ms;
-            ADJ_TRY(hipMemcpyAsync(work.pos, a->ckpt_pos + (size_t)j * Ms * 2, Ms * 8,
-                                   hipMemcpyDeviceToDevice, h->stream));
-            ADJ_TRY(hipMemcpyAsync(work.dir, a->ckpt_dir + (size_t)j * Ms, Ms * 4,
-                                   hipMemcpyDeviceToDevice, h->stream));
-            ADJ_TRY(hipMemcpyAsync(work.status, ci, Ms * 4, hipMemcpyDeviceToDevice, h->stream));
-            ADJ_TRY(hipMemcpyAsync(work.target, ci + Ms, Ms * 4, hipMemcpyDeviceToDevice,
-                                   h->stream));
-            ADJ_TRY(hipMemcpyAsync(work.event_step, ci + 2 * Ms, Ms * 4,
-                                   hipMemcpyDeviceToDevice, h->stream));
-        }
-        for (int t = 0; t < len; ++t) {
-            ADJ_TRY(launch_record_cones2d(work, tape_cones + (size_t)t * Ms, h->stream));
+        for (int t = 0; t < len; ++t)
             for (int s = 0; s < ns; ++s) {
                 ADJ_TRY(launch_field2d(nx, ny, field_at(t, s), field_at(t + 1, s), h->coef[s],
                                        h->stream));
@@ -1167,21 +1155,28 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
                                        SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
                                        h->stream));
             }
-            ADJ_TRY(launch_cones2d(h->rules, field_at(t + 1, 0),
-                                   field_at(t + 1, ns > 1 ? 1 : 0), work, (uint32_t)(seg0 + t),
-                                   h->stream));
+        // the segment's cones: forward re-run recording each step's state, then the reverse
+        // carrying the cone adjoints and scattering the samples' adjoints
+        ADJ_TRY(hipMemsetAsync(scatter, 0, (size_t)len * ns * cells * sizeof(float), h->stream));
+        if (M > 0) {
+            const int32_t* ci = a->ckpt_int + (size_t)j * 3 * Ms;
+            ADJ_TRY(hipMemcpyAsync(work.pos, a->ckpt_pos + (size_t)j * Ms * 2, Ms * 8,
+                                   hipMemcpyDeviceToDevice, h->stream));
+            ADJ_TRY(hipMemcpyAsync(work.dir, a->ckpt_dir + (size_t)j * Ms, Ms * 4,
+                                   hipMemcpyDeviceToDevice, h->stream));
+            ADJ_TRY(hipMemcpyAsync(work.status, ci, Ms * 4, hipMemcpyDeviceToDevice, h->stream));
+            ADJ_TRY(launch_cones_segment2d(h->rules, tape, cells, ns, (uint32_t)seg0, len, work,
+                                           tape_cones, h->stream));
+            ADJ_TRY(launch_cone_adjoint_segment2d(h->rules, tape, cells, ns, (uint32_t)seg0, len,
+                                                  scatter, tape_cones, h->cones.status,
+                                                  h->cones.event_step, a->acone, M,
+                                                  h->stream));
         }
-        // reverse the segment's steps
+        // reverse the segment's field steps
         for (int t = len - 1; t >= 0; --t) {
-            ADJ_TRY(launch_cone_adjoint2d(ns, h->rules, field_at(t + 1, 0),
-                                          field_at(t + 1, ns > 1 ? 1 : 0), afield_at(0, cur),
-                                          afield_at(ns > 1 ? 1 : 0, cur),
-                                          tape_cones + (size_t)t * Ms, h->cones.status,
-                                          h->cones.event_step, (uint32_t)(seg0 + t), a->acone,
-                                          M, h->stream));
             for (int s = 0; s < ns; ++s)
-                ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), field_at(t, s),
-                                               afield_at(s, cur ^ 1), h->coef[s],
+                ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), scatter_at(t, s),
+                                               field_at(t, s), afield_at(s, cur ^ 1), h->coef[s],
                                                acc_D + (size_t)s * fb, acc_k + (size_t)s * fb,
                                                q_cell + q_off[s], n_q[s], acc_q + q_off[s],
                                                h->stream));
