@@ -20,11 +20,6 @@ struct StencilCoef {
 };
 
 // Per-species source entries (unique cells, amounts already divided by dx^dim).
-struct SourceList {
-    const int32_t* cell;
-    const float* q;
-    int n;
-};
 
 // Cone state in the caller's order (structure of arrays).
 struct ConeArrays {
@@ -36,15 +31,38 @@ struct ConeArrays {
     int n;
 };
 
-// One 2D step without temporal blocking: stencil of one species (HBM in -> HBM out), then
-// sources, then one thread per cone.  start/stop (may be null): events the launch itself
-// records around the stencil kernel.
-hipError_t launch_field2d(int nx, int ny, const float* in, float* out, StencilCoef coef,
-                          hipStream_t stream, hipEvent_t start = nullptr,
-                          hipEvent_t stop = nullptr);
-hipError_t launch_sources(float* field, SourceList src, hipStream_t stream);
+// One 2D step's cones in the caller's order (kernels_plain.hip).
 hipError_t launch_cones2d(const ConeRules& rules, const float* f0, const float* f1,
                           ConeArrays cones, uint32_t step, hipStream_t stream);
+
+// 2D field step of every species in one launch, sources included (kernels_field2d.hip).
+// Field2DStep holds the per-box source lists (row, column in the box, amount) built once by
+// field2d_prepare from the merged, pre-scaled sources of each species.
+struct Field2DStep {
+    int nx = 0, ny = 0, n_species = 0, n_boxes = 0;
+    int32_t* src_start = nullptr;   // [n_boxes + 1]
+    int32_t* src_row = nullptr;     // per entry: row j
+    int32_t* src_col = nullptr;     // per entry: thread of the box owning the cell
+    float* src_q = nullptr;         // per entry: amount / dx^2
+};
+struct Field2DStepArgs {
+    const float* in[2];
+    float* out[2];
+    StencilCoef coef[2];
+    int nx, ny, n_species;
+    int tx, ty, per_xcd;
+    const int32_t* src_start;
+    const int32_t* src_row;
+    const int32_t* src_col;
+    const float* src_q;
+};
+hipError_t field2d_prepare(Field2DStep& f, int nx, int ny, int n_species,
+                           const std::vector<int32_t>* cells, const std::vector<float>* q);
+void field2d_release(Field2DStep& f);
+// start/stop (may be null): events the launch itself records.
+hipError_t launch_field2d_rows(const Field2DStep& f, const float* const* in, float* const* out,
+                               const StencilCoef* coef, hipStream_t stream,
+                               hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 // 3D field step of every species in one launch, sources included (kernels_field3d.hip).
 // Field3D holds the per-box source lists (plane, thread, amount) built once by

@@ -13,9 +13,10 @@
 //                             (p, theta) through advance, capped turn and interpolated
 //                             gradient; the gradient samples' adjoints are scattered into
 //                             e^{n+1}, one buffer per step (12 cells per species per cone);
-//   k_field_adjoint2d         one launch per step: with b = a^{n+1} + e^{n+1},
-//                             a^n = b + r Lap b - k dt b (the zero-flux Laplacian is
-//                             symmetric, so the adjoint stencil is the stencil), and
+//   k_field_adjoint2d_rows    (kernels_field2d.hip) one launch per step: with
+//                             b = a^{n+1} + e^{n+1}, a^n = b + r Lap b - k dt b (the
+//                             zero-flux Laplacian is symmetric, so the adjoint stencil is
+//                             the stencil), and
 //                             per-workgroup FP64 sums of b Lap c^n (for dL/dD) and b c^n (for
 //                             dL/dk) plus b at every source cell (dL/dq).
 // HBM bytes per cell of the reverse field step: a^{n+1}, e^{n+1} and c^n read, a^n written.
@@ -229,46 +230,6 @@ __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
     acone[3 * i + 2] = ath;
 }
 
-// Reverse field step of one species (see the file comment).  The grid is the same every
-// step, so workgroup b owns slots acc_D[b] and acc_k[b] and adds its partial sums there.
-__global__ __launch_bounds__(kAdjThreads) void k_field_adjoint2d(
-    const float* __restrict__ a_in, const float* __restrict__ e_in, const float* __restrict__ c,
-    float* __restrict__ a_out, int nx, int ny, StencilCoef coef, double* __restrict__ acc_D,
-    double* __restrict__ acc_k, const int32_t* __restrict__ q_cell, int n_q,
-    double* __restrict__ acc_q) {
-    const int i = blockIdx.x * kAdjThreads + threadIdx.x;
-    const int j = blockIdx.y;
-    double pD = 0.0, pk = 0.0;
-    auto total = [&](int at) { return a_in[at] + e_in[at]; };
-    if (i < nx) {
-        const int at = j * nx + i;
-        const float a = total(at);
-        const float aw = i > 0 ? total(at - 1) : a;
-        const float ae = i < nx - 1 ? total(at + 1) : a;
-        const float as = j > 0 ? total(at - nx) : a;
-        const float an = j < ny - 1 ? total(at + nx) : a;
-        const float lap_a = ((aw + ae) + (as + an)) - 4.0f * a;
-        a_out[at] = fmaf(coef.r, lap_a, fmaf(-coef.kdt, a, a));
-        const float v = c[at];
-        const float vw = i > 0 ? c[at - 1] : v;
-        const float ve = i < nx - 1 ? c[at + 1] : v;
-        const float vs = j > 0 ? c[at - nx] : v;
-        const float vn = j < ny - 1 ? c[at + nx] : v;
-        const float lap_c = ((vw + ve) + (vs + vn)) - 4.0f * v;
-        pD = (double)a * (double)lap_c;
-        pk = (double)a * (double)v;
-    }
-    const double sD = adj_block_sum(pD);
-    const double sk = adj_block_sum(pk);
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
-    if (threadIdx.x == 0) {
-        acc_D[b] += sD;
-        acc_k[b] += sk;
-    }
-    if (b == 0)
-        for (int m = threadIdx.x; m < n_q; m += kAdjThreads) acc_q[m] += (double)total(q_cell[m]);
-}
-
 // Loss at the final tips and the seed of the cone adjoints: a_p = 2 w (p - t), a_theta = 0.
 __global__ __launch_bounds__(kAdjThreads) void k_adjoint_seed2d(
     const float* __restrict__ pos, const float* __restrict__ tip_target,
@@ -291,10 +252,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_seed2d(
 
 
 }  // namespace
-
-int adjoint_field_blocks(int nx, int ny) {
-    return ((nx + kAdjThreads - 1) / kAdjThreads) * ny;
-}
 
 int adjoint_cone_blocks(int n) { return (n + kAdjThreads - 1) / kAdjThreads; }
 
@@ -327,16 +284,6 @@ hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fi
     else
         hipLaunchKernelGGL(k_cone_adjoint_segment2d<1>, grid, dim3(kSegThreads), 0, stream,
                            rules, seg, e, tape, status, event_step, acone, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* e_in,
-                                  const float* c, float* a_out, StencilCoef coef, double* acc_D,
-                                  double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
-                                  hipStream_t stream) {
-    const dim3 grid((nx + kAdjThreads - 1) / kAdjThreads, ny);
-    hipLaunchKernelGGL(k_field_adjoint2d, grid, dim3(kAdjThreads), 0, stream, a_in, e_in, c,
-                       a_out, nx, ny, coef, acc_D, acc_k, q_cell, n_q, acc_q);
     return hipGetLastError();
 }
 

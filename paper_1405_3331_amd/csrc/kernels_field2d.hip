@@ -1,0 +1,292 @@
+// kernels_field2d.hip -- one explicit 2D field step per launch (every species, sources
+// included) and its reverse for the gradient sweep, both marching up the rows.
+//
+// A workgroup owns kRX columns x kRY rows of one species; each thread keeps the rows below,
+// at and above its cell in registers and reads its two row neighbours from lines the
+// workgroup has just brought into L1, so a cell is fetched from HBM about once.  Rows are
+// taken kRUnroll at a time with every load of the group issued before the arithmetic.  A
+// missing neighbour at a wall is the cell itself (clamped index).  The stencil expression
+// is term for term the one of the temporally blocked kernel, so both paths give the same
+// bits.  Boxes are dealt to the accelerator dies in contiguous stretches.
+//
+// Step (Sec. 3.4 cue field: diffusion with first-order decay and point sources):
+//   c' = c + r ((w + e) + (s + n) - 4c) - k dt c, then c' += q / dx^2 at each source cell
+//   (a separate FP32 add, the rounding of a source pass), from a per-box list built once.
+// Reverse, with b = a^{n+1} + e^{n+1} (e: the cone samples' adjoints of the step):
+//   a^n = b + r Lap b - k dt b, and per-workgroup FP64 sums of b Lap c^n and b c^n.
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cuesim {
+
+namespace {
+
+constexpr int kRX = 256, kRY = 8, kRUnroll = 4;
+constexpr int kXcds = 8;
+
+struct Tiles2D {
+    int tx, ty;
+};
+
+Tiles2D tiles_for(int nx, int ny) {
+    return Tiles2D{(nx + kRX - 1) / kRX, (ny + kRY - 1) / kRY};
+}
+
+__device__ __forceinline__ float stencil2d(float c, float w, float e, float s, float n,
+                                           const StencilCoef& k) {
+    const float lap = ((w + e) + (s + n)) - 4.0f * c;
+    return fmaf(k.r, lap, fmaf(-k.kdt, c, c));
+}
+
+// Logical box of this workgroup (die-contiguous stretches of the box order).
+__device__ __forceinline__ int box_of(int per_xcd) {
+    return (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+}
+
+__global__ __launch_bounds__(kRX) void k_field2d_rows(Field2DStepArgs a) {
+    const int box = box_of(a.per_xcd);
+    if (box >= a.n_species * a.tx * a.ty) return;
+    const int bx = box % a.tx, by = (box / a.tx) % a.ty, s = box / (a.tx * a.ty);
+    int e = a.src_start[box];
+    const int e_end = a.src_start[box + 1];
+    const int tid = threadIdx.x;
+    const int i = bx * kRX + tid;
+    if (i >= a.nx) return;   // no barriers below
+    const StencilCoef k = a.coef[s];
+    const int nx = a.nx, ny = a.ny;
+    const float* col = a.in[s] + i;
+    float* dst = a.out[s] + i;
+    const int dw = i > 0 ? -1 : 0, de = i < nx - 1 ? 1 : 0;
+    const int j0 = by * kRY, j1 = min(j0 + kRY, ny);
+    float c = col[(size_t)j0 * nx];
+    float below = col[(size_t)max(j0 - 1, 0) * nx];
+    int j = j0;
+    auto finish = [&](float v, int row) {
+        while (e < e_end && a.src_row[e] == row) {
+            if (a.src_col[e] == tid) v += a.src_q[e];
+            ++e;
+        }
+        dst[(size_t)row * nx] = v;
+    };
+    for (; j + kRUnroll <= j1; j += kRUnroll) {
+        float up[kRUnroll], w[kRUnroll], ea[kRUnroll];
+#pragma unroll
+        for (int u = 0; u < kRUnroll; ++u) {
+            const float* p = col + (size_t)(j + u) * nx;
+            up[u] = col[(size_t)min(j + u + 1, ny - 1) * nx];
+            w[u] = p[dw];
+            ea[u] = p[de];
+        }
+#pragma unroll
+        for (int u = 0; u < kRUnroll; ++u) {
+            finish(stencil2d(c, w[u], ea[u], below, up[u], k), j + u);
+            below = c;
+            c = up[u];
+        }
+    }
+    for (; j < j1; ++j) {
+        const float* p = col + (size_t)j * nx;
+        const float above = col[(size_t)min(j + 1, ny - 1) * nx];
+        finish(stencil2d(c, p[dw], p[de], below, above, k), j);
+        below = c;
+        c = above;
+    }
+}
+
+__device__ double block_sum_fp64(double v) {
+    __shared__ double part[kRX / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();   // part[] may still be read from a previous call
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kRX / 64; ++w) t += part[w];
+    return t;
+}
+
+// Reverse step of one species; box b of the launch owns acc_D[b] and acc_k[b].  Box 0 also
+// adds b at every source cell into acc_q.
+__global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
+    const float* __restrict__ a_in, const float* __restrict__ e_in, const float* __restrict__ c,
+    float* __restrict__ a_out, int nx, int ny, int tx, int ty, int per_xcd, StencilCoef k,
+    double* __restrict__ acc_D, double* __restrict__ acc_k, const int32_t* __restrict__ q_cell,
+    int n_q, double* __restrict__ acc_q) {
+    const int box = box_of(per_xcd);
+    if (box >= tx * ty) return;   // whole workgroup: the barriers below stay uniform
+    const int bx = box % tx, by = box / tx;
+    const int i = bx * kRX + threadIdx.x;
+    double pD = 0.0, pk = 0.0;
+    if (i < nx) {
+        const float* ca = a_in + i;
+        const float* ce = e_in + i;
+        const float* cc = c + i;
+        float* dst = a_out + i;
+        const int dw = i > 0 ? -1 : 0, de = i < nx - 1 ? 1 : 0;
+        const int j0 = by * kRY, j1 = min(j0 + kRY, ny);
+        auto total = [&](size_t at, int off) { return ca[at + off] + ce[at + off]; };
+        const size_t r0 = (size_t)j0 * nx, rm = (size_t)max(j0 - 1, 0) * nx;
+        float b = total(r0, 0), b_below = total(rm, 0);
+        float v = cc[r0], v_below = cc[rm];
+        int j = j0;
+        for (; j + kRUnroll <= j1; j += kRUnroll) {
+            float bu[kRUnroll], bw[kRUnroll], be[kRUnroll], vu[kRUnroll], vw[kRUnroll],
+                ve[kRUnroll];
+#pragma unroll
+            for (int u = 0; u < kRUnroll; ++u) {
+                const size_t at = (size_t)(j + u) * nx;
+                const size_t up = (size_t)min(j + u + 1, ny - 1) * nx;
+                bu[u] = total(up, 0);
+                bw[u] = total(at, dw);
+                be[u] = total(at, de);
+                vu[u] = cc[up];
+                vw[u] = cc[at + dw];
+                ve[u] = cc[at + de];
+            }
+#pragma unroll
+            for (int u = 0; u < kRUnroll; ++u) {
+                dst[(size_t)(j + u) * nx] = stencil2d(b, bw[u], be[u], b_below, bu[u], k);
+                const float lap_c = ((vw[u] + ve[u]) + (v_below + vu[u])) - 4.0f * v;
+                pD += (double)b * (double)lap_c;
+                pk += (double)b * (double)v;
+                b_below = b;
+                b = bu[u];
+                v_below = v;
+                v = vu[u];
+            }
+        }
+        for (; j < j1; ++j) {
+            const size_t at = (size_t)j * nx, up = (size_t)min(j + 1, ny - 1) * nx;
+            const float b_up = total(up, 0), v_up = cc[up];
+            dst[at] = stencil2d(b, total(at, dw), total(at, de), b_below, b_up, k);
+            const float lap_c = ((cc[at + dw] + cc[at + de]) + (v_below + v_up)) - 4.0f * v;
+            pD += (double)b * (double)lap_c;
+            pk += (double)b * (double)v;
+            b_below = b;
+            b = b_up;
+            v_below = v;
+            v = v_up;
+        }
+    }
+    const double sD = block_sum_fp64(pD);
+    const double sk = block_sum_fp64(pk);
+    if (threadIdx.x == 0) {
+        acc_D[box] += sD;
+        acc_k[box] += sk;
+    }
+    if (box == 0)
+        for (int m = threadIdx.x; m < n_q; m += kRX)
+            acc_q[m] += (double)(a_in[q_cell[m]] + e_in[q_cell[m]]);
+}
+
+}  // namespace
+
+hipError_t field2d_prepare(Field2DStep& f, int nx, int ny, int n_species,
+                           const std::vector<int32_t>* cells, const std::vector<float>* q) {
+    field2d_release(f);
+    const Tiles2D t = tiles_for(nx, ny);
+    const int n_boxes = n_species * t.tx * t.ty;
+    // source entries per box, in row order (cells are unique per species)
+    std::vector<std::vector<std::pair<int64_t, float>>> per_box(n_boxes);
+    for (int s = 0; s < n_species; ++s)
+        for (size_t m = 0; m < cells[s].size(); ++m) {
+            const int i = cells[s][m] % nx, j = cells[s][m] / nx;
+            const int box = (s * t.ty + j / kRY) * t.tx + i / kRX;
+            per_box[box].push_back({(int64_t)j * kRX + i % kRX, q[s][m]});
+        }
+    std::vector<int32_t> start(n_boxes + 1, 0), row_of, col_of;
+    std::vector<float> amount;
+    for (int box = 0; box < n_boxes; ++box) {
+        auto& v = per_box[box];
+        std::sort(v.begin(), v.end(),
+                  [](const std::pair<int64_t, float>& x, const std::pair<int64_t, float>& y) {
+                      return x.first < y.first;
+                  });
+        for (auto& en : v) {
+            row_of.push_back((int32_t)(en.first / kRX));
+            col_of.push_back((int32_t)(en.first % kRX));
+            amount.push_back(en.second);
+        }
+        start[box + 1] = (int32_t)row_of.size();
+    }
+    const size_t n_src = std::max<size_t>(row_of.size(), 1);
+    hipError_t e;
+    if ((e = hipMalloc((void**)&f.src_start, start.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&f.src_row, n_src * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&f.src_col, n_src * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&f.src_q, n_src * sizeof(float))) != hipSuccess)
+        return e;
+    if ((e = hipMemcpy(f.src_start, start.data(), start.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if (!row_of.empty() &&
+        ((e = hipMemcpy(f.src_row, row_of.data(), row_of.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+         (e = hipMemcpy(f.src_col, col_of.data(), col_of.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+         (e = hipMemcpy(f.src_q, amount.data(), amount.size() * sizeof(float),
+                        hipMemcpyHostToDevice)) != hipSuccess))
+        return e;
+    f.nx = nx;
+    f.ny = ny;
+    f.n_species = n_species;
+    f.n_boxes = n_boxes;
+    return hipSuccess;
+}
+
+void field2d_release(Field2DStep& f) {
+    if (f.src_start) (void)hipFree(f.src_start);
+    if (f.src_row) (void)hipFree(f.src_row);
+    if (f.src_col) (void)hipFree(f.src_col);
+    if (f.src_q) (void)hipFree(f.src_q);
+    f = Field2DStep{};
+}
+
+hipError_t launch_field2d_rows(const Field2DStep& f, const float* const* in, float* const* out,
+                               const StencilCoef* coef, hipStream_t stream, hipEvent_t start,
+                               hipEvent_t stop) {
+    const Tiles2D t = tiles_for(f.nx, f.ny);
+    Field2DStepArgs a = {};
+    for (int s = 0; s < f.n_species; ++s) {
+        a.in[s] = in[s];
+        a.out[s] = out[s];
+        a.coef[s] = coef[s];
+    }
+    a.nx = f.nx;
+    a.ny = f.ny;
+    a.n_species = f.n_species;
+    a.tx = t.tx;
+    a.ty = t.ty;
+    a.per_xcd = (f.n_boxes + kXcds - 1) / kXcds;
+    a.src_start = f.src_start;
+    a.src_row = f.src_row;
+    a.src_col = f.src_col;
+    a.src_q = f.src_q;
+    void* args[] = {&a};
+    return hipExtLaunchKernel((const void*)k_field2d_rows, dim3(a.per_xcd * kXcds), dim3(kRX),
+                              args, 0, stream, start, stop, 0);
+}
+
+int adjoint_field_blocks(int nx, int ny) {
+    const Tiles2D t = tiles_for(nx, ny);
+    return t.tx * t.ty;
+}
+
+hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* e_in,
+                                  const float* c, float* a_out, StencilCoef coef, double* acc_D,
+                                  double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
+                                  hipStream_t stream) {
+    const Tiles2D t = tiles_for(nx, ny);
+    const int per_xcd = (t.tx * t.ty + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(k_field_adjoint2d_rows, dim3(per_xcd * kXcds), dim3(kRX), 0, stream,
+                       a_in, e_in, c, a_out, nx, ny, t.tx, t.ty, per_xcd, coef, acc_D, acc_k,
+                       q_cell, n_q, acc_q);
+    return hipGetLastError();
+}
+
+}  // namespace cuesim

@@ -1,9 +1,6 @@
-// kernels_plain.hip -- one time step per kernel sequence, no temporal blocking.
-//
-// The 2D stencil reads each cell's 4 neighbours from HBM/L2 and writes the new value:
-// 8 algorithmic bytes per cell-update (one FP32 read, one FP32 write), the HBM-bound
-// baseline the tiled kernel improves on.  Cones run one thread each, in the caller's order,
-// against the just-updated field.
+// kernels_plain.hip -- the parts of an un-blocked 2D step besides the field update: the
+// cones, one thread each in the caller's order, against the just-updated fields; and the
+// FP64 mass of a field.
 #include <hip/hip_ext.h>
 
 #include "internal.hpp"
@@ -11,29 +8,6 @@
 namespace cuesim {
 
 namespace {
-
-constexpr int kRowThreads = 256;
-
-__global__ __launch_bounds__(kRowThreads) void k_field2d(const float* __restrict__ in,
-                                                         float* __restrict__ out, int nx,
-                                                         int ny, StencilCoef coef) {
-    const int i = blockIdx.x * kRowThreads + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= nx) return;
-    const int at = j * nx + i;
-    const float c = in[at];
-    const float w = i > 0 ? in[at - 1] : c;
-    const float e = i < nx - 1 ? in[at + 1] : c;
-    const float s = j > 0 ? in[at - nx] : c;
-    const float n = j < ny - 1 ? in[at + nx] : c;
-    const float lap = ((w + e) + (s + n)) - 4.0f * c;
-    out[at] = fmaf(coef.r, lap, fmaf(-coef.kdt, c, c));
-}
-
-__global__ void k_sources(float* __restrict__ field, SourceList src) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < src.n) field[src.cell[m]] += src.q[m];   // cells are unique per list
-}
 
 struct Global2D {
     const float* f;
@@ -109,20 +83,6 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_final(const double* __res
 }
 
 }  // namespace
-
-hipError_t launch_field2d(int nx, int ny, const float* in, float* out, StencilCoef coef,
-                          hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
-    const int bx = (nx + kRowThreads - 1) / kRowThreads;
-    hipExtLaunchKernelGGL(k_field2d, dim3(bx, ny), dim3(kRowThreads), 0, stream, start, stop,
-                          0, in, out, nx, ny, coef);
-    return hipGetLastError();
-}
-
-hipError_t launch_sources(float* field, SourceList src, hipStream_t stream) {
-    if (src.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sources, dim3((src.n + 63) / 64), dim3(64), 0, stream, field, src);
-    return hipGetLastError();
-}
 
 hipError_t launch_cones2d(const ConeRules& rules, const float* f0, const float* f1,
                           ConeArrays cones, uint32_t step, hipStream_t stream) {

@@ -61,9 +61,7 @@ struct sim_handle {
     // device state
     float* field[SIM_MAX_SPECIES][2] = {};
     int cur[SIM_MAX_SPECIES] = {0, 0};
-    int32_t* src_cell[SIM_MAX_SPECIES] = {};
-    float* src_q[SIM_MAX_SPECIES] = {};
-    int n_src[SIM_MAX_SPECIES] = {};
+    Field2DStep field2d = {};   // 2D un-blocked field step with its per-box source lists
     ConeArrays cones = {};
     float4* target_pts = nullptr;
     int32_t* target_cells = nullptr;
@@ -193,8 +191,6 @@ void release(sim_handle* h) {
     graph_release(h);
     for (int s = 0; s < SIM_MAX_SPECIES; ++s) {
         for (int b = 0; b < 2; ++b) dfree(h->field[s][b]);
-        dfree(h->src_cell[s]);
-        dfree(h->src_q[s]);
     }
     dfree(h->cones.pos);
     dfree(h->cones.dir);
@@ -208,6 +204,7 @@ void release(sim_handle* h) {
     tiled_release(h->tiled);
     order3d_release(h->order3d);
     field3d_release(h->field3d);
+    field2d_release(h->field2d);
     drop_events(h);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     h->stream = nullptr;
@@ -356,28 +353,19 @@ sim_status build_targets(sim_handle* h, const sim_params* p) {
     return SIM_OK;
 }
 
-// Merge sources sharing a cell (amounts summed in double) and scale by 1/dx^dim.
-sim_status upload_sources(sim_handle* h, const sim_params* p, int s) {
+// Merge sources sharing a cell (amounts summed in double) and scale by 1/dx^dim; the field
+// kernels take them from these host lists.
+void merge_sources(sim_handle* h, const sim_params* p, int s) {
     std::map<int32_t, double> merged;
     const double vol = std::pow(p->dx, p->dim);
     for (int m = 0; m < p->n_sources[s]; ++m)
         merged[p->source_cell[s][m]] += (double)p->source_q[s][m] / vol;
-    std::vector<int32_t> cells;
-    std::vector<float> q;
+    h->src_merged_cell[s].clear();
+    h->src_merged_q[s].clear();
     for (auto& kv : merged) {
-        cells.push_back(kv.first);
-        q.push_back((float)kv.second);
+        h->src_merged_cell[s].push_back(kv.first);
+        h->src_merged_q[s].push_back((float)kv.second);
     }
-    h->n_src[s] = (int)cells.size();
-    h->src_merged_cell[s] = cells;
-    h->src_merged_q[s] = q;
-    HIP_TRY(h, dalloc(&h->src_cell[s], cells.size()));
-    HIP_TRY(h, dalloc(&h->src_q[s], q.size()));
-    if (!cells.empty()) {
-        HIP_TRY(h, hipMemcpy(h->src_cell[s], cells.data(), cells.size() * 4, hipMemcpyHostToDevice));
-        HIP_TRY(h, hipMemcpy(h->src_q[s], q.data(), q.size() * 4, hipMemcpyHostToDevice));
-    }
-    return SIM_OK;
 }
 
 sim_status item_size(sim_handle* h, sim_item what, int32_t index, size_t* bytes) {
@@ -441,33 +429,23 @@ sim_status collect_timing(sim_handle* h) {
     return SIM_OK;
 }
 
-// One un-blocked step.  2D: stencil and sources per species, then the cones in caller order.
-// 3D: one launch for the stencil and sources of every species, then the cones in spatial
-// order.
+// One un-blocked step: one launch for the stencil and sources of every species, then the
+// cones (2D: in caller order; 3D: in spatial order).
 sim_status plain_step(sim_handle* h) {
     hipEvent_t t0, t1;
-    sim_status st = SIM_OK;
-    if (h->dim == 3) {
-        const float* in[SIM_MAX_SPECIES] = {};
-        float* out[SIM_MAX_SPECIES] = {};
-        for (int s = 0; s < h->n_species; ++s) {
-            in[s] = h->field[s][h->cur[s]];
-            out[s] = h->field[s][h->cur[s] ^ 1];
-        }
-        if ((st = timing_events(h, &t0, &t1)) != SIM_OK) return st;
-        HIP_TRY(h, launch_field3d(h->field3d, in, out, h->coef, h->stream, t0, t1));
-        for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
-    } else {
-        for (int s = 0; s < h->n_species; ++s) {
-            const float* in = h->field[s][h->cur[s]];
-            float* out = h->field[s][h->cur[s] ^ 1];
-            if ((st = timing_events(h, &t0, &t1)) != SIM_OK) return st;
-            HIP_TRY(h, launch_field2d(h->nx, h->ny, in, out, h->coef[s], h->stream, t0, t1));
-            HIP_TRY(h, launch_sources(out, SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
-                                      h->stream));
-            h->cur[s] ^= 1;
-        }
+    sim_status st = timing_events(h, &t0, &t1);
+    if (st != SIM_OK) return st;
+    const float* in[SIM_MAX_SPECIES] = {};
+    float* out[SIM_MAX_SPECIES] = {};
+    for (int s = 0; s < h->n_species; ++s) {
+        in[s] = h->field[s][h->cur[s]];
+        out[s] = h->field[s][h->cur[s] ^ 1];
     }
+    if (h->dim == 3)
+        HIP_TRY(h, launch_field3d(h->field3d, in, out, h->coef, h->stream, t0, t1));
+    else
+        HIP_TRY(h, launch_field2d_rows(h->field2d, in, out, h->coef, h->stream, t0, t1));
+    for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
     const float* f0 = h->field[0][h->cur[0]];
     const float* f1 = h->n_species > 1 ? h->field[1][h->cur[1]] : f0;
     if (h->dim == 2) {
@@ -583,8 +561,7 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
         else
             e = hipMemset(h->field[s][0], 0, h->n_cells * sizeof(float));
         if (e != hipSuccess) return bail(device_fail(h, e, "field upload"));
-        st = upload_sources(h, p, s);
-        if (st != SIM_OK) return bail(st);
+        merge_sources(h, p, s);
         h->src_caller_cell[s].assign(p->source_cell[s], p->source_cell[s] + p->n_sources[s]);
     }
     // cones (caller order)
@@ -606,11 +583,13 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
             (e = hipMemcpy(h->cones.event_step, minus1.data(), M * 4, hipMemcpyHostToDevice)))
             return bail(device_fail(h, e, "cone upload"));
     }
-    if (p->dim == 3) {
+    if (p->dim == 3)
         e = field3d_prepare(h->field3d, h->nx, h->ny, h->nz, h->n_species, h->src_merged_cell,
                             h->src_merged_q);
-        if (e != hipSuccess) return bail(device_fail(h, e, "3D field set-up"));
-    }
+    else
+        e = field2d_prepare(h->field2d, h->nx, h->ny, h->n_species, h->src_merged_cell,
+                            h->src_merged_q);
+    if (e != hipSuccess) return bail(device_fail(h, e, "field step set-up"));
     if (p->dim == 3 && M > 0) {
         e = order3d_allocate(h->order3d, p->n_cones, h->nx, h->ny, h->nz);
         if (e != hipSuccess) return bail(device_fail(h, e, "cone order allocation"));
@@ -1147,14 +1126,11 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         // restore the checkpoint and re-run the segment's fields, keeping every step
         ADJ_TRY(hipMemcpyAsync(tape, a->ckpt_field + (size_t)j * ns * cells,
                                (size_t)ns * cells * 4, hipMemcpyDeviceToDevice, h->stream));
-        for (int t = 0; t < len; ++t)
-            for (int s = 0; s < ns; ++s) {
-                ADJ_TRY(launch_field2d(nx, ny, field_at(t, s), field_at(t + 1, s), h->coef[s],
-                                       h->stream));
-                ADJ_TRY(launch_sources(field_at(t + 1, s),
-                                       SourceList{h->src_cell[s], h->src_q[s], h->n_src[s]},
-                                       h->stream));
-            }
+        for (int t = 0; t < len; ++t) {
+            const float* in[SIM_MAX_SPECIES] = {field_at(t, 0), field_at(t, ns - 1)};
+            float* out[SIM_MAX_SPECIES] = {field_at(t + 1, 0), field_at(t + 1, ns - 1)};
+            ADJ_TRY(launch_field2d_rows(h->field2d, in, out, h->coef, h->stream));
+        }
         // the segment's cones: forward re-run recording each step's state, then the reverse
         // carrying the cone adjoints and scattering the samples' adjoints
         ADJ_TRY(hipMemsetAsync(scatter, 0, (size_t)len * ns * cells * sizeof(float), h->stream));

@@ -98,6 +98,19 @@ def test_volume_3d_two_species(block):
 
 
 @pytest.mark.parametrize("block", BLOCKS)
+@pytest.mark.parametrize("shape", [(300, 21), (513, 9)])
+def test_dense_sources_2d(shape, block):
+    """Hundreds of sources per species (some cells drawn twice), on grids that end inside a
+    workgroup's box on both axes (the un-blocked step's 256-column x 8-row boxes)."""
+    sc = S.make_scenario("dense sources", 2, shape, 1.0, 0.2,
+                         ((1.0, 0.01, 1.0), (0.5, 0.02, -1.0)), [400, 300], (0.5, 2.0), 0, 0,
+                         seed=22)
+    _say(f"dense sources {shape} block_steps={block}")
+    sim, ref, _ = run_pair(sc, 60, block, 30)
+    sim.close()
+
+
+@pytest.mark.parametrize("block", BLOCKS)
 def test_degenerate_cases(block):
     # no cones, no targets, no sources: the field just decays
     sc = S.make_scenario("empty", 2, (33, 17), 1.0, 0.2, ((1.0, 0.05, 1.0),), 0, (1, 1), 0, 0)
