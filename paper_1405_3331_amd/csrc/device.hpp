@@ -200,33 +200,80 @@ __device__ __forceinline__ void corner(float p, float inv_dx, int n, int& i0, fl
 // Accessor concept: F(i, j) / F(i, j, l) returns the cue value of in-grid cell (i, j[, l])
 // of one species.
 
+// The footprint of the interpolated 2D gradient at a tip: the lower corner (i0, j0) of the
+// 2x2 cell-centre block, the fractions, the clamped indices one beyond each side (ghost =
+// own value at a wall) and the 12 cells read: rows j0, j0+1 at columns im, i0, i0+1, ip
+// (a, b) and columns i0, i0+1 at rows jm, jp (c, d).
+struct Footprint2D {
+    int i0, j0, im, ip, jm, jp;
+    float fx, fy;
+    float a0, a1, a2, a3, b0, b1, b2, b3, c0, c1, d0, d1;
+};
+
+template <class F>
+__device__ __forceinline__ Footprint2D footprint_2d(const F& f, const ConeRules& r, float x,
+                                                    float y) {
+    Footprint2D p;
+    corner(x, r.inv_dx, r.nx, p.i0, p.fx);
+    corner(y, r.inv_dx, r.ny, p.j0, p.fy);
+    p.im = max(p.i0 - 1, 0);
+    p.ip = min(p.i0 + 2, r.nx - 1);
+    p.jm = max(p.j0 - 1, 0);
+    p.jp = min(p.j0 + 2, r.ny - 1);
+    const int i0 = p.i0, j0 = p.j0;
+    p.a0 = f(p.im, j0);
+    p.a1 = f(i0, j0);
+    p.a2 = f(i0 + 1, j0);
+    p.a3 = f(p.ip, j0);
+    p.b0 = f(p.im, j0 + 1);
+    p.b1 = f(i0, j0 + 1);
+    p.b2 = f(i0 + 1, j0 + 1);
+    p.b3 = f(p.ip, j0 + 1);
+    p.c0 = f(i0, p.jm);
+    p.c1 = f(i0 + 1, p.jm);
+    p.d0 = f(i0, p.jp);
+    p.d1 = f(i0 + 1, p.jp);
+    return p;
+}
+
+// Central differences at the four corner centres: g?ab at corner (i0 + a, j0 + b).
+struct CornerGradients2D {
+    float gx00, gx10, gx01, gx11, gy00, gy10, gy01, gy11;
+};
+
+__device__ __forceinline__ CornerGradients2D corner_gradients_2d(const Footprint2D& p,
+                                                                 const ConeRules& r) {
+    CornerGradients2D g;
+    g.gx00 = (p.a2 - p.a0) * r.half_inv_dx;
+    g.gx10 = (p.a3 - p.a1) * r.half_inv_dx;
+    g.gx01 = (p.b2 - p.b0) * r.half_inv_dx;
+    g.gx11 = (p.b3 - p.b1) * r.half_inv_dx;
+    g.gy00 = (p.b1 - p.c0) * r.half_inv_dx;
+    g.gy10 = (p.b2 - p.c1) * r.half_inv_dx;
+    g.gy01 = (p.d0 - p.a1) * r.half_inv_dx;
+    g.gy11 = (p.d1 - p.a2) * r.half_inv_dx;
+    return g;
+}
+
+// Bilinear interpolation of the corner gradients (and, if asked, of the cell values).
+__device__ __forceinline__ void gradient_from_2d(const Footprint2D& p,
+                                                 const CornerGradients2D& g, float& gx,
+                                                 float& gy, float* value) {
+    const float fx = p.fx, fy = p.fy;
+    const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy);
+    const float w01 = (1.0f - fx) * fy, w11 = fx * fy;
+    gx = w00 * g.gx00 + w10 * g.gx10 + w01 * g.gx01 + w11 * g.gx11;
+    gy = w00 * g.gy00 + w10 * g.gy10 + w01 * g.gy01 + w11 * g.gy11;
+    // the interpolated concentration itself, from the same corners and weights
+    if (value) *value = w00 * p.a1 + w10 * p.a2 + w01 * p.b1 + w11 * p.b2;
+}
+
 // Interpolated central-difference gradient of one species at (x, y).
 template <class F>
 __device__ __forceinline__ void gradient_2d(const F& f, const ConeRules& r, float x, float y,
                                             float& gx, float& gy, float* value = nullptr) {
-    int i0, j0;
-    float fx, fy;
-    corner(x, r.inv_dx, r.nx, i0, fx);
-    corner(y, r.inv_dx, r.ny, j0, fy);
-    const int im = max(i0 - 1, 0), ip = min(i0 + 2, r.nx - 1);
-    const int jm = max(j0 - 1, 0), jp = min(j0 + 2, r.ny - 1);
-    // rows j0, j0+1: columns im, i0, i0+1, ip
-    const float a0 = f(im, j0), a1 = f(i0, j0), a2 = f(i0 + 1, j0), a3 = f(ip, j0);
-    const float b0 = f(im, j0 + 1), b1 = f(i0, j0 + 1), b2 = f(i0 + 1, j0 + 1), b3 = f(ip, j0 + 1);
-    // columns i0, i0+1: rows jm, jp
-    const float c0 = f(i0, jm), c1 = f(i0 + 1, jm);
-    const float d0 = f(i0, jp), d1 = f(i0 + 1, jp);
-    // central differences at the four corner centres (ghost = own value at walls)
-    const float gx00 = (a2 - a0) * r.half_inv_dx, gx10 = (a3 - a1) * r.half_inv_dx;
-    const float gx01 = (b2 - b0) * r.half_inv_dx, gx11 = (b3 - b1) * r.half_inv_dx;
-    const float gy00 = (b1 - c0) * r.half_inv_dx, gy10 = (b2 - c1) * r.half_inv_dx;
-    const float gy01 = (d0 - a1) * r.half_inv_dx, gy11 = (d1 - a2) * r.half_inv_dx;
-    const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy);
-    const float w01 = (1.0f - fx) * fy, w11 = fx * fy;
-    gx = w00 * gx00 + w10 * gx10 + w01 * gx01 + w11 * gx11;
-    gy = w00 * gy00 + w10 * gy10 + w01 * gy01 + w11 * gy11;
-    // the interpolated concentration itself, from the same corners and weights
-    if (value) *value = w00 * a1 + w10 * a2 + w01 * b1 + w11 * b2;
+    const Footprint2D p = footprint_2d(f, r, x, y);
+    gradient_from_2d(p, corner_gradients_2d(p, r), gx, gy, value);
 }
 
 // The footprint of the interpolated 3D gradient: the lower corner (i0, j0, l0) of the 2x2x2

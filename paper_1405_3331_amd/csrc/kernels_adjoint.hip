@@ -20,6 +20,8 @@
 //                             per-workgroup FP64 sums of b Lap c^n (for dL/dD) and b c^n (for
 //                             dL/dk) plus b at every source cell (dL/dq).
 // HBM bytes per cell of the reverse field step: a^{n+1}, e^{n+1} and c^n read, a^n written.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace cuesim {
@@ -42,58 +44,58 @@ __device__ double adj_block_sum(double v) {
     return t;
 }
 
-// Reverse of the interpolated central-difference gradient of one species at (x, y).
-// (agx, agy) is the adjoint of the sampled gradient, already weighted by the species
-// sign.  Adds the adjoint of the tip position into (apx, apy) -- the interpolation
-// weights depend on the tip; along an axis where the tip is clamped to the outermost
-// centres they do not -- and scatters the adjoint of the 12 loaded values into af.
-__device__ __forceinline__ void gradient_2d_reverse(const float* __restrict__ f,
-                                                    float* __restrict__ af,
-                                                    const ConeRules& r, float x, float y,
-                                                    float agx, float agy, float& apx,
-                                                    float& apy) {
-    int i0, j0;
-    float fx, fy;
-    corner(x, r.inv_dx, r.nx, i0, fx);
-    corner(y, r.inv_dx, r.ny, j0, fy);
+// The adjoints of one gradient sample's 12 loaded cells: adds to af[at[k]] of v[k].
+struct Scatter2D {
+    int at[12];
+    float v[12];
+};
+
+__device__ __forceinline__ void scatter_add(float* __restrict__ af, const Scatter2D& s) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) atomicAdd(&af[s.at[k]], s.v[k]);
+}
+
+// Reverse of the interpolated central-difference gradient of one species at (x, y), from
+// the footprint and corner gradients the forward sample used.  (agx, agy) is the adjoint of
+// the sampled gradient, already weighted by the species sign.  Adds the adjoint of the tip
+// position into (apx, apy) -- the interpolation weights depend on the tip; along an axis
+// where the tip is clamped to the outermost centres they do not -- and returns the adjoint
+// of the 12 loaded values (cells repeat at walls; their adds then combine).
+__device__ __forceinline__ Scatter2D gradient_2d_reverse(const Footprint2D& p,
+                                                         const CornerGradients2D& g,
+                                                         const ConeRules& r, float x, float y,
+                                                         float agx, float agy, float& apx,
+                                                         float& apy) {
+    const float fx = p.fx, fy = p.fy;
     const float ux = fmaf(x, r.inv_dx, -0.5f), uy = fmaf(y, r.inv_dx, -0.5f);
     const bool free_x = ux > 0.0f && ux < (float)(r.nx - 1);
     const bool free_y = uy > 0.0f && uy < (float)(r.ny - 1);
-    const int im = max(i0 - 1, 0), ip = min(i0 + 2, r.nx - 1);
-    const int jm = max(j0 - 1, 0), jp = min(j0 + 2, r.ny - 1);
-    const int nx = r.nx;
-    const int ia0 = j0 * nx + im, ia1 = j0 * nx + i0, ia2 = j0 * nx + i0 + 1, ia3 = j0 * nx + ip;
-    const int r1 = (j0 + 1) * nx;
-    const int ib0 = r1 + im, ib1 = r1 + i0, ib2 = r1 + i0 + 1, ib3 = r1 + ip;
-    const int ic0 = jm * nx + i0, ic1 = jm * nx + i0 + 1;
-    const int id0 = jp * nx + i0, id1 = jp * nx + i0 + 1;
-    const float h = r.half_inv_dx;
-    // corner gradients (forward values, for the position term)
-    const float gx00 = (f[ia2] - f[ia0]) * h, gx10 = (f[ia3] - f[ia1]) * h;
-    const float gx01 = (f[ib2] - f[ib0]) * h, gx11 = (f[ib3] - f[ib1]) * h;
-    const float gy00 = (f[ib1] - f[ic0]) * h, gy10 = (f[ib2] - f[ic1]) * h;
-    const float gy01 = (f[id0] - f[ia1]) * h, gy11 = (f[id1] - f[ia2]) * h;
+    const int nx = r.nx, i0 = p.i0, j0 = p.j0;
     const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy);
     const float w01 = (1.0f - fx) * fy, w11 = fx * fy;
     // position: d w / d f along each axis, times d f / d p = 1 / dx where not clamped
-    const float aw00 = agx * gx00 + agy * gy00, aw10 = agx * gx10 + agy * gy10;
-    const float aw01 = agx * gx01 + agy * gy01, aw11 = agx * gx11 + agy * gy11;
+    const float aw00 = agx * g.gx00 + agy * g.gy00, aw10 = agx * g.gx10 + agy * g.gy10;
+    const float aw01 = agx * g.gx01 + agy * g.gy01, aw11 = agx * g.gx11 + agy * g.gy11;
     if (free_x) apx += r.inv_dx * ((1.0f - fy) * (aw10 - aw00) + fy * (aw11 - aw01));
     if (free_y) apy += r.inv_dx * ((1.0f - fx) * (aw01 - aw00) + fx * (aw11 - aw10));
-    // field: each loaded value's adjoint (cells repeat at walls; the adds then combine)
+    // field: each loaded value's adjoint
+    const float h = r.half_inv_dx;
     const float hx = h * agx, hy = h * agy;
-    atomicAdd(&af[ia0], -w00 * hx);
-    atomicAdd(&af[ia1], -w10 * hx - w01 * hy);
-    atomicAdd(&af[ia2], w00 * hx - w11 * hy);
-    atomicAdd(&af[ia3], w10 * hx);
-    atomicAdd(&af[ib0], -w01 * hx);
-    atomicAdd(&af[ib1], -w11 * hx + w00 * hy);
-    atomicAdd(&af[ib2], w01 * hx + w10 * hy);
-    atomicAdd(&af[ib3], w11 * hx);
-    atomicAdd(&af[ic0], -w00 * hy);
-    atomicAdd(&af[ic1], -w10 * hy);
-    atomicAdd(&af[id0], w01 * hy);
-    atomicAdd(&af[id1], w11 * hy);
+    const int r0 = j0 * nx, r1 = r0 + nx;
+    Scatter2D s;
+    s.at[0] = r0 + p.im;      s.v[0] = -w00 * hx;
+    s.at[1] = r0 + i0;        s.v[1] = -w10 * hx - w01 * hy;
+    s.at[2] = r0 + i0 + 1;    s.v[2] = w00 * hx - w11 * hy;
+    s.at[3] = r0 + p.ip;      s.v[3] = w10 * hx;
+    s.at[4] = r1 + p.im;      s.v[4] = -w01 * hx;
+    s.at[5] = r1 + i0;        s.v[5] = -w11 * hx + w00 * hy;
+    s.at[6] = r1 + i0 + 1;    s.v[6] = w01 * hx + w10 * hy;
+    s.at[7] = r1 + p.ip;      s.v[7] = w11 * hx;
+    s.at[8] = p.jm * nx + i0; s.v[8] = -w00 * hy;
+    s.at[9] = s.at[8] + 1;    s.v[9] = -w10 * hy;
+    s.at[10] = p.jp * nx + i0; s.v[10] = w01 * hy;
+    s.at[11] = s.at[10] + 1;  s.v[11] = w11 * hy;
+    return s;
 }
 
 struct Field2D {
@@ -103,26 +105,19 @@ struct Field2D {
 };
 
 // Reverse of one cone step (step index `step`) of cone i from its state (x, y, theta) at
-// the start of the step; f0/f1 are the fields after the step's field update and af0/af1
-// receive the adjoints of their sampled values.  (apx, apy, ath) holds the adjoint of the
-// state after the step on entry and of the state before it on exit.
+// the start of the step, the footprints p0/p1 of its gradient samples in the fields after
+// the step's field update, their corner gradients and the weighted gradient (gx, gy).  (apx, apy, ath) holds the adjoint of the state after the
+// step on entry and of the state before it on exit; out[s] receives the adjoints of species
+// s's sampled cells.
 template <int NS>
-__device__ __forceinline__ void cone_adjoint_step(const ConeRules& r, const float* f0,
-                                                  const float* f1, float* af0, float* af1,
-                                                  float4 st, int i, uint32_t step, float& apx,
-                                                  float& apy, float& ath) {
+__device__ __forceinline__ void cone_adjoint_step(const ConeRules& r, const Footprint2D& p0,
+                                                  const Footprint2D& p1,
+                                                  const CornerGradients2D& g0,
+                                                  const CornerGradients2D& g1, float gx,
+                                                  float gy, float4 st, int i, uint32_t step,
+                                                  float& apx, float& apy, float& ath,
+                                                  Scatter2D* out) {
     const float x = st.x, y = st.y, th = st.z;
-    // forward quantities, computed exactly as the forward step computes them
-    float gx, gy;
-    gradient_2d(Field2D{f0, r.nx}, r, x, y, gx, gy);
-    gx *= r.sign0;
-    gy *= r.sign0;
-    if (NS > 1) {
-        float hx, hy;
-        gradient_2d(Field2D{f1, r.nx}, r, x, y, hx, hy);
-        gx = fmaf(r.sign1, hx, gx);
-        gy = fmaf(r.sign1, hy, gy);
-    }
     float s, c;
     sincosf(th, &s, &c);
     float cross = r.gain * (c * gy - s * gx);
@@ -152,8 +147,29 @@ __device__ __forceinline__ void cone_adjoint_step(const ConeRules& r, const floa
         agx = r.gain * (a_along * c - a_cross * s);
         agy = r.gain * (a_cross * c + a_along * s);
     }
-    gradient_2d_reverse(f0, af0, r, x, y, r.sign0 * agx, r.sign0 * agy, apx, apy);
-    if (NS > 1) gradient_2d_reverse(f1, af1, r, x, y, r.sign1 * agx, r.sign1 * agy, apx, apy);
+    out[0] = gradient_2d_reverse(p0, g0, r, x, y, r.sign0 * agx, r.sign0 * agy, apx, apy);
+    if (NS > 1)
+        out[NS - 1] = gradient_2d_reverse(p1, g1, r, x, y, r.sign1 * agx, r.sign1 * agy, apx,
+                                          apy);
+}
+
+// The forward gradient sample of a step from its footprints, computed exactly as the
+// forward step computes it.
+template <int NS>
+__device__ __forceinline__ void sample_2d(const ConeRules& r, const Footprint2D& p0,
+                                          const Footprint2D& p1, CornerGradients2D& g0,
+                                          CornerGradients2D& g1, float& gx, float& gy) {
+    g0 = corner_gradients_2d(p0, r);
+    g1 = NS > 1 ? corner_gradients_2d(p1, r) : g0;
+    gradient_from_2d(p0, g0, gx, gy, nullptr);
+    gx *= r.sign0;
+    gy *= r.sign0;
+    if (NS > 1) {
+        float hx, hy;
+        gradient_from_2d(p1, g1, hx, hy, nullptr);
+        gx = fmaf(r.sign1, hx, gx);
+        gy = fmaf(r.sign1, hy, gy);
+    }
 }
 
 // A checkpoint segment of `len` steps from step seg0: fields[t] (species-major, `cells`
@@ -217,13 +233,42 @@ __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
     // steps < last take part (all steps when the cone is still active)
     const int64_t last = status[i] == kActive ? INT64_MAX : (int64_t)event_step[i];
     float apx = acone[3 * i], apy = acone[3 * i + 1], ath = acone[3 * i + 2];
-    for (int t = seg.len - 1; t >= 0; --t) {
-        const uint32_t step = seg.seg0 + (uint32_t)t;
-        if ((int64_t)step >= last) continue;
-        float* et = e + (size_t)t * seg.n_species * seg.cells;
-        cone_adjoint_step<NS>(r, seg.field(t + 1, 0), seg.field(t + 1, NS - 1), et,
-                              et + (NS - 1) * seg.cells, tape[(size_t)t * n + i], i, step, apx,
-                              apy, ath);
+    // steps t <= t_hi take part; the state of the step before is loaded one step ahead, and
+    // a step's scatter is issued once the next step's samples have arrived, so no load waits
+    // on the scatter's atomics
+    const int t_hi = (int)min<int64_t>(seg.len - 1, last - 1 - (int64_t)seg.seg0);
+    if (t_hi >= 0) {
+        float4 st = tape[(size_t)t_hi * n + i];
+        Scatter2D pending[NS];
+        float* pending_to = nullptr;
+        // one reverse step; FLUSH: first issue the previous step's scatter (every step but
+        // the first has one, so the loop body below has no branch on it)
+        auto reverse_step = [&](int t, auto flush) {
+            const float4 next = tape[(size_t)max(t - 1, 0) * n + i];
+            const Footprint2D p0 =
+                footprint_2d(Field2D{seg.field(t + 1, 0), r.nx}, r, st.x, st.y);
+            const Footprint2D p1 =
+                NS > 1 ? footprint_2d(Field2D{seg.field(t + 1, NS - 1), r.nx}, r, st.x, st.y)
+                       : p0;
+            CornerGradients2D g0, g1;
+            float gx, gy;
+            sample_2d<NS>(r, p0, p1, g0, g1, gx, gy);
+            if (decltype(flush)::value) {
+                // an empty barrier that needs the sampled gradient: the scatter is issued
+                // only after the samples have arrived (else its atomics join the load waits)
+                asm volatile("" ::"v"(gx), "v"(gy) : "memory");
+                scatter_add(pending_to, pending[0]);
+                if (NS > 1) scatter_add(pending_to + seg.cells, pending[NS - 1]);
+            }
+            cone_adjoint_step<NS>(r, p0, p1, g0, g1, gx, gy, st, i, seg.seg0 + (uint32_t)t,
+                                  apx, apy, ath, pending);
+            pending_to = e + (size_t)t * seg.n_species * seg.cells;
+            st = next;
+        };
+        reverse_step(t_hi, std::false_type{});
+        for (int t = t_hi - 1; t >= 0; --t) reverse_step(t, std::true_type{});
+        scatter_add(pending_to, pending[0]);
+        if (NS > 1) scatter_add(pending_to + seg.cells, pending[NS - 1]);
     }
     acone[3 * i] = apx;
     acone[3 * i + 1] = apy;
