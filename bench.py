@@ -181,6 +181,12 @@ def bench_adjoint(args):
     sim.synchronize()
     forward_s = time.perf_counter() - t0
     sim.close()
+    # warm-up: a short gradient run loads the reverse-sweep kernels (code objects load on
+    # first launch)
+    sim = B.Simulation(sc, block_steps=block)
+    sim.adjoint(2 * every, assign, weight, every)
+    sim.adjoint_backward()
+    sim.close()
     sim = B.Simulation(sc, block_steps=block)
     t0 = time.perf_counter()
     loss = sim.adjoint(steps, assign, weight, every)

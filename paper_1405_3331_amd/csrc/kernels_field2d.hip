@@ -1,10 +1,10 @@
 // kernels_field2d.hip -- one explicit 2D field step per launch (every species, sources
 // included) and its reverse for the gradient sweep, both marching up the rows.
 //
-// A workgroup owns kRX columns x kRY rows of one species; each thread keeps the rows below,
-// at and above its cell in registers and reads its two row neighbours from lines the
-// workgroup has just brought into L1, so a cell is fetched from HBM about once.  Rows are
-// taken kRUnroll at a time with every load of the group issued before the arithmetic.  A
+// A workgroup owns kRX columns x kRY rows (kAY for the reverse) of one species; each thread
+// keeps the rows below, at and above its cell in registers and reads its two row neighbours
+// from lines the workgroup has just brought into L1, so a cell is fetched from HBM about
+// once.  Rows are taken in groups with every load of a group issued before the arithmetic.  A
 // missing neighbour at a wall is the cell itself (clamped index).  The stencil expression
 // is term for term the one of the temporally blocked kernel, so both paths give the same
 // bits.  Boxes are dealt to the accelerator dies in contiguous stretches.
@@ -25,15 +25,17 @@ namespace cuesim {
 
 namespace {
 
-constexpr int kRX = 256, kRY = 8, kRUnroll = 4;
+// step: 256 columns x 8 rows, all 8 rows' loads at once; reverse: 256 x 4 (measured best)
+constexpr int kRX = 256, kRY = 8, kRUnroll = 8;
+constexpr int kAY = 4, kAUnroll = 4;
 constexpr int kXcds = 8;
 
 struct Tiles2D {
     int tx, ty;
 };
 
-Tiles2D tiles_for(int nx, int ny) {
-    return Tiles2D{(nx + kRX - 1) / kRX, (ny + kRY - 1) / kRY};
+Tiles2D tiles_for(int nx, int ny, int rows = kRY) {
+    return Tiles2D{(nx + kRX - 1) / kRX, (ny + rows - 1) / rows};
 }
 
 __device__ __forceinline__ float stencil2d(float c, float w, float e, float s, float n,
@@ -128,17 +130,17 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
         const float* cc = c + i;
         float* dst = a_out + i;
         const int dw = i > 0 ? -1 : 0, de = i < nx - 1 ? 1 : 0;
-        const int j0 = by * kRY, j1 = min(j0 + kRY, ny);
+        const int j0 = by * kAY, j1 = min(j0 + kAY, ny);
         auto total = [&](size_t at, int off) { return ca[at + off] + ce[at + off]; };
         const size_t r0 = (size_t)j0 * nx, rm = (size_t)max(j0 - 1, 0) * nx;
         float b = total(r0, 0), b_below = total(rm, 0);
         float v = cc[r0], v_below = cc[rm];
         int j = j0;
-        for (; j + kRUnroll <= j1; j += kRUnroll) {
-            float bu[kRUnroll], bw[kRUnroll], be[kRUnroll], vu[kRUnroll], vw[kRUnroll],
-                ve[kRUnroll];
+        for (; j + kAUnroll <= j1; j += kAUnroll) {
+            float bu[kAUnroll], bw[kAUnroll], be[kAUnroll], vu[kAUnroll], vw[kAUnroll],
+                ve[kAUnroll];
 #pragma unroll
-            for (int u = 0; u < kRUnroll; ++u) {
+            for (int u = 0; u < kAUnroll; ++u) {
                 const size_t at = (size_t)(j + u) * nx;
                 const size_t up = (size_t)min(j + u + 1, ny - 1) * nx;
                 bu[u] = total(up, 0);
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
                 ve[u] = cc[at + de];
             }
 #pragma unroll
-            for (int u = 0; u < kRUnroll; ++u) {
+            for (int u = 0; u < kAUnroll; ++u) {
                 dst[(size_t)(j + u) * nx] = stencil2d(b, bw[u], be[u], b_below, bu[u], k);
                 const float lap_c = ((vw[u] + ve[u]) + (v_below + vu[u])) - 4.0f * v;
                 pD += (double)b * (double)lap_c;
@@ -268,12 +270,15 @@ hipError_t launch_field2d_rows(const Field2DStep& f, const float* const* in, flo
     a.src_col = f.src_col;
     a.src_q = f.src_q;
     void* args[] = {&a};
+    if (!start && !stop)   // a plain launch (also what a graph capture records)
+        return hipLaunchKernel((const void*)k_field2d_rows, dim3(a.per_xcd * kXcds), dim3(kRX),
+                               args, 0, stream);
     return hipExtLaunchKernel((const void*)k_field2d_rows, dim3(a.per_xcd * kXcds), dim3(kRX),
                               args, 0, stream, start, stop, 0);
 }
 
 int adjoint_field_blocks(int nx, int ny) {
-    const Tiles2D t = tiles_for(nx, ny);
+    const Tiles2D t = tiles_for(nx, ny, kAY);
     return t.tx * t.ty;
 }
 
@@ -281,7 +286,7 @@ hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float
                                   const float* c, float* a_out, StencilCoef coef, double* acc_D,
                                   double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
                                   hipStream_t stream) {
-    const Tiles2D t = tiles_for(nx, ny);
+    const Tiles2D t = tiles_for(nx, ny, kAY);
     const int per_xcd = (t.tx * t.ty + kXcds - 1) / kXcds;
     hipLaunchKernelGGL(k_field_adjoint2d_rows, dim3(per_xcd * kXcds), dim3(kRX), 0, stream,
                        a_in, e_in, c, a_out, nx, ny, t.tx, t.ty, per_xcd, coef, acc_D, acc_k,
