@@ -23,6 +23,10 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;   // workgroups are dealt to the accelerator dies round-robin
+// workgroups per die of the cone step: up to 8 per CU (32 CUs per die), so the 256^3
+// workload's 262,144 cones run as one wave of workgroups; fewer, each walking several blocks,
+// fetched more from HBM and were not faster
+constexpr int kConeWgsPerXcd = 32 * 8;
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
     v &= 0x3ffu;
@@ -88,21 +92,11 @@ struct Global3D {
     __device__ float operator()(int i, int j, int l) const { return f[(l * ny + j) * nx + i]; }
 };
 
-// One step of every ordered cone against the updated fields.  Workgroup w of the launch
-// takes the w-th block of kThreads cones counted die by die, so each die works through one
-// contiguous stretch of the order and its L2 holds that region of the fields.  (Loading
-// both species' footprints before combining either was measured slower: the wider register
-// live range costs more than the extra loads in flight gain.)
+// One step of ordered cone t against the updated fields.
 template <int NS>
-__global__ __launch_bounds__(kThreads) void k_cones3d_ordered(ConeRules r,
-                                                              const float* __restrict__ f0,
-                                                              const float* __restrict__ f1,
-                                                              float4* tip, float4* dir, int n,
-                                                              int per_xcd, ConeArrays c,
-                                                              uint32_t step) {
-    const int block = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    const int t = block * kThreads + threadIdx.x;
-    if (t >= n) return;
+__device__ __forceinline__ void step_ordered_cone(const ConeRules& r, const float* f0,
+                                                  const float* f1, float4* tip, float4* dir,
+                                                  const ConeArrays& c, uint32_t step, int t) {
     const float4 p = tip[t];
     const int id = __float_as_int(p.w);
     if (id < 0) return;
@@ -137,6 +131,27 @@ __global__ __launch_bounds__(kThreads) void k_cones3d_ordered(ConeRules r,
     c.status[id] = ev.status;
     c.target[id] = ev.target;
     c.event_step[id] = (int32_t)(step + 1);
+}
+
+// One step of every ordered cone.  The blocks of kThreads cones are split into one
+// contiguous stretch of the order per accelerator die (workgroups are dealt to the dies
+// round-robin), so a die works on one compact region of the fields; when there are more
+// blocks than workgroups, the workgroups of a die walk its stretch block after block.  (Loading
+// both species' footprints before combining either was measured slower: the wider register
+// live range costs more than the extra loads in flight gain.)
+template <int NS>
+__global__ __launch_bounds__(kThreads) void k_cones3d_ordered(ConeRules r,
+                                                              const float* __restrict__ f0,
+                                                              const float* __restrict__ f1,
+                                                              float4* tip, float4* dir, int n,
+                                                              int per_xcd, ConeArrays c,
+                                                              uint32_t step) {
+    const int xcd = blockIdx.x % kXcds;
+    const int wgs_per_xcd = gridDim.x / kXcds;
+    for (int b = blockIdx.x / kXcds; b < per_xcd; b += wgs_per_xcd) {
+        const int t = (xcd * per_xcd + b) * kThreads + threadIdx.x;
+        if (t < n) step_ordered_cone<NS>(r, f0, f1, tip, dir, c, step, t);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_unpack3d(const float4* __restrict__ tip,
@@ -242,12 +257,13 @@ hipError_t launch_cones3d_ordered(const ConeRules& r, const float* f0, const flo
     if (o.n == 0) return hipSuccess;
     const int blocks = blocks_for(o.n);
     const int per_xcd = (blocks + kXcds - 1) / kXcds;
+    const int wgs_per_xcd = std::min(per_xcd, kConeWgsPerXcd);
     if (r.n_species > 1)
-        hipLaunchKernelGGL(k_cones3d_ordered<2>, dim3(per_xcd * kXcds), dim3(kThreads), 0,
+        hipLaunchKernelGGL(k_cones3d_ordered<2>, dim3(wgs_per_xcd * kXcds), dim3(kThreads), 0,
                            stream, r, f0, f1, o.tip[o.cur], o.dir[o.cur], o.n, per_xcd, cones,
                            step);
     else
-        hipLaunchKernelGGL(k_cones3d_ordered<1>, dim3(per_xcd * kXcds), dim3(kThreads), 0,
+        hipLaunchKernelGGL(k_cones3d_ordered<1>, dim3(wgs_per_xcd * kXcds), dim3(kThreads), 0,
                            stream, r, f0, f1, o.tip[o.cur], o.dir[o.cur], o.n, per_xcd, cones,
                            step);
     return hipGetLastError();
