@@ -248,7 +248,7 @@ def bench_volume(args):
                      "frac": achieved / HBM_PEAK_GBS, "kernel_avg_us": avg_us},
     }
     if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(sc, max(1, args.cpu_steps // 20))
+        out["cpu_baseline"] = cpu_baseline(sc, max(1, args.cpu_steps // 10))
     print(json.dumps(out), flush=True)
 
 
@@ -260,8 +260,9 @@ def main():
     ap.add_argument("--block-steps", type=int, default=0,
                     help="steps per launch of the tiled kernel (0 = the autotuner's record "
                          "for this workload, else the library default)")
-    ap.add_argument("--cpu-steps", type=int, default=60,
-                    help="steps of the oracle timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=600,
+                    help="steps of the oracle timed for cpu_baseline, about 10 s of the "
+                         "host's cores on the headline workload (0 = skip)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run a device-to-device copy of this size first (for counters)")
