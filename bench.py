@@ -89,6 +89,16 @@ def active_cone_steps(event_step, start, end):
     return int(np.clip(e, start, end).sum() - start * len(e))
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sc, steps):
     import oracle
     from oracle import build as obuild
@@ -103,6 +113,7 @@ def cpu_baseline(sc, steps):
         "value": sc.n_cells * steps / dt,
         "unit": "cell-updates/s",
         "cores": oracle.num_threads(),
+        "host": host_cpu_model(),
         "kind": "oracle",
         "sample": f"{sc.name}: first {steps} steps, all cells and cones (FP64, brute-force "
                   f"contact), {dt:.1f} s wall",
@@ -211,6 +222,50 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+# SNR turn law parameters of the --snr run: snr_scale, cone_width, kd, c_min, c_max
+SNR_LAW = (50.0, 1.0, 0.5, 1e-3, 1e3)
+
+
+def bench_connectivity(args):
+    """The connections of the headline run after --connectivity-steps steps: the adjacency
+    list (V_a, E_a) of neuron -> neuron contacts and the BFS levels from neuron 0 (Sec. 3.4,
+    Figs. 4-5), 16 cones per neuron (65,536 cones -> 4096 neurons), targets owned by a fixed
+    affine map.  Times each call end to end (host arrays in and out)."""
+    sc = S.headline()
+    steps = args.connectivity_steps
+    n_neurons = sc.n_cones // 16
+    cone_owner = np.arange(sc.n_cones) // 16
+    target_owner = (np.arange(sc.n_targets) * 7 + 3) % n_neurons
+    block = autotune.apply(sc)
+    sim = B.Simulation(sc, block_steps=block)
+    sim.step(steps)
+    sim.synchronize()
+    sim.connectivity(n_neurons, cone_owner, target_owner)   # warm-up (first launches)
+    sim.bfs_levels(0, n_neurons)
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        row_start, edges = sim.connectivity(n_neurons, cone_owner, target_owner)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        level = sim.bfs_levels(0, n_neurons)
+    t2 = time.perf_counter()
+    counts = sim.counts()
+    sim.close()
+    conn_ms = (t1 - t0) * 1e3 / reps
+    out = {
+        "metric": "connectivity: adjacency list and BFS levels of the contacts, ms per call",
+        "value": conn_ms, "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{sc.name} after {steps} steps, 16 cones per neuron",
+                   "neurons": n_neurons, "cones": sc.n_cones, "targets": sc.n_targets},
+        "edges": int(edges.size), "contacts": int(counts[1]),
+        "adjacency_ms": conn_ms, "bfs_ms": (t2 - t1) * 1e3 / reps,
+        "bfs_depth": int(level.max()), "reached": int((level >= 0).sum()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_volume(args):
     """3D 256^3 two-species workload through the per-step path (one stencil + sources launch
     for both species, then one thread per cone in spatial order)."""
@@ -278,6 +333,11 @@ def main():
                     help="measure the trajectory-loss gradient of the 1024^2 workload")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--checkpoint-every", type=int, default=100)
+    ap.add_argument("--snr", action="store_true",
+                    help="the headline workload under the SNR turn law (Sec. 3.5, Eq. 5)")
+    ap.add_argument("--connectivity", action="store_true",
+                    help="adjacency list and BFS levels of the headline run's contacts")
+    ap.add_argument("--connectivity-steps", type=int, default=4000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
@@ -295,7 +355,13 @@ def main():
     if args.adjoint:
         bench_adjoint(args)
         return
+    if args.connectivity:
+        bench_connectivity(args)
+        return
     sc = S.headline()
+    if args.snr:
+        sc.snr_law = SNR_LAW
+        sc.name += ", SNR turn law"
     block = args.block_steps
     if block == 0:   # blocking depth and tile shape recorded by the autotuner, if any
         block = autotune.apply(sc)
@@ -336,7 +402,8 @@ def main():
         steps_per_launch = args.steps / launches
         algo_bytes = BYTES_PER_CELL_UPDATE * cells * steps_per_launch
         achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
-        traffic = recorded_traffic(tiling) if tiling["block_steps"] > 1 else None
+        # the counter record was taken under the vector-addition law
+        traffic = recorded_traffic(tiling) if tiling["block_steps"] > 1 and not args.snr else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "kernel_avg_us": avg_ms * 1e3, "launches": launches,
