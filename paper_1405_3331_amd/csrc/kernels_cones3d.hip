@@ -92,6 +92,60 @@ struct Global3D {
     __device__ float operator()(int i, int j, int l) const { return f[(l * ny + j) * nx + i]; }
 };
 
+// The 3D gradient footprint of one species read row by row: each of the four rows
+// (j0 + b, l0 + c) with four cells (im, i0, i0 + 1, ip) is one 16-byte load of the cells
+// [s, s + 4), s = clamp(i0 - 1, 0, nx - 4), from which the four values are picked (at a wall
+// the clamped indices repeat a cell, exactly as the per-cell accessor reads it); the other
+// eight rows hold two adjacent cells each.  Needs nx >= 4.
+__device__ __forceinline__ Footprint3D load_footprint_3d_rows(const float* __restrict__ f,
+                                                              const ConeRules& r,
+                                                              const Corner3D& k) {
+    Footprint3D p;
+    const size_t nx = (size_t)r.nx, plane = nx * (size_t)r.ny;
+    const int s = min(max(k.i0 - 1, 0), r.nx - 4);
+    const int am = k.im - s, a0 = k.i0 - s, ap = k.ip - s;
+    auto row4 = [&](int j, int l) {
+        float4 v;
+        __builtin_memcpy(&v, f + (size_t)l * plane + (size_t)j * nx + s, sizeof v);
+        return v;
+    };
+    auto pick = [](const float4& v, int i) {
+        return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+    };
+    auto row2 = [&](int j, int l) {
+        float2 v;
+        __builtin_memcpy(&v, f + (size_t)l * plane + (size_t)j * nx + k.i0, sizeof v);
+        return v;
+    };
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float4 v = row4(k.j0 + b, k.l0 + c);
+            p.xm[b][c] = pick(v, am);
+            p.blk[0][b][c] = pick(v, a0);
+            p.blk[1][b][c] = pick(v, a0 + 1);
+            p.xp[b][c] = pick(v, ap);
+        }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float2 ym = row2(k.jm, k.l0 + c), yp = row2(k.jp, k.l0 + c);
+        p.ym[0][c] = ym.x;
+        p.ym[1][c] = ym.y;
+        p.yp[0][c] = yp.x;
+        p.yp[1][c] = yp.y;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const float2 zm = row2(k.j0 + b, k.lm), zp = row2(k.j0 + b, k.lp);
+        p.zm[0][b] = zm.x;
+        p.zm[1][b] = zm.y;
+        p.zp[0][b] = zp.x;
+        p.zp[1][b] = zp.y;
+    }
+    return p;
+}
+
 // One step of ordered cone t against the updated fields.
 template <int NS>
 __device__ __forceinline__ void step_ordered_cone(const ConeRules& r, const float* f0,
@@ -102,14 +156,22 @@ __device__ __forceinline__ void step_ordered_cone(const ConeRules& r, const floa
     if (id < 0) return;
     const float4 h = dir[t];
     float x = p.x, y = p.y, z = p.z, hx = h.x, hy = h.y, hz = h.z;
+    const Corner3D k = corner_3d(r, x, y, z);
     float gx, gy, gz;
-    gradient_3d(Global3D{f0, r.nx, r.ny}, r, x, y, z, gx, gy, gz);
+    if (r.nx >= 4)
+        gradient_from_3d(r, k, load_footprint_3d_rows(f0, r, k), gx, gy, gz);
+    else
+        gradient_from_3d(r, k, load_footprint_3d(Global3D{f0, r.nx, r.ny}, k), gx, gy, gz);
     gx *= r.sign0;
     gy *= r.sign0;
     gz *= r.sign0;
     if (NS > 1) {
         float ax, ay, az;
-        gradient_3d(Global3D{f1, r.nx, r.ny}, r, x, y, z, ax, ay, az);
+        if (r.nx >= 4)
+            gradient_from_3d(r, k, load_footprint_3d_rows(f1, r, k), ax, ay, az);
+        else
+            gradient_from_3d(r, k, load_footprint_3d(Global3D{f1, r.nx, r.ny}, k), ax, ay,
+                             az);
         gx = fmaf(r.sign1, ax, gx);
         gy = fmaf(r.sign1, ay, gy);
         gz = fmaf(r.sign1, az, gz);
