@@ -23,10 +23,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;   // workgroups are dealt to the accelerator dies round-robin
-// workgroups per die of the cone step: up to 8 per CU (32 CUs per die), so the 256^3
-// workload's 262,144 cones run as one wave of workgroups; fewer, each walking several blocks,
-// fetched more from HBM and were not faster
-constexpr int kConeWgsPerXcd = 32 * 8;
+// workgroups per die of the cone step: two per CU (32 CUs per die), each walking several
+// blocks of its die's stretch, so a die works on a region of the fields its L2 can hold
+// (256^3 workload: 62 us and 247 MB fetched per step, against 70 us and 336 MB with every
+// block resident at once; one per CU fetched least, 186 MB, but took 67 us)
+constexpr int kConeWgsPerXcd = 32 * 2;
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
     v &= 0x3ffu;
