@@ -22,8 +22,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
-// Steps between refreshes of the spatial order of 3D cones (a cone moves step_len per step).
-constexpr int kOrderRefresh = 16;
+// Steps between refreshes of the spatial order of 3D cones (a cone moves step_len per step;
+// 8, 16, 32 and 64 were measured at 256^3, 32 was fastest).
+constexpr int kOrderRefresh = 32;
 
 bool finite(double v) { return std::isfinite(v); }
 
