@@ -130,3 +130,12 @@ def test_torch_autograd_function():
     np.testing.assert_allclose(q.grad.numpy(), 2.0 * dq, rtol=1e-5, atol=1e-9 * np.abs(dq).max())
     np.testing.assert_allclose(D.grad.numpy(), 2.0 * dD, rtol=1e-5)
     np.testing.assert_allclose(k.grad.numpy(), 2.0 * dk, rtol=1e-5)
+
+
+def test_full_size_gradient_matches_oracle():
+    """The gradient workload at full size (1024^2, 8192 cones, 32 sources, 256 targets) in the
+    launch configuration bench.py times, over 60 steps in three checkpoint segments (the last
+    ragged), against the oracle's FP64 reverse sweep of the same run.  (Finite differences of
+    the FP32 forward run are no check at this size: rounding noise in 8192 tips outweighs the
+    loss change of any perturbation small enough to stay linear.)"""
+    _compare(scenarios.adjoint(), 60, 25)
