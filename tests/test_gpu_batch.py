@@ -90,3 +90,32 @@ def test_plain_and_tiled_paths_are_bitwise_identical():
     assert_same(a.cones(), b.cones(), "plain vs tiled")
     a.close()
     b.close()
+
+
+def test_full_size_batch():
+    """The batched workload at full size (512 simulations, sides 64..512, 16..4096 cones) in
+    bench.py's launch configuration (10 launches per graph replay): after 80 steps every member
+    equals the same simulation run alone bit for bit, and eight of those single runs (the
+    smallest, the largest, the most and the fewest cones, four more) match the FP64 oracle
+    (full-run parity with the classification of dynamically amplified cones)."""
+    scs = S.batched()
+    print(f"[gpu] full-size batch: {len(scs)} simulations, 80 steps", flush=True)
+    with B.Batch(scs, graph_launches=10) as bt:
+        bt.step(80)
+        for i, sc in enumerate(scs):
+            with B.Simulation(sc) as one:
+                one.step(80)
+                assert np.array_equal(bt.field(i), one.field()), i
+                assert_same(bt.cones(i), one.cones(), i)
+    sides = np.array([sc.nx for sc in scs])
+    cones = np.array([sc.n_cones for sc in scs])
+    picks = sorted({int(sides.argmin()), int(sides.argmax()), int(cones.argmax()),
+                    int(cones.argmin()), 7, 100, 301, 511})
+    for i in picks:
+        run = parity.FullRun(scs[i])
+        run.advance(40, where=f"member {i} step 40")
+        run.advance(40, where=f"member {i} step 80")
+        print(f"[gpu] member {i}: side {scs[i].nx}, {scs[i].n_cones} cones, worst field "
+              f"{run.worst['field']:.2e} tip {run.worst['tip']:.2e}, amplified "
+              f"{int(run.amplified.sum())}", flush=True)
+        run.sim.close()
