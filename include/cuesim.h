@@ -162,8 +162,9 @@ sim_status sim_device_ptr(sim_handle* h, sim_item what, int32_t index, void** de
                           size_t* bytes);
 
 /* Enable (1) or disable (0) HIP-event timing of every launch of the step kernel (the
- * tiled kernel, or the stencil kernel when block_steps = 1); enabling resets the totals
- * read back through SIM_KERNEL_TIME. */
+ * tiled kernel; with block_steps = 1 and in 3D, the field kernel, whose one launch covers
+ * the stencil and sources of every species); enabling resets the totals read back through
+ * SIM_KERNEL_TIME. */
 sim_status sim_set_timing(sim_handle* h, int32_t enable);
 
 /* Block until all work enqueued on the handle's stream has finished. */
