@@ -129,9 +129,15 @@ hipError_t order3d_end(const ConeOrder3D& o, ConeArrays cones, hipStream_t strea
 // A segment's fields are `fields + (t * n_species + s) * cells` for t = 0..len.
 int adjoint_field_blocks(int nx, int ny);
 int adjoint_cone_blocks(int n);
-hipError_t launch_cones_segment2d(const ConeRules& rules, const float* fields, size_t cells,
-                                  int n_species, uint32_t seg0, int len, ConeArrays cones,
-                                  float4* tape, hipStream_t stream);
+// Forward re-run of segments seg_first .. seg_first + n_seg - 1 of a run checkpointed every
+// `every` of its n_steps steps from step n0; run step t's fields are at
+// fields + ((t - t_base) * n_species + s) * cells and its cone states go to
+// tape[(t - t_base) * M + i].
+hipError_t launch_cones_segments2d(const ConeRules& rules, const float* fields, size_t cells,
+                                   int n_species, int t_base, int seg_first, int n_seg,
+                                   int every, int n_steps, uint32_t n0, const float* ckpt_pos,
+                                   const float* ckpt_dir, const int32_t* ckpt_int, int M,
+                                   float4* tape, hipStream_t stream);
 hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fields,
                                          size_t cells, int n_species, uint32_t seg0, int len,
                                          float* e, const float4* tape, const int32_t* status,

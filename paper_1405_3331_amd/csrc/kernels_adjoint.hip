@@ -7,8 +7,10 @@
 //
 // The fields never depend on the cones, so within a checkpoint segment the cones can be
 // handled apart from the fields, each cone by one thread over all the segment's steps:
-//   k_cones_segment2d         re-runs the segment's cone steps against the re-run fields and
-//                             records (x, y, theta) of every cone at the start of each step;
+//   k_cones_segments2d        re-runs the segment's cone steps against the re-run fields and
+//                             records (x, y, theta) of every cone at the start of each step
+//                             (when the whole run's fields fit in memory, every segment at
+//                             once, one thread per segment and cone);
 //   k_cone_adjoint_segment2d  walks the steps backwards carrying each cone's adjoint of
 //                             (p, theta) through advance, capped turn and interpolated
 //                             gradient; the gradient samples' adjoints are scattered into
@@ -174,6 +176,25 @@ __device__ __forceinline__ void sample_2d(const ConeRules& r, const Footprint2D&
 
 // A checkpoint segment of `len` steps from step seg0: fields[t] (species-major, `cells`
 // each) is the field state after t steps of the segment, t = 0..len.
+// Segments of a checkpointed run of n_steps steps from step n0, every `every` steps: run
+// step t's field state (after t steps) is fields + ((t - t_base) * n_species + s) * cells;
+// the checkpoint arrays hold each segment's cone state at its first step.
+struct SegmentSet2D {
+    const float* fields;
+    size_t cells;
+    int n_species;
+    int t_base;
+    int seg_first, every, n_steps;
+    uint32_t n0;
+    const float* ckpt_pos;         // [segments][M][2]
+    const float* ckpt_dir;         // [segments][M]
+    const int32_t* ckpt_status;    // [segments][3][M]: status first
+    int M;
+    __device__ const float* field(int t, int s) const {
+        return fields + ((size_t)(t - t_base) * n_species + s) * cells;
+    }
+};
+
 struct Segment2D {
     const float* fields;
     size_t cells;
@@ -185,35 +206,42 @@ struct Segment2D {
     }
 };
 
-// Forward re-run of one segment's cone steps, one thread per cone over all the steps; the
-// state at the start of step t goes to tape[t][i] whether or not the cone is still active.
-// Same arithmetic as the forward step (gradient, turn, noise, advance, exit, contact).
+// Forward re-run of the cone steps of segments seg_first .. seg_first + gridDim.y - 1, one
+// thread per (segment, cone) over all the segment's steps, each starting from its
+// checkpoint; the state at the start of run step t goes to tape[t - t_base][i] whether or
+// not the cone is still active.  Same arithmetic as the forward step (gradient, turn,
+// noise, advance, exit, contact).
 template <int NS>
-__global__ __launch_bounds__(kSegThreads) void k_cones_segment2d(ConeRules r, Segment2D seg,
-                                                                 ConeArrays c,
-                                                                 float4* __restrict__ tape) {
+__global__ __launch_bounds__(kSegThreads) void k_cones_segments2d(ConeRules r, SegmentSet2D set,
+                                                                  float4* __restrict__ tape) {
     const int i = blockIdx.x * kSegThreads + threadIdx.x;
-    if (i >= c.n) return;
-    float x = c.pos[2 * i], y = c.pos[2 * i + 1], th = c.dir[i];
-    int status = c.status[i];
-    for (int t = 0; t < seg.len; ++t) {
-        tape[(size_t)t * c.n + i] = make_float4(x, y, th, 0.0f);
+    if (i >= set.M) return;
+    const int seg = set.seg_first + (int)blockIdx.y;
+    const int t0 = seg * set.every;
+    const int t1 = min(t0 + set.every, set.n_steps);
+    const size_t M = (size_t)set.M;
+    float x = set.ckpt_pos[((size_t)seg * M + i) * 2];
+    float y = set.ckpt_pos[((size_t)seg * M + i) * 2 + 1];
+    float th = set.ckpt_dir[(size_t)seg * M + i];
+    int status = set.ckpt_status[(size_t)seg * 3 * M + i];
+    for (int t = t0; t < t1; ++t) {
+        tape[(size_t)(t - set.t_base) * M + i] = make_float4(x, y, th, 0.0f);
         if (status != kActive) continue;
-        const float* f0 = seg.field(t + 1, 0);
+        const float* f0 = set.field(t + 1, 0);
         float gx, gy;
         gradient_2d(Field2D{f0, r.nx}, r, x, y, gx, gy);
         gx *= r.sign0;
         gy *= r.sign0;
         if (NS > 1) {
             float hx, hy;
-            gradient_2d(Field2D{seg.field(t + 1, NS - 1), r.nx}, r, x, y, hx, hy);
+            gradient_2d(Field2D{set.field(t + 1, NS - 1), r.nx}, r, x, y, hx, hy);
             gx = fmaf(r.sign1, hx, gx);
             gy = fmaf(r.sign1, hy, gy);
         }
         float sn, cs;
         sincosf(th, &sn, &cs);
         float z[2];
-        noise_2d(r.key, (uint32_t)i, seg.seg0 + (uint32_t)t, z);
+        noise_2d(r.key, (uint32_t)i, set.n0 + (uint32_t)t, z);
         const ConeEvent ev = cone_step_2d(r, gx, gy, 0.0f, z, x, y, th, sn, cs,
                                           GridContact{&r.targets});
         status = ev.status;
@@ -300,18 +328,21 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_seed2d(
 
 int adjoint_cone_blocks(int n) { return (n + kAdjThreads - 1) / kAdjThreads; }
 
-hipError_t launch_cones_segment2d(const ConeRules& rules, const float* fields, size_t cells,
-                                  int n_species, uint32_t seg0, int len, ConeArrays cones,
-                                  float4* tape, hipStream_t stream) {
-    if (cones.n == 0 || len == 0) return hipSuccess;
-    const Segment2D seg{fields, cells, n_species, seg0, len};
-    const dim3 grid((cones.n + kSegThreads - 1) / kSegThreads);
+hipError_t launch_cones_segments2d(const ConeRules& rules, const float* fields, size_t cells,
+                                   int n_species, int t_base, int seg_first, int n_seg,
+                                   int every, int n_steps, uint32_t n0, const float* ckpt_pos,
+                                   const float* ckpt_dir, const int32_t* ckpt_int, int M,
+                                   float4* tape, hipStream_t stream) {
+    if (M == 0 || n_seg == 0) return hipSuccess;
+    const SegmentSet2D set{fields, cells, n_species, t_base, seg_first, every, n_steps, n0,
+                           ckpt_pos, ckpt_dir, ckpt_int, M};
+    const dim3 grid((M + kSegThreads - 1) / kSegThreads, n_seg);
     if (n_species > 1)
-        hipLaunchKernelGGL(k_cones_segment2d<2>, grid, dim3(kSegThreads), 0, stream, rules, seg,
-                           cones, tape);
+        hipLaunchKernelGGL(k_cones_segments2d<2>, grid, dim3(kSegThreads), 0, stream, rules,
+                           set, tape);
     else
-        hipLaunchKernelGGL(k_cones_segment2d<1>, grid, dim3(kSegThreads), 0, stream, rules, seg,
-                           cones, tape);
+        hipLaunchKernelGGL(k_cones_segments2d<1>, grid, dim3(kSegThreads), 0, stream, rules,
+                           set, tape);
     return hipGetLastError();
 }
 

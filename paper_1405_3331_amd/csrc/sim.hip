@@ -1057,13 +1057,23 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     q_off[1] = n_q[0];
     const int nq_all = n_q[0] + (ns > 1 ? n_q[1] : 0);
 
-    // workspace: one segment of fields, cone states and per-step sample adjoints, the
-    // re-run's cones (tip, heading, status), the field adjoint (ping-pong per species), FP64
-    // accumulators
+    // Workspace.  The field states of the reverse sweep (a window of steps), the cone state at
+    // every step of the window, one segment's per-step sample adjoints, the re-run's cones,
+    // the field adjoint (ping-pong per species) and FP64 accumulators.  When the whole run's
+    // fields fit comfortably (under half the free device memory), the window is the whole
+    // run: the fields are re-run once and the cone steps of every segment are re-run at once,
+    // one thread per (segment, cone), instead of segment after segment.
+    const int n_seg = a->n_ckpt;
+    const int64_t n_run = a->n_steps;
+    size_t free_bytes = 0, total_bytes = 0;
+    if (hipMemGetInfo(&free_bytes, &total_bytes) != hipSuccess) free_bytes = 0;
+    const size_t whole_bytes = ((size_t)(n_run + 1) * ns * cells + (size_t)K * ns * cells) * 4 +
+                               (size_t)n_run * std::max<size_t>(Ms, 1) * 16;
+    const bool whole = n_seg > 1 && whole_bytes < free_bytes / 2;
+    const int64_t window = whole ? n_run : K;
     float* tape = nullptr;
     float4* tape_cones = nullptr;
     float* scatter = nullptr;
-    ConeArrays work = {};
     float* afield = nullptr;
     double* acc = nullptr;
     int32_t* q_cell = nullptr;
@@ -1071,21 +1081,15 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         dfree(tape);
         dfree(tape_cones);
         dfree(scatter);
-        dfree(work.pos);
-        dfree(work.dir);
-        dfree(work.status);
         dfree(afield);
         dfree(acc);
         dfree(q_cell);
     };
     hipError_t e;
     const size_t acc_n = (size_t)2 * ns * fb + (size_t)std::max(nq_all, 1);
-    if ((e = dalloc(&tape, (size_t)(K + 1) * ns * cells)) != hipSuccess ||
-        (e = dalloc(&tape_cones, (size_t)K * std::max<size_t>(Ms, 1))) != hipSuccess ||
+    if ((e = dalloc(&tape, (size_t)(window + 1) * ns * cells)) != hipSuccess ||
+        (e = dalloc(&tape_cones, (size_t)window * std::max<size_t>(Ms, 1))) != hipSuccess ||
         (e = dalloc(&scatter, (size_t)K * ns * cells)) != hipSuccess ||
-        (e = dalloc(&work.pos, Ms * 2)) != hipSuccess ||
-        (e = dalloc(&work.dir, Ms)) != hipSuccess ||
-        (e = dalloc(&work.status, Ms)) != hipSuccess ||
         (e = dalloc(&afield, (size_t)2 * ns * cells)) != hipSuccess ||
         (e = dalloc(&acc, acc_n)) != hipSuccess ||
         (e = dalloc(&q_cell, (size_t)std::max(nq_all, 1))) != hipSuccess) {
@@ -1094,7 +1098,6 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
             return fail(h, SIM_ENOMEM, "adjoint workspace: out of device memory");
         return device_fail(h, e, "adjoint workspace");
     }
-    work.n = M;
 #define ADJ_TRY(expr)                                                       \
     do {                                                                    \
         hipError_t e_ = (expr);                                             \
@@ -1117,46 +1120,53 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         free_all();
         return st;
     }
-    auto field_at = [&](int t, int s) { return tape + ((size_t)t * ns + s) * cells; };
+    int64_t t_base = 0;   // run step whose field state is at the start of the window
+    auto field_at = [&](int64_t t, int s) {
+        return tape + ((size_t)(t - t_base) * ns + s) * cells;
+    };
     auto scatter_at = [&](int t, int s) { return scatter + ((size_t)t * ns + s) * cells; };
     int cur = 0;
     auto afield_at = [&](int s, int half) { return afield + ((size_t)s * 2 + half) * cells; };
-    for (int j = a->n_ckpt - 1; j >= 0; --j) {
-        const int64_t seg0 = a->n0 + (int64_t)j * a->every;
-        const int len = (int)std::min<int64_t>(a->every, a->n_steps - (int64_t)j * a->every);
-        // restore the checkpoint and re-run the segment's fields, keeping every step
-        ADJ_TRY(hipMemcpyAsync(tape, a->ckpt_field + (size_t)j * ns * cells,
-                               (size_t)ns * cells * 4, hipMemcpyDeviceToDevice, h->stream));
-        for (int t = 0; t < len; ++t) {
+    // re-run the fields of run steps [t0, t0 + len) from the checkpoint of segment j, and
+    // the cone steps of segments j .. j + n - 1
+    auto rerun = [&](int j, int64_t t0, int64_t len, int n) -> hipError_t {
+        hipError_t r = hipMemcpyAsync(field_at(t0, 0), a->ckpt_field + (size_t)j * ns * cells,
+                                      (size_t)ns * cells * 4, hipMemcpyDeviceToDevice,
+                                      h->stream);
+        for (int64_t t = t0; t < t0 + len && r == hipSuccess; ++t) {
             const float* in[SIM_MAX_SPECIES] = {field_at(t, 0), field_at(t, ns - 1)};
             float* out[SIM_MAX_SPECIES] = {field_at(t + 1, 0), field_at(t + 1, ns - 1)};
-            ADJ_TRY(launch_field2d_rows(h->field2d, in, out, h->coef, h->stream));
+            r = launch_field2d_rows(h->field2d, in, out, h->coef, h->stream);
         }
-        // the segment's cones: forward re-run recording each step's state, then the reverse
-        // carrying the cone adjoints and scattering the samples' adjoints
+        if (r == hipSuccess)
+            r = launch_cones_segments2d(h->rules, tape, cells, ns, (int)t_base, j, n, a->every,
+                                        (int)n_run, (uint32_t)a->n0, a->ckpt_pos, a->ckpt_dir,
+                                        a->ckpt_int, M, tape_cones, h->stream);
+        return r;
+    };
+    if (whole) ADJ_TRY(rerun(0, 0, n_run, n_seg));
+    for (int j = n_seg - 1; j >= 0; --j) {
+        const int64_t t0 = (int64_t)j * a->every;
+        const int len = (int)std::min<int64_t>(a->every, n_run - t0);
+        if (!whole) {
+            t_base = t0;
+            ADJ_TRY(rerun(j, t0, len, 1));
+        }
+        // the segment's cone adjoints, scattering the samples' adjoints per step
         ADJ_TRY(hipMemsetAsync(scatter, 0, (size_t)len * ns * cells * sizeof(float), h->stream));
-        if (M > 0) {
-            const int32_t* ci = a->ckpt_int + (size_t)j * 3 * Ms;
-            ADJ_TRY(hipMemcpyAsync(work.pos, a->ckpt_pos + (size_t)j * Ms * 2, Ms * 8,
-                                   hipMemcpyDeviceToDevice, h->stream));
-            ADJ_TRY(hipMemcpyAsync(work.dir, a->ckpt_dir + (size_t)j * Ms, Ms * 4,
-                                   hipMemcpyDeviceToDevice, h->stream));
-            ADJ_TRY(hipMemcpyAsync(work.status, ci, Ms * 4, hipMemcpyDeviceToDevice, h->stream));
-            ADJ_TRY(launch_cones_segment2d(h->rules, tape, cells, ns, (uint32_t)seg0, len, work,
-                                           tape_cones, h->stream));
-            ADJ_TRY(launch_cone_adjoint_segment2d(h->rules, tape, cells, ns, (uint32_t)seg0, len,
-                                                  scatter, tape_cones, h->cones.status,
-                                                  h->cones.event_step, a->acone, M,
-                                                  h->stream));
-        }
+        ADJ_TRY(launch_cone_adjoint_segment2d(h->rules, field_at(t0, 0), cells, ns,
+                                              (uint32_t)(a->n0 + t0), len, scatter,
+                                              tape_cones + (size_t)(t0 - t_base) * Ms,
+                                              h->cones.status, h->cones.event_step, a->acone,
+                                              M, h->stream));
         // reverse the segment's field steps
         for (int t = len - 1; t >= 0; --t) {
             for (int s = 0; s < ns; ++s)
                 ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), scatter_at(t, s),
-                                               field_at(t, s), afield_at(s, cur ^ 1), h->coef[s],
-                                               acc_D + (size_t)s * fb, acc_k + (size_t)s * fb,
-                                               q_cell + q_off[s], n_q[s], acc_q + q_off[s],
-                                               h->stream));
+                                               field_at(t0 + t, s), afield_at(s, cur ^ 1),
+                                               h->coef[s], acc_D + (size_t)s * fb,
+                                               acc_k + (size_t)s * fb, q_cell + q_off[s],
+                                               n_q[s], acc_q + q_off[s], h->stream));
             cur ^= 1;
         }
     }
