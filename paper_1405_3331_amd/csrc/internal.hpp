@@ -147,6 +147,19 @@ hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float
                                   const float* c, float* a_out, StencilCoef coef, double* acc_D,
                                   double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
                                   hipStream_t stream);
+// Two reverse steps per launch (n, then n - 1): a_in = a^{n+1}, e1/e0 = e^{n+1}/e^n,
+// c1/c0 = c^n/c^{n-1}, a_out = a^{n-1}; adjoint_pair_blocks(nx, ny) boxes own acc_D/acc_k
+// slots, and the sources are listed per box (adjoint_pair_sources: q_start[box] ..
+// q_start[box + 1] - 1 index q_index, the source numbers m of q_cell / acc_q).
+int adjoint_pair_blocks(int nx, int ny);
+void adjoint_pair_sources(int nx, int ny, const std::vector<int32_t>& cells,
+                          std::vector<int32_t>& start, std::vector<int32_t>& index);
+hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const float* e1,
+                                       const float* e0, const float* c1, const float* c0,
+                                       float* a_out, StencilCoef coef, double* acc_D,
+                                       double* acc_k, const int32_t* q_start,
+                                       const int32_t* q_index, const int32_t* q_cell,
+                                       double* acc_q, hipStream_t stream);
 hipError_t launch_adjoint_seed2d(const float* pos, const float* tip_target, const float* weight,
                                  float* acone, double* partial, int n, hipStream_t stream);
 

@@ -13,7 +13,12 @@
 //   c' = c + r ((w + e) + (s + n) - 4c) - k dt c, then c' += q / dx^2 at each source cell
 //   (a separate FP32 add, the rounding of a source pass), from a per-box list built once.
 // Reverse, with b = a^{n+1} + e^{n+1} (e: the cone samples' adjoints of the step):
-//   a^n = b + r Lap b - k dt b, and per-workgroup FP64 sums of b Lap c^n and b c^n.
+//   a^n = b + r Lap b - k dt b, and per-workgroup FP64 sums of b Lap c^n and b c^n.  Two
+//   reverse steps are taken per launch where the segment allows (k_field_adjoint2d_pair):
+//   a box of 256 x 8 cells holds b^{n+1} on the box and a two-cell ring in LDS, takes the
+//   first step on the box and a one-cell ring, adds e^n and takes the second on the box;
+//   per cell and two steps a^{n+1}, e^{n+1}, e^n, c^n, c^{n-1} are read and a^{n-1}
+//   written (12 instead of 16 B per cell and step, and half the launches).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -186,6 +191,175 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
             acc_q[m] += (double)(a_in[q_cell[m]] + e_in[q_cell[m]]);
 }
 
+// Two reverse steps (n, then n - 1) of one species.  Box b of the launch (256 x kPY cells)
+// owns acc_D[b] and acc_k[b] (both steps' sums are added) and the sources listed for it.
+// Every neighbour index is the clamped grid index mapped into the tile, so the walls are
+// exactly those of the single step.
+constexpr int kPY = 8;
+constexpr int kPW = kRX + 4, kPH = kPY + 4;   // b^{n+1}: box and a two-cell ring
+constexpr int kQW = kRX + 2, kQH = kPY + 2;   // b^n: box and a one-cell ring
+
+struct FieldAdjointPairArgs {
+    const float* a_in;    // a^{n+1}
+    const float* e1;      // e^{n+1}
+    const float* e0;      // e^n
+    const float* c1;      // c^n
+    const float* c0;      // c^{n-1}
+    float* a_out;         // a^{n-1}
+    int nx, ny, tx, ty, per_xcd;
+    StencilCoef k;
+    double* acc_D;
+    double* acc_k;
+    const int32_t* q_start;   // [n_boxes + 1] into q_index
+    const int32_t* q_index;   // source numbers m
+    const int32_t* q_cell;    // cell of source m
+    double* acc_q;
+};
+
+__global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairArgs a) {
+    const int box = box_of(a.per_xcd);
+    if (box >= a.tx * a.ty) return;   // whole workgroup: the barriers below stay uniform
+    const int bx = box % a.tx, by = box / a.tx;
+    const int x0 = bx * kRX, y0 = by * kPY;
+    const int nx = a.nx, ny = a.ny;
+    const int tid = threadIdx.x;
+    __shared__ float B1[kPH][kPW];
+    __shared__ float B2[kQH][kQW];
+    auto b1 = [&](int i, int j) { return B1[j - y0 + 2][i - x0 + 2]; };
+    auto b2 = [&](int i, int j) { return B2[j - y0 + 1][i - x0 + 1]; };
+
+    // Every global value this thread needs is requested first.  The thread owns column
+    // i = x0 + tid (clamped for loads where past the grid); threads 0..3 also load the
+    // ring columns x0 - 2, x0 - 1, x0 + 256, x0 + 257 of b^{n+1}, threads 0 and 1 the ring
+    // columns x0 - 1 and x0 + 256 of e^n.
+    const int i = x0 + tid;
+    const bool live = i < nx;
+    const int ci = min(i, nx - 1);
+    const int iw = max(ci - 1, 0), ie = min(ci + 1, nx - 1);
+    int brow[kPH];   // grid rows of the tile rows y0 - 2 .. y0 + kPY + 1, clamped
+#pragma unroll
+    for (int u = 0; u < kPH; ++u) brow[u] = min(max(y0 - 2 + u, 0), ny - 1);
+    const int xcol = tid < 2 ? tid : kRX + tid;              // tile column, threads 0..3
+    const int xi = min(max(x0 - 2 + xcol, 0), nx - 1);
+    const int ri = tid == 0 ? x0 - 1 : x0 + kRX;             // ring column, threads 0, 1
+    const int rci = min(max(ri, 0), nx - 1);
+    float va[kPH], ve[kPH], xa[kPH], xe[kPH];
+    float en[kQH], xen[kQH], c1v[kQH], c0v[kQH];
+    float c1w[kPY], c1e[kPY], c0w[kPY], c0e[kPY];
+#pragma unroll
+    for (int u = 0; u < kPH; ++u) {
+        const size_t at = (size_t)brow[u] * nx;
+        va[u] = a.a_in[at + ci];
+        ve[u] = a.e1[at + ci];
+    }
+    if (tid < 4) {
+#pragma unroll
+        for (int u = 0; u < kPH; ++u) {
+            const size_t at = (size_t)brow[u] * nx;
+            xa[u] = a.a_in[at + xi];
+            xe[u] = a.e1[at + xi];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kQH; ++r) en[r] = a.e0[(size_t)brow[r + 1] * nx + ci];
+    if (tid < 2) {
+#pragma unroll
+        for (int r = 0; r < kQH; ++r) xen[r] = a.e0[(size_t)brow[r + 1] * nx + rci];
+    }
+#pragma unroll
+    for (int r = 0; r < kQH; ++r) {
+        const size_t at = (size_t)brow[r + 1] * nx;
+        c1v[r] = a.c1[at + ci];
+        c0v[r] = a.c0[at + ci];
+    }
+#pragma unroll
+    for (int r = 0; r < kPY; ++r) {
+        const size_t at = (size_t)brow[r + 2] * nx;
+        c1w[r] = a.c1[at + iw];
+        c1e[r] = a.c1[at + ie];
+        c0w[r] = a.c0[at + iw];
+        c0e[r] = a.c0[at + ie];
+    }
+
+    // b^{n+1} = a^{n+1} + e^{n+1} on the box and a two-cell ring (ring cells outside the
+    // grid hold clamped copies and are never read: every read below uses clamped indices)
+#pragma unroll
+    for (int u = 0; u < kPH; ++u) B1[u][tid + 2] = va[u] + ve[u];
+    if (tid < 4) {
+#pragma unroll
+        for (int u = 0; u < kPH; ++u) B1[u][xcol] = xa[u] + xe[u];
+    }
+    __syncthreads();
+
+    // first step on the box and a one-cell ring: a^n = S b^{n+1}, b^n = a^n + e^n; the box
+    // cells add b^{n+1} Lap c^n and b^{n+1} c^n
+    double pD = 0.0, pk = 0.0;
+    if (live) {
+        const int w = max(i - 1, 0), e = min(i + 1, nx - 1);
+#pragma unroll
+        for (int r = 0; r < kQH; ++r) {
+            const int j = y0 - 1 + r;
+            if (j < 0 || j >= ny) continue;
+            const int js = max(j - 1, 0), jn = min(j + 1, ny - 1);
+            const float b = b1(i, j);
+            B2[r][tid + 1] = stencil2d(b, b1(w, j), b1(e, j), b1(i, js), b1(i, jn), a.k) + en[r];
+            if (r >= 1 && r <= kPY) {
+                const float v = c1v[r];
+                const float lap_c = ((c1w[r - 1] + c1e[r - 1]) + (c1v[r - 1] + c1v[r + 1])) -
+                                    4.0f * v;
+                pD += (double)b * (double)lap_c;
+                pk += (double)b * (double)v;
+            }
+        }
+    }
+    if (tid < 2 && ri >= 0 && ri < nx) {
+        const int w = max(ri - 1, 0), e = min(ri + 1, nx - 1);
+        const int col = tid == 0 ? 0 : kRX + 1;
+#pragma unroll
+        for (int r = 0; r < kQH; ++r) {
+            const int j = y0 - 1 + r;
+            if (j < 0 || j >= ny) continue;
+            const int js = max(j - 1, 0), jn = min(j + 1, ny - 1);
+            B2[r][col] = stencil2d(b1(ri, j), b1(w, j), b1(e, j), b1(ri, js), b1(ri, jn), a.k) +
+                         xen[r];
+        }
+    }
+    __syncthreads();
+
+    // second step on the box: a^{n-1} = S b^n, and b^n Lap c^{n-1}, b^n c^{n-1}
+    if (live) {
+        const int w = max(i - 1, 0), e = min(i + 1, nx - 1);
+        const int rows = min(kPY, ny - y0);
+#pragma unroll
+        for (int r = 0; r < kPY; ++r) {
+            if (r >= rows) break;
+            const int j = y0 + r;
+            const int js = max(j - 1, 0), jn = min(j + 1, ny - 1);
+            const float b = b2(i, j);
+            a.a_out[(size_t)j * nx + i] =
+                stencil2d(b, b2(w, j), b2(e, j), b2(i, js), b2(i, jn), a.k);
+            const float v = c0v[r + 1];
+            const float lap_c = ((c0w[r] + c0e[r]) + (c0v[r] + c0v[r + 2])) - 4.0f * v;
+            pD += (double)b * (double)lap_c;
+            pk += (double)b * (double)v;
+        }
+    }
+    const double sD = block_sum_fp64(pD);
+    const double sk = block_sum_fp64(pk);
+    if (tid == 0) {
+        a.acc_D[box] += sD;
+        a.acc_k[box] += sk;
+    }
+    // b^{n+1}, then b^n, at this box's source cells (each source is listed by one box)
+    for (int q = a.q_start[box] + tid; q < a.q_start[box + 1]; q += kRX) {
+        const int m = a.q_index[q];
+        const int cell = a.q_cell[m];
+        const int ci = cell % nx, cj = cell / nx;
+        a.acc_q[m] += (double)b1(ci, cj);
+        a.acc_q[m] += (double)b2(ci, cj);
+    }
+}
+
 }  // namespace
 
 hipError_t field2d_prepare(Field2DStep& f, int nx, int ny, int n_species,
@@ -280,6 +454,60 @@ hipError_t launch_field2d_rows(const Field2DStep& f, const float* const* in, flo
 int adjoint_field_blocks(int nx, int ny) {
     const Tiles2D t = tiles_for(nx, ny, kAY);
     return t.tx * t.ty;
+}
+
+int adjoint_pair_blocks(int nx, int ny) {
+    const Tiles2D t = tiles_for(nx, ny, kPY);
+    return t.tx * t.ty;
+}
+
+void adjoint_pair_sources(int nx, int ny, const std::vector<int32_t>& cells,
+                          std::vector<int32_t>& start, std::vector<int32_t>& index) {
+    const Tiles2D t = tiles_for(nx, ny, kPY);
+    const int nb = t.tx * t.ty;
+    std::vector<std::vector<int32_t>> per_box(nb);
+    for (size_t m = 0; m < cells.size(); ++m) {
+        const int i = cells[m] % nx, j = cells[m] / nx;
+        per_box[(j / kPY) * t.tx + i / kRX].push_back((int32_t)m);
+    }
+    start.assign(nb + 1, 0);
+    index.clear();
+    for (int b = 0; b < nb; ++b) {
+        start[b] = (int32_t)index.size();
+        index.insert(index.end(), per_box[b].begin(), per_box[b].end());
+    }
+    start[nb] = (int32_t)index.size();
+}
+
+hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const float* e1,
+                                       const float* e0, const float* c1, const float* c0,
+                                       float* a_out, StencilCoef coef, double* acc_D,
+                                       double* acc_k, const int32_t* q_start,
+                                       const int32_t* q_index, const int32_t* q_cell,
+                                       double* acc_q, hipStream_t stream) {
+    const Tiles2D t = tiles_for(nx, ny, kPY);
+    FieldAdjointPairArgs a{};
+    a.a_in = a_in;
+    a.e1 = e1;
+    a.e0 = e0;
+    a.c1 = c1;
+    a.c0 = c0;
+    a.a_out = a_out;
+    a.nx = nx;
+    a.ny = ny;
+    a.tx = t.tx;
+    a.ty = t.ty;
+    a.per_xcd = (t.tx * t.ty + kXcds - 1) / kXcds;
+    a.k = coef;
+    a.acc_D = acc_D;
+    a.acc_k = acc_k;
+    a.q_start = q_start;
+    a.q_index = q_index;
+    a.q_cell = q_cell;
+    a.acc_q = acc_q;
+    hipLaunchKernelGGL(k_field_adjoint2d_pair, dim3(a.per_xcd * kXcds), dim3(kRX), 0, stream,
+                       a);
+    return hipGetLastError();
 }
 
 hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* e_in,

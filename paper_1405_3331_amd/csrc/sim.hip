@@ -1051,7 +1051,9 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     const int ns = h->n_species, M = h->n_cones, nx = h->nx, ny = h->ny;
     const size_t cells = (size_t)h->n_cells, Ms = (size_t)M;
     const int K = (int)std::min<int64_t>(a->every, std::max<int64_t>(a->n_steps, 1));
-    const int fb = adjoint_field_blocks(nx, ny);
+    // accumulator slots: enough for the boxes of the single- and the two-step reverse field
+    // kernels (both are used; the host sums every slot)
+    const int fb = std::max(adjoint_field_blocks(nx, ny), adjoint_pair_blocks(nx, ny));
     int n_q[SIM_MAX_SPECIES] = {0, 0}, q_off[SIM_MAX_SPECIES] = {0, 0};
     for (int s = 0; s < ns; ++s) n_q[s] = (int)h->src_caller_cell[s].size();
     q_off[1] = n_q[0];
@@ -1077,6 +1079,8 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     float* afield = nullptr;
     double* acc = nullptr;
     int32_t* q_cell = nullptr;
+    int32_t* q_start = nullptr;
+    int32_t* q_index = nullptr;
     auto free_all = [&]() {
         dfree(tape);
         dfree(tape_cones);
@@ -1084,7 +1088,20 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         dfree(afield);
         dfree(acc);
         dfree(q_cell);
+        dfree(q_start);
+        dfree(q_index);
     };
+    // each species' sources listed by the box of the two-step kernel that holds their cell:
+    // q_start[s * (nbp + 1) + box] indexes q_index (source numbers within the species)
+    const int nbp = adjoint_pair_blocks(nx, ny);
+    std::vector<int32_t> q_start_h((size_t)ns * (nbp + 1)), q_index_h;
+    for (int s = 0; s < ns; ++s) {
+        std::vector<int32_t> st, ix;
+        adjoint_pair_sources(nx, ny, h->src_caller_cell[s], st, ix);
+        for (int b = 0; b <= nbp; ++b)
+            q_start_h[(size_t)s * (nbp + 1) + b] = st[b] + (int32_t)q_index_h.size();
+        q_index_h.insert(q_index_h.end(), ix.begin(), ix.end());
+    }
     hipError_t e;
     const size_t acc_n = (size_t)2 * ns * fb + (size_t)std::max(nq_all, 1);
     if ((e = dalloc(&tape, (size_t)(window + 1) * ns * cells)) != hipSuccess ||
@@ -1092,7 +1109,9 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         (e = dalloc(&scatter, (size_t)K * ns * cells)) != hipSuccess ||
         (e = dalloc(&afield, (size_t)2 * ns * cells)) != hipSuccess ||
         (e = dalloc(&acc, acc_n)) != hipSuccess ||
-        (e = dalloc(&q_cell, (size_t)std::max(nq_all, 1))) != hipSuccess) {
+        (e = dalloc(&q_cell, (size_t)std::max(nq_all, 1))) != hipSuccess ||
+        (e = dalloc(&q_start, q_start_h.size())) != hipSuccess ||
+        (e = dalloc(&q_index, std::max<size_t>(q_index_h.size(), 1))) != hipSuccess) {
         free_all();
         if (e == hipErrorOutOfMemory)
             return fail(h, SIM_ENOMEM, "adjoint workspace: out of device memory");
@@ -1110,6 +1129,11 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         if (n_q[s] > 0)
             ADJ_TRY(hipMemcpyAsync(q_cell + q_off[s], h->src_caller_cell[s].data(), n_q[s] * 4,
                                    hipMemcpyHostToDevice, h->stream));
+    ADJ_TRY(hipMemcpyAsync(q_start, q_start_h.data(), q_start_h.size() * 4,
+                           hipMemcpyHostToDevice, h->stream));
+    if (!q_index_h.empty())
+        ADJ_TRY(hipMemcpyAsync(q_index, q_index_h.data(), q_index_h.size() * 4,
+                               hipMemcpyHostToDevice, h->stream));
     ADJ_TRY(hipMemsetAsync(afield, 0, (size_t)2 * ns * cells * sizeof(float), h->stream));
     ADJ_TRY(hipMemsetAsync(acc, 0, acc_n * sizeof(double), h->stream));
     double* acc_D = acc;
@@ -1159,8 +1183,19 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
                                               tape_cones + (size_t)(t0 - t_base) * Ms,
                                               h->cones.status, h->cones.event_step, a->acone,
                                               M, h->stream));
-        // reverse the segment's field steps
-        for (int t = len - 1; t >= 0; --t) {
+        // reverse the segment's field steps, two per launch while two remain
+        int t = len - 1;
+        for (; t >= 1; t -= 2) {
+            for (int s = 0; s < ns; ++s)
+                ADJ_TRY(launch_field_adjoint2d_pair(
+                    nx, ny, afield_at(s, cur), scatter_at(t, s), scatter_at(t - 1, s),
+                    field_at(t0 + t, s), field_at(t0 + t - 1, s), afield_at(s, cur ^ 1),
+                    h->coef[s], acc_D + (size_t)s * fb, acc_k + (size_t)s * fb,
+                    q_start + (size_t)s * (nbp + 1), q_index, q_cell + q_off[s],
+                    acc_q + q_off[s], h->stream));
+            cur ^= 1;
+        }
+        if (t == 0) {
             for (int s = 0; s < ns; ++s)
                 ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), scatter_at(t, s),
                                                field_at(t0 + t, s), afield_at(s, cur ^ 1),

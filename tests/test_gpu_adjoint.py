@@ -56,6 +56,14 @@ def test_gradient_matches_oracle(n_species):
     _compare(sc, 120, 50)   # three segments, the last one ragged
 
 
+def test_ragged_boxes_two_species():
+    """A grid that ends inside the reverse kernels' boxes on both axes (300 x 43: two
+    256-column boxes, rows not a multiple of 4 or 8), two species, odd and even segment
+    lengths (25, 25, 10): the two-step and the single-step reverse launches both run."""
+    sc = _case(2, n=(300, 43), cones=64, seed=9)
+    _compare(sc, 60, 25)
+
+
 def test_checkpoint_spacing_does_not_change_the_gradient():
     sc = _case(1, seed=7)
     a = _compare(sc, 90, 90)   # whole run recorded once
