@@ -44,6 +44,12 @@ struct Field2DStep {
     int32_t* src_row = nullptr;     // per entry: row j
     int32_t* src_col = nullptr;     // per entry: thread of the box owning the cell
     float* src_q = nullptr;         // per entry: amount / dx^2
+    // two steps per launch (launch_field2d_pair): per box of 256 x 8 cells, the sources on
+    // the box and its one-cell ring, as (tile position, amount / dx^2)
+    int n_pair_boxes = 0;
+    int32_t* pair_start = nullptr;  // [n_pair_boxes + 1]
+    int32_t* pair_pos = nullptr;    // per entry: row * 258 + column within the ringed box
+    float* pair_q = nullptr;
 };
 struct Field2DStepArgs {
     const float* in[2];
@@ -59,6 +65,9 @@ struct Field2DStepArgs {
 hipError_t field2d_prepare(Field2DStep& f, int nx, int ny, int n_species,
                            const std::vector<int32_t>* cells, const std::vector<float>* q);
 void field2d_release(Field2DStep& f);
+// Two steps: out1 = the state after one step, out2 after two (every species).
+hipError_t launch_field2d_pair(const Field2DStep& f, const float* const* in, float* const* out1,
+                               float* const* out2, const StencilCoef* coef, hipStream_t stream);
 // start/stop (may be null): events the launch itself records.
 hipError_t launch_field2d_rows(const Field2DStep& f, const float* const* in, float* const* out,
                                const StencilCoef* coef, hipStream_t stream,

@@ -12,6 +12,10 @@
 // Step (Sec. 3.4 cue field: diffusion with first-order decay and point sources):
 //   c' = c + r ((w + e) + (s + n) - 4c) - k dt c, then c' += q / dx^2 at each source cell
 //   (a separate FP32 add, the rounding of a source pass), from a per-box list built once.
+//   Where every state is kept (the gradient sweep's re-run), k_field2d_pair takes two steps
+//   per launch: a box of 256 x 8 cells holds c^n on the box and a two-cell ring in LDS,
+//   steps the box and a one-cell ring (with the sources there), writes c^{n+1}, steps the
+//   box again and writes c^{n+2}: 12 instead of 16 B per cell and two steps, same bits.
 // Reverse, with b = a^{n+1} + e^{n+1} (e: the cone samples' adjoints of the step):
 //   a^n = b + r Lap b - k dt b, and per-workgroup FP64 sums of b Lap c^n and b c^n.  Two
 //   reverse steps are taken per launch where the segment allows (k_field_adjoint2d_pair):
@@ -33,6 +37,11 @@ namespace {
 // step: 256 columns x 8 rows, all 8 rows' loads at once; reverse: 256 x 4 (measured best)
 constexpr int kRX = 256, kRY = 8, kRUnroll = 8;
 constexpr int kAY = 4, kAUnroll = 4;
+// two steps per launch (forward and reverse): boxes of 256 x kPY cells held with a two-cell
+// ring (kPW x kPH) for the first step and a one-cell ring (kQW x kQH) for the second
+constexpr int kPY = 8;
+constexpr int kPW = kRX + 4, kPH = kPY + 4;
+constexpr int kQW = kRX + 2, kQH = kPY + 2;
 constexpr int kXcds = 8;
 
 struct Tiles2D {
@@ -191,14 +200,116 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
             acc_q[m] += (double)(a_in[q_cell[m]] + e_in[q_cell[m]]);
 }
 
+// Two forward steps of one species per box; the stencil and the separate source add are
+// those of the single step, and neighbour indices are clamped grid indices mapped into the
+// tile, so the result has the single step's bits.
+struct Field2DPairArgs {
+    const float* in[2];
+    float* out1[2];
+    float* out2[2];
+    StencilCoef coef[2];
+    int nx, ny, n_species, tx, ty, per_xcd;
+    const int32_t* src_start;   // [boxes + 1]
+    const int32_t* src_pos;     // row * (kRX + 2) + column in the box with its one-cell ring
+    const float* src_q;
+};
+
+
+__global__ __launch_bounds__(kRX) void k_field2d_pair(Field2DPairArgs a) {
+    const int box = box_of(a.per_xcd);
+    if (box >= a.n_species * a.tx * a.ty) return;   // whole workgroup
+    const int bx = box % a.tx, by = (box / a.tx) % a.ty, s = box / (a.tx * a.ty);
+    const int x0 = bx * kRX, y0 = by * kPY;
+    const int nx = a.nx, ny = a.ny;
+    const int tid = threadIdx.x;
+    const StencilCoef k = a.coef[s];
+    __shared__ float T0[kPH][kPW];   // c^n: box and a two-cell ring
+    __shared__ float T1[kQH][kQW];   // c^{n+1}: box and a one-cell ring
+    __shared__ float T2[kPY][kRX];   // c^{n+2}: box
+    auto t0 = [&](int i, int j) { return T0[j - y0 + 2][i - x0 + 2]; };
+    auto t1 = [&](int i, int j) { return T1[j - y0 + 1][i - x0 + 1]; };
+
+    // c^n (clamped into the grid; ring copies outside it are never read), this thread's
+    // column and, for threads 0..3, the ring columns x0 - 2, x0 - 1, x0 + 256, x0 + 257
+    const float* src = a.in[s];
+    const int i = x0 + tid;
+    const int ci = min(i, nx - 1);
+    const int xcol = tid < 2 ? tid : kRX + tid;
+    const int xi = min(max(x0 - 2 + xcol, 0), nx - 1);
+    float v[kPH], xv[kPH];
+#pragma unroll
+    for (int u = 0; u < kPH; ++u)
+        v[u] = src[(size_t)min(max(y0 - 2 + u, 0), ny - 1) * nx + ci];
+    if (tid < 4) {
+#pragma unroll
+        for (int u = 0; u < kPH; ++u)
+            xv[u] = src[(size_t)min(max(y0 - 2 + u, 0), ny - 1) * nx + xi];
+    }
+#pragma unroll
+    for (int u = 0; u < kPH; ++u) T0[u][tid + 2] = v[u];
+    if (tid < 4) {
+#pragma unroll
+        for (int u = 0; u < kPH; ++u) T0[u][xcol] = xv[u];
+    }
+    __syncthreads();
+
+    // first step on the box and a one-cell ring (in-grid cells)
+    auto step1 = [&](int ii, int col) {
+        const int w = max(ii - 1, 0), e = min(ii + 1, nx - 1);
+#pragma unroll
+        for (int r = 0; r < kQH; ++r) {
+            const int j = y0 - 1 + r;
+            if (j < 0 || j >= ny) continue;
+            const int js = max(j - 1, 0), jn = min(j + 1, ny - 1);
+            T1[r][col] = stencil2d(t0(ii, j), t0(w, j), t0(e, j), t0(ii, js), t0(ii, jn), k);
+        }
+    };
+    if (i < nx) step1(i, tid + 1);
+    if (tid < 2) {
+        const int ri = tid == 0 ? x0 - 1 : x0 + kRX;
+        if (ri >= 0 && ri < nx) step1(ri, tid == 0 ? 0 : kRX + 1);
+    }
+    __syncthreads();
+    // its sources (every listed cell is in the grid and appears once)
+    const int q0 = a.src_start[box], q1 = a.src_start[box + 1];
+    for (int q = q0 + tid; q < q1; q += kRX) (&T1[0][0])[a.src_pos[q]] += a.src_q[q];
+    __syncthreads();
+
+    // c^{n+1} out, then the second step on the box
+    if (i < nx) {
+        const int w = max(i - 1, 0), e = min(i + 1, nx - 1);
+        const int rows = min(kPY, ny - y0);
+        float* out1 = a.out1[s];
+#pragma unroll
+        for (int r = 0; r < kPY; ++r) {
+            if (r >= rows) break;
+            const int j = y0 + r;
+            const int js = max(j - 1, 0), jn = min(j + 1, ny - 1);
+            out1[(size_t)j * nx + i] = T1[r + 1][tid + 1];
+            T2[r][tid] = stencil2d(t1(i, j), t1(w, j), t1(e, j), t1(i, js), t1(i, jn), k);
+        }
+    }
+    __syncthreads();
+    for (int q = q0 + tid; q < q1; q += kRX) {
+        const int r = a.src_pos[q] / kQW, col = a.src_pos[q] % kQW;
+        if (r >= 1 && r <= kPY && col >= 1 && col <= kRX) T2[r - 1][col - 1] += a.src_q[q];
+    }
+    __syncthreads();
+    if (i < nx) {
+        const int rows = min(kPY, ny - y0);
+        float* out2 = a.out2[s];
+#pragma unroll
+        for (int r = 0; r < kPY; ++r) {
+            if (r >= rows) break;
+            out2[(size_t)(y0 + r) * nx + i] = T2[r][tid];
+        }
+    }
+}
+
 // Two reverse steps (n, then n - 1) of one species.  Box b of the launch (256 x kPY cells)
 // owns acc_D[b] and acc_k[b] (both steps' sums are added) and the sources listed for it.
 // Every neighbour index is the clamped grid index mapped into the tile, so the walls are
 // exactly those of the single step.
-constexpr int kPY = 8;
-constexpr int kPW = kRX + 4, kPH = kPY + 4;   // b^{n+1}: box and a two-cell ring
-constexpr int kQW = kRX + 2, kQH = kPY + 2;   // b^n: box and a one-cell ring
-
 struct FieldAdjointPairArgs {
     const float* a_in;    // a^{n+1}
     const float* e1;      // e^{n+1}
@@ -408,6 +519,46 @@ hipError_t field2d_prepare(Field2DStep& f, int nx, int ny, int n_species,
          (e = hipMemcpy(f.src_q, amount.data(), amount.size() * sizeof(float),
                         hipMemcpyHostToDevice)) != hipSuccess))
         return e;
+    // two-step boxes: the sources on each box and its one-cell ring (a cell near a box edge
+    // is listed by up to four boxes)
+    const Tiles2D p = tiles_for(nx, ny, kPY);
+    const int n_pair = n_species * p.tx * p.ty;
+    std::vector<std::vector<std::pair<int32_t, float>>> per_pair(n_pair);
+    for (int s = 0; s < n_species; ++s)
+        for (size_t m = 0; m < cells[s].size(); ++m) {
+            const int i = cells[s][m] % nx, j = cells[s][m] / nx;
+            for (int by = std::max(j / kPY - 1, 0); by <= std::min(j / kPY + 1, p.ty - 1); ++by)
+                for (int bx = std::max(i / kRX - 1, 0); bx <= std::min(i / kRX + 1, p.tx - 1);
+                     ++bx) {
+                    const int r = j - (by * kPY - 1), c = i - (bx * kRX - 1);
+                    if (r < 0 || r >= kQH || c < 0 || c >= kQW) continue;
+                    per_pair[(s * p.ty + by) * p.tx + bx].push_back({r * kQW + c, q[s][m]});
+                }
+        }
+    std::vector<int32_t> pstart(n_pair + 1, 0), ppos;
+    std::vector<float> pq;
+    for (int b = 0; b < n_pair; ++b) {
+        for (auto& en : per_pair[b]) {
+            ppos.push_back(en.first);
+            pq.push_back(en.second);
+        }
+        pstart[b + 1] = (int32_t)ppos.size();
+    }
+    const size_t n_p = std::max<size_t>(ppos.size(), 1);
+    if ((e = hipMalloc((void**)&f.pair_start, pstart.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&f.pair_pos, n_p * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void**)&f.pair_q, n_p * sizeof(float))) != hipSuccess)
+        return e;
+    if ((e = hipMemcpy(f.pair_start, pstart.data(), pstart.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if (!ppos.empty() &&
+        ((e = hipMemcpy(f.pair_pos, ppos.data(), ppos.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+         (e = hipMemcpy(f.pair_q, pq.data(), pq.size() * sizeof(float),
+                        hipMemcpyHostToDevice)) != hipSuccess))
+        return e;
+    f.n_pair_boxes = n_pair;
     f.nx = nx;
     f.ny = ny;
     f.n_species = n_species;
@@ -420,6 +571,9 @@ void field2d_release(Field2DStep& f) {
     if (f.src_row) (void)hipFree(f.src_row);
     if (f.src_col) (void)hipFree(f.src_col);
     if (f.src_q) (void)hipFree(f.src_q);
+    if (f.pair_start) (void)hipFree(f.pair_start);
+    if (f.pair_pos) (void)hipFree(f.pair_pos);
+    if (f.pair_q) (void)hipFree(f.pair_q);
     f = Field2DStep{};
 }
 
@@ -449,6 +603,29 @@ hipError_t launch_field2d_rows(const Field2DStep& f, const float* const* in, flo
                                args, 0, stream);
     return hipExtLaunchKernel((const void*)k_field2d_rows, dim3(a.per_xcd * kXcds), dim3(kRX),
                               args, 0, stream, start, stop, 0);
+}
+
+hipError_t launch_field2d_pair(const Field2DStep& f, const float* const* in, float* const* out1,
+                               float* const* out2, const StencilCoef* coef, hipStream_t stream) {
+    const Tiles2D t = tiles_for(f.nx, f.ny, kPY);
+    Field2DPairArgs a = {};
+    for (int s = 0; s < f.n_species; ++s) {
+        a.in[s] = in[s];
+        a.out1[s] = out1[s];
+        a.out2[s] = out2[s];
+        a.coef[s] = coef[s];
+    }
+    a.nx = f.nx;
+    a.ny = f.ny;
+    a.n_species = f.n_species;
+    a.tx = t.tx;
+    a.ty = t.ty;
+    a.per_xcd = (f.n_pair_boxes + kXcds - 1) / kXcds;
+    a.src_start = f.pair_start;
+    a.src_pos = f.pair_pos;
+    a.src_q = f.pair_q;
+    hipLaunchKernelGGL(k_field2d_pair, dim3(a.per_xcd * kXcds), dim3(kRX), 0, stream, a);
+    return hipGetLastError();
 }
 
 int adjoint_field_blocks(int nx, int ny) {

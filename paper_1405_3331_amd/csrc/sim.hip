@@ -1157,7 +1157,15 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         hipError_t r = hipMemcpyAsync(field_at(t0, 0), a->ckpt_field + (size_t)j * ns * cells,
                                       (size_t)ns * cells * 4, hipMemcpyDeviceToDevice,
                                       h->stream);
-        for (int64_t t = t0; t < t0 + len && r == hipSuccess; ++t) {
+        // two steps per launch (every state is kept), the last one alone if odd
+        int64_t t = t0;
+        for (; t + 2 <= t0 + len && r == hipSuccess; t += 2) {
+            const float* in[SIM_MAX_SPECIES] = {field_at(t, 0), field_at(t, ns - 1)};
+            float* out1[SIM_MAX_SPECIES] = {field_at(t + 1, 0), field_at(t + 1, ns - 1)};
+            float* out2[SIM_MAX_SPECIES] = {field_at(t + 2, 0), field_at(t + 2, ns - 1)};
+            r = launch_field2d_pair(h->field2d, in, out1, out2, h->coef, h->stream);
+        }
+        if (t < t0 + len && r == hipSuccess) {
             const float* in[SIM_MAX_SPECIES] = {field_at(t, 0), field_at(t, ns - 1)};
             float* out[SIM_MAX_SPECIES] = {field_at(t + 1, 0), field_at(t + 1, ns - 1)};
             r = launch_field2d_rows(h->field2d, in, out, h->coef, h->stream);
