@@ -64,6 +64,30 @@ def test_ragged_boxes_two_species():
     _compare(sc, 60, 25)
 
 
+def test_sources_on_box_edges():
+    """Sources on the cells either side of the two-step kernels' box edges (columns 255/256,
+    rows 7/8 and 15/16 of 256 x 8 boxes), at the walls and duplicated: the forward re-run
+    adds them in the one-cell ring of the neighbouring boxes, the reverse gathers them per
+    box.  Two species, a segment of odd length."""
+    sc = _case(2, n=(300, 24), cones=64, seed=11)
+    cells = [(255, 7), (256, 8), (255, 8), (256, 7), (0, 0), (299, 23), (128, 15), (128, 16),
+             (255, 16), (0, 8)]
+    for s, sp in enumerate(sc.species):
+        picked = cells[s::2] + [cells[s]]            # one cell listed twice
+        sp.source_cell = np.array([j * 300 + i for i, j in picked], dtype=np.int32)
+        sp.source_q = np.linspace(2.0, 6.0, len(picked)).astype(np.float32).astype(np.float64)
+    _compare(sc, 45, 15)
+
+
+def test_tiny_grid():
+    """A 7 x 2 grid (short steps, one target far enough for the cones to keep moving):
+    every box is ragged and nearly every neighbour index is clamped; segments of 4, 4, 1."""
+    sc = scenarios.make_scenario("tiny", 2, (7, 2), 1.0, 0.2, ((1.0, 0.01, 1.0),), 2,
+                                 (2.0, 8.0), 4, 1, 0.2, 0.05, 10.0, math.pi / 30.0, 0.1,
+                                 seed=12)
+    _compare(sc, 9, 4)
+
+
 def test_checkpoint_spacing_does_not_change_the_gradient():
     sc = _case(1, seed=7)
     a = _compare(sc, 90, 90)   # whole run recorded once
