@@ -31,7 +31,8 @@ namespace cuesim {
 namespace {
 
 constexpr int kAdjThreads = 256;
-constexpr int kSegThreads = 64;   // segment kernels: one short wave per CU where possible
+constexpr int kSegThreads = 32;   // segment kernels: half-wave workgroups, so that a few
+                                  // thousand cones reach every CU (measured: 64 is ~1.5% slower)
 
 __device__ double adj_block_sum(double v) {
     __shared__ double part[kAdjThreads / 64];
