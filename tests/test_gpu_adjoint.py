@@ -92,7 +92,9 @@ def test_checkpoint_spacing_does_not_change_the_gradient():
     sc = _case(1, seed=7)
     a = _compare(sc, 90, 90)   # whole run recorded once
     b = _compare(sc, 90, 7)    # many short segments
+    c = _compare(sc, 90, 1)    # one-step segments: single-step kernels only
     assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
+    assert np.abs(a - c).max() <= 1e-5 * np.abs(a).max()
 
 
 def test_tiled_forward_and_plain_forward_agree():
