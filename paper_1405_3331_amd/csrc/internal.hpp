@@ -44,7 +44,7 @@ struct Field2DStep {
     int32_t* src_row = nullptr;     // per entry: row j
     int32_t* src_col = nullptr;     // per entry: thread of the box owning the cell
     float* src_q = nullptr;         // per entry: amount / dx^2
-    // two steps per launch (launch_field2d_pair): per box of 256 x 8 cells, the sources on
+    // two steps per launch (launch_field2d_pair): per box of 256 x 4 cells, the sources on
     // the box and its one-cell ring, as (tile position, amount / dx^2)
     int n_pair_boxes = 0;
     int32_t* pair_start = nullptr;  // [n_pair_boxes + 1]

@@ -13,13 +13,13 @@
 //   c' = c + r ((w + e) + (s + n) - 4c) - k dt c, then c' += q / dx^2 at each source cell
 //   (a separate FP32 add, the rounding of a source pass), from a per-box list built once.
 //   Where every state is kept (the gradient sweep's re-run), k_field2d_pair takes two steps
-//   per launch: a box of 256 x 8 cells holds c^n on the box and a two-cell ring in LDS,
+//   per launch: a box of 256 x 4 cells holds c^n on the box and a two-cell ring in LDS,
 //   steps the box and a one-cell ring (with the sources there), writes c^{n+1}, steps the
 //   box again and writes c^{n+2}: 12 instead of 16 B per cell and two steps, same bits.
 // Reverse, with b = a^{n+1} + e^{n+1} (e: the cone samples' adjoints of the step):
 //   a^n = b + r Lap b - k dt b, and per-workgroup FP64 sums of b Lap c^n and b c^n.  Two
 //   reverse steps are taken per launch where the segment allows (k_field_adjoint2d_pair):
-//   a box of 256 x 8 cells holds b^{n+1} on the box and a two-cell ring in LDS, takes the
+//   a box of 256 x 4 cells holds b^{n+1} on the box and a two-cell ring in LDS, takes the
 //   first step on the box and a one-cell ring, adds e^n and takes the second on the box;
 //   per cell and two steps a^{n+1}, e^{n+1}, e^n, c^n, c^{n-1} are read and a^{n-1}
 //   written (12 instead of 16 B per cell and step, and half the launches).
@@ -38,8 +38,9 @@ namespace {
 constexpr int kRX = 256, kRY = 8, kRUnroll = 8;
 constexpr int kAY = 4, kAUnroll = 4;
 // two steps per launch (forward and reverse): boxes of 256 x kPY cells held with a two-cell
-// ring (kPW x kPH) for the first step and a one-cell ring (kQW x kQH) for the second
-constexpr int kPY = 8;
+// ring (kPW x kPH) for the first step and a one-cell ring (kQW x kQH) for the second; 4 rows
+// measured best (2, 6 and 8 rows slower)
+constexpr int kPY = 4;
 constexpr int kPW = kRX + 4, kPH = kPY + 4;
 constexpr int kQW = kRX + 2, kQH = kPY + 2;
 constexpr int kXcds = 8;

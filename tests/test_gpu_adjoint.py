@@ -66,9 +66,9 @@ def test_ragged_boxes_two_species():
 
 def test_sources_on_box_edges():
     """Sources on the cells either side of the two-step kernels' box edges (columns 255/256,
-    rows 7/8 and 15/16 of 256 x 8 boxes), at the walls and duplicated: the forward re-run
-    adds them in the one-cell ring of the neighbouring boxes, the reverse gathers them per
-    box.  Two species, a segment of odd length."""
+    rows 7/8 and 15/16, edges of 4- and of 8-row boxes), at the walls and duplicated: the
+    forward re-run adds them in the one-cell ring of the neighbouring boxes, the reverse
+    gathers them per box.  Two species, a segment of odd length."""
     sc = _case(2, n=(300, 24), cones=64, seed=11)
     cells = [(255, 7), (256, 8), (255, 8), (256, 7), (0, 0), (299, 23), (128, 15), (128, 16),
              (255, 16), (0, 8)]
