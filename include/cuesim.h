@@ -17,10 +17,15 @@
  *   4. turns its heading toward the direction of h + turn_gain * g (the vector-addition
  *      steering of Sec. 3.5, Eqs. 6-7: angle from the dot and cross products), by at most
  *      max_turn (pi/30 in Sec. 3.5);
- *   5. adds angular noise: four normal deviates from Philox4x32-10 with
- *      key = (seed lo, seed hi), counter = (original cone index, n, 0, sim_index), by
- *      Box-Muller on uniforms ((x >> 9) + 0.5) * 2^-23 (the stateless per-thread generator
- *      style of Sec. 5.1).  2D: theta += noise_sigma * Z0, wrapped to [-pi, pi).  3D: h is
+ *   5. adds angular noise from Philox4x32-10 with key = (seed lo, seed hi) (the stateless
+ *      per-thread generator style of Sec. 5.1).  Each 128-bit block (x0, x1, x2, x3) gives
+ *      two Box-Muller pairs on uniforms u = ((x >> 9) + 0.5) * 2^-23: (Z0, Z1) from
+ *      (u0, u1) and (Z2, Z3) from (u2, u3), Z0 = sqrt(-2 ln u0) cos(2 pi u1),
+ *      Z1 = sqrt(-2 ln u0) sin(2 pi u1).
+ *      2D: one block serves two steps: counter = (original cone index, floor(n / 2), 0,
+ *      sim_index); step n takes the pair (Z0, Z1) when n is even and (Z2, Z3) when n is odd,
+ *      and theta += noise_sigma * (the pair's first deviate), wrapped to [-pi, pi).
+ *      3D: one block per step: counter = (original cone index, n, 0, sim_index); h is
  *      rotated by |w| toward w = noise_sigma * (z - (z.h) h), z = (Z0, Z1, Z2), then
  *      renormalised;
  *   6. advances step_len along the heading (a fixed distance per step, Sec. 3.5);
@@ -51,8 +56,14 @@ typedef enum sim_status {
     SIM_ENOMEM = -3,   /* device or host allocation failed */
     SIM_EDEVICE = -4,  /* a HIP call failed; see sim_last_error */
     SIM_ERANGE = -5,   /* destination buffer too small (bytes_written = size needed) */
-    SIM_ESTATE = -6    /* the handle hit a sticky device error earlier: only
+    SIM_ESTATE = -6,   /* the handle hit a sticky device error earlier: only
                           sim_last_error and sim_destroy remain usable */
+    SIM_ENONFINITE = -7 /* a mass check (a SIM_MASS read, or the periodic check of
+                          sim_set_mass_check) found a non-finite total: the fields hold NaN
+                          or Inf.  Sticky: sim_step and sim_adjoint_run refuse with this
+                          status (and sim_synchronize reports it) until the state has been
+                          replaced through sim_write_state and a SIM_MASS read finds every
+                          total finite again.  Reads and writes stay usable. */
 } sim_status;
 
 /* Cone status codes (CONE_STATUS items and the kind column of EVENTS). */
@@ -120,11 +131,12 @@ typedef struct sim_params {
      * decision of Sec. 3.5, Eq. 5: with c the concentration of species 0 at the tip
      * (interpolated from the cell centres like the gradient) inside the detection window
      * [c_min, c_max] and g != 0, the heading turns by max_turn to the right (clockwise)
-     * when SNR + Z0 > 0 and to the left otherwise, where
+     * when SNR + z0 > 0 and to the left otherwise, where (z0, z1) is the step's normal
+     * pair of step 5 (2D layout: (Z0, Z1) on even steps, (Z2, Z3) on odd ones) and
      *   SNR = snr_scale * mu * sqrt(gamma / (1 + gamma)^3) * sin(theta - theta_g),
      *   gamma = c / kd, mu = cone_width * |g| / c, theta_g = the direction of g;
-     * outside the window it does not turn.  The angular noise is then noise_sigma * Z1
-     * (Z0 decided the turn).  turn_gain is unused.  Requires dim = 2, kd > 0,
+     * outside the window it does not turn.  The angular noise is then noise_sigma * z1
+     * (z0 decided the turn).  turn_gain is unused.  Requires dim = 2, kd > 0,
      * 0 < c_min <= c_max, cone_width >= 0, all finite.  The trajectory-loss gradient
      * (sim_adjoint_run) is defined for SIM_TURN_VECTOR only. */
     int32_t turn_law;
@@ -141,13 +153,23 @@ typedef struct sim_handle sim_handle;
  * *out = NULL and sim_last_error(NULL) describes the problem. */
 sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out);
 
-/* Enqueue n_steps >= 0 time steps on the handle's stream and return without waiting. */
+/* Enqueue n_steps >= 0 time steps on the handle's stream and return without waiting.
+ * SIM_ENONFINITE (nothing enqueued) once a mass check has found a non-finite total. */
 sim_status sim_step(sim_handle* h, int64_t n_steps);
+
+/* Mass check every `every` steps (0 = off, the default): whenever the step count reaches a
+ * multiple of `every`, sim_step enqueues the FP64 mass of every species (the same reduction
+ * as a SIM_MASS read, no host synchronisation); a non-finite total makes the handle
+ * SIM_ENONFINITE, reported by the first sim_step or sim_synchronize that finds the check
+ * completed.  SIM_EINVAL if every < 0. */
+sim_status sim_set_mass_check(sim_handle* h, int64_t every);
 
 /* Wait for the stream, then copy `what` (species `index` for FIELD, else 0) into the
  * caller's host buffer dst of dst_bytes.  Cones come back in the caller's original order.
  * *bytes_written (may be NULL) receives the size of the item; SIM_ERANGE if dst_bytes is
- * smaller (nothing is copied). */
+ * smaller (nothing is copied).  SIM_MASS is a mass check: its totals are written in any
+ * case, and it returns SIM_ENONFINITE (sticky, see above) if one is not finite, SIM_OK
+ * (clearing that state) if all are. */
 sim_status sim_read_state(sim_handle* h, sim_item what, int32_t index, void* dst,
                           size_t dst_bytes, size_t* bytes_written);
 
@@ -167,7 +189,8 @@ sim_status sim_device_ptr(sim_handle* h, sim_item what, int32_t index, void** de
  * SIM_KERNEL_TIME. */
 sim_status sim_set_timing(sim_handle* h, int32_t enable);
 
-/* Block until all work enqueued on the handle's stream has finished. */
+/* Block until all work enqueued on the handle's stream has finished.  SIM_ENONFINITE if a
+ * mass check has found a non-finite total. */
 sim_status sim_synchronize(sim_handle* h);
 
 /* Release all resources; NULL is a no-op.  Returns SIM_EDEVICE if a HIP call failed
@@ -205,6 +228,14 @@ sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_ev
  * in the caller's order, then species 1's), dL_dD[n_species] and dL_dk[n_species].  May be
  * called again for the same record.  Synchronises the stream. */
 sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, double* dL_dk);
+
+/* Device memory (bytes) that sim_adjoint_backward may spend on recorded states so that it
+ * re-runs the fields and cone steps of the whole run once (instead of re-running each
+ * checkpoint segment from its checkpoint just before reversing it).  0 (the default) means
+ * half the device memory free when the sweep starts.  When the whole run's states do not
+ * fit within the limit, each segment is re-run from its checkpoint; both ways give the
+ * same gradient.  SIM_EINVAL if max_bytes < 0. */
+sim_status sim_adjoint_set_tape_limit(sim_handle* h, int64_t max_bytes);
 
 /* ----------------------------------------------------------------------------------------
  * Connectivity (Sec. 3.4, Figs. 4-5): a cone that stopped on a target is a connection from

@@ -82,7 +82,7 @@ def load(path: str = LIBRARY):
         lib.oracle_bfs_levels.restype = C.c_int
     if hasattr(lib, "oracle_adjoint"):
         lib.oracle_adjoint.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.c_int64,
-                                       C.POINTER(C.c_int32), _dp, _dp, _dp, _dp, _dp]
+                                       C.POINTER(C.c_int32), _dp, _dp, _dp, _dp, _dp, _dp]
         lib.oracle_adjoint.restype = C.c_int
     if path == LIBRARY:
         _lib = lib
@@ -240,10 +240,12 @@ class OracleSim:
             self.fields[s][...] = out[s]
         return self
 
-    def adjoint(self, n_steps: int, assign, weight):
+    def adjoint(self, n_steps: int, assign, weight, magnitude=False):
         """Run n_steps forward (advancing this simulation) and return the trajectory loss
         sum_i weight[i] |p_i^N - target[assign[i]]|^2 with its gradient along the run's
-        branch: (loss, dL/dq [all sources, species 0 first], dL/dD [species], dL/dk)."""
+        branch: (loss, dL/dq [all sources, species 0 first], dL/dD [species], dL/dk).  With
+        magnitude=True a fifth item holds, for every component in the order
+        (dL/dq..., dL/dD..., dL/dk...), the same sum over the absolute values of its terms."""
         assign = np.ascontiguousarray(assign, dtype=np.int32)
         weight = np.ascontiguousarray(weight, dtype=np.float64)
         assert assign.shape == (self.pos.shape[0],) and weight.shape == assign.shape
@@ -252,18 +254,21 @@ class OracleSim:
         dD = np.zeros(2)
         dk = np.zeros(2)
         loss = np.zeros(1)
+        ns = self.params.n_species
+        mag = np.zeros(nq + 2 * ns)
         self.state.step = self.step_count
         rc = self.lib.oracle_adjoint(C.byref(self.params), C.byref(self.state), int(n_steps),
                                      _ptr(assign, C.c_int32), _ptr(weight, C.c_double),
                                      _ptr(loss, C.c_double), _ptr(dq, C.c_double),
-                                     _ptr(dD, C.c_double), _ptr(dk, C.c_double))
+                                     _ptr(dD, C.c_double), _ptr(dk, C.c_double),
+                                     _ptr(mag, C.c_double) if magnitude else None)
         if rc == -2:
             raise ValueError("oracle_adjoint: 2D only")
         if rc != 0:
             raise MemoryError("oracle_adjoint: allocation failed")
         self.step_count = int(self.state.step)
-        ns = self.params.n_species
-        return float(loss[0]), dq[:nq].copy(), dD[:ns].copy(), dk[:ns].copy()
+        out = (float(loss[0]), dq[:nq].copy(), dD[:ns].copy(), dk[:ns].copy())
+        return out + (mag,) if magnitude else out
 
     # -- reading ---------------------------------------------------------------------
     def mass(self, s: int = 0) -> float:

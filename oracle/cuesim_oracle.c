@@ -613,7 +613,7 @@ static void cone_reverse_2d(const oracle_params* p, const double* const fields[2
 
 int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
                    const int32_t* assign, const double* weight, double* loss,
-                   double* dL_dq, double* dL_dD, double* dL_dk)
+                   double* dL_dq, double* dL_dD, double* dL_dk, double* magnitude)
 {
     if (p->dim != 2)
         return -2;
@@ -661,12 +661,19 @@ int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
     }
     *loss = L;
     int q_off[2] = {0, p->n_sources[0]};
+    const int nq = p->n_sources[0] + (ns > 1 ? p->n_sources[1] : 0);
     for (int sp = 0; sp < ns; ++sp) {
         for (int m = 0; m < p->n_sources[sp]; ++m)
             dL_dq[q_off[sp] + m] = 0.0;
         dL_dD[sp] = 0.0;
         dL_dk[sp] = 0.0;
     }
+    /* magnitude (optional): the same sums taken over absolute values of their terms,
+       [dL/dq ..., dL/dD per species, dL/dk per species]; the scale of rounding error that a
+       sum of these terms can carry (its cancellation) */
+    if (magnitude)
+        for (int m = 0; m < nq + 2 * ns; ++m)
+            magnitude[m] = 0.0;
     const double vol = p->dx * p->dx;
     for (int64_t n = N - 1; n >= 0; --n) {
         const double* fnext[2] = {tape_c + ((size_t)(n + 1) * ns) * cells,
@@ -689,16 +696,25 @@ int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
         for (int sp = 0; sp < ns; ++sp) {
             const double* c = tape_c + ((size_t)n * ns + sp) * cells;
             double* a = afield + (size_t)sp * cells;
-            for (int m = 0; m < p->n_sources[sp]; ++m)
+            for (int m = 0; m < p->n_sources[sp]; ++m) {
                 dL_dq[q_off[sp] + m] += a[p->source_cell[sp][m]] / vol;
+                if (magnitude)
+                    magnitude[q_off[sp] + m] += fabs(a[p->source_cell[sp][m]]) / vol;
+            }
             laplacian_2d(p, c, lap);
-            double sD = 0.0, sk = 0.0;
+            double sD = 0.0, sk = 0.0, mD = 0.0, mk = 0.0;
             for (int64_t x = 0; x < cells; ++x) {
                 sD += a[x] * lap[x];
                 sk += a[x] * c[x];
+                mD += fabs(a[x] * lap[x]);
+                mk += fabs(a[x] * c[x]);
             }
             dL_dD[sp] += sD * p->dt / (p->dx * p->dx);
             dL_dk[sp] += -p->dt * sk;
+            if (magnitude) {
+                magnitude[nq + sp] += mD * p->dt / (p->dx * p->dx);
+                magnitude[nq + ns + sp] += p->dt * mk;
+            }
             const double r = p->D[sp] * p->dt / (p->dx * p->dx);
             const double kdt = p->k[sp] * p->dt;
             laplacian_2d(p, a, lap);

@@ -87,10 +87,14 @@ int oracle_run(const oracle_params* p, oracle_state* s, int64_t n_steps);
  * branch (exit/contact decisions and the active side of the turn cap held fixed) with
  * respect to every source amount (dL_dq: species 0's sources, then species 1's), and D
  * and k of every species (dL_dD, dL_dk: [n_species]).  2D only.  Returns 0, -1 on
- * allocation failure, -2 for 3D.  Records the whole forward run (n_steps + 1 fields). */
+ * allocation failure, -2 for 3D.  Records the whole forward run (n_steps + 1 fields).
+ * magnitude (may be NULL; [n_q + 2 n_species], ordered like dL_dq, dL_dD, dL_dk) receives
+ * the same sums taken over the absolute values of their terms: the size of the terms each
+ * gradient component cancels, which bounds the rounding error a lower-precision
+ * evaluation of that component can carry. */
 int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
                    const int32_t* assign, const double* weight, double* loss,
-                   double* dL_dq, double* dL_dD, double* dL_dk);
+                   double* dL_dq, double* dL_dD, double* dL_dk, double* magnitude);
 
 /* Adjacency list of the connections (a cone with status CONTACT links its owner neuron to
  * the owner of its target): row_start[n_neurons + 1] (V_a) and edges (E_a, capacity

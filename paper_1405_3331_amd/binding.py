@@ -19,19 +19,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBRARY = os.path.join(HERE, "libcuesim.so")
 
 SIM_OK, SIM_EINVAL, SIM_ECFL, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE, SIM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SIM_ENONFINITE = -7
 STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ECFL", -3: "SIM_ENOMEM",
-                -4: "SIM_EDEVICE", -5: "SIM_ERANGE", -6: "SIM_ESTATE"}
+                -4: "SIM_EDEVICE", -5: "SIM_ERANGE", -6: "SIM_ESTATE", -7: "SIM_ENONFINITE"}
 ACTIVE, CONTACT, EXITED = 0, 1, 2
 SIM_TURN_VECTOR, SIM_TURN_SNR = 0, 1
 
 FIELD, CONE_POS, CONE_DIR, CONE_STATUS, CONE_TARGET, CONE_EVENT_STEP, EVENTS, MASS, STEP, \
     COUNTS, KERNEL_TIME, TILING = range(12)
 
-EXPORTED = ["sim_create", "sim_step", "sim_read_state", "sim_write_state", "sim_device_ptr",
-            "sim_set_timing", "sim_synchronize", "sim_destroy", "sim_last_error",
+EXPORTED = ["sim_create", "sim_step", "sim_set_mass_check", "sim_read_state",
+            "sim_write_state", "sim_device_ptr", "sim_set_timing", "sim_synchronize", "sim_destroy", "sim_last_error",
             "sim_batch_create", "sim_batch_step", "sim_batch_read_state",
             "sim_batch_synchronize", "sim_batch_destroy", "sim_batch_last_error",
-            "sim_adjoint_run", "sim_adjoint_backward", "sim_connectivity", "sim_bfs_levels"]
+            "sim_adjoint_run", "sim_adjoint_backward", "sim_adjoint_set_tape_limit",
+            "sim_connectivity", "sim_bfs_levels"]
 
 
 class SimError(RuntimeError):
@@ -79,6 +81,7 @@ def load(path: str = LIBRARY):
     H = C.c_void_p
     lib.sim_create.argtypes = [C.POINTER(SimParams), C.c_void_p, C.POINTER(H)]
     lib.sim_step.argtypes = [H, C.c_int64]
+    lib.sim_set_mass_check.argtypes = [H, C.c_int64]
     lib.sim_read_state.argtypes = [H, C.c_int, C.c_int32, C.c_void_p, C.c_size_t,
                                    C.POINTER(C.c_size_t)]
     lib.sim_write_state.argtypes = [H, C.c_int, C.c_int32, C.c_void_p, C.c_size_t]
@@ -101,6 +104,7 @@ def load(path: str = LIBRARY):
     _dp = C.POINTER(C.c_double)
     lib.sim_adjoint_run.argtypes = [H, C.c_int64, C.c_int32, _ip, _fp, _dp]
     lib.sim_adjoint_backward.argtypes = [H, _dp, _dp, _dp]
+    lib.sim_adjoint_set_tape_limit.argtypes = [H, C.c_int64]
     lib.sim_connectivity.argtypes = [H, C.c_int32, _ip, _ip, _ip, _ip, C.c_int64,
                                      C.POINTER(C.c_int64)]
     lib.sim_bfs_levels.argtypes = [H, C.c_int32, _ip]
@@ -318,6 +322,11 @@ class Simulation:
     def events(self) -> np.ndarray:
         return sim_read_state(self.h, EVENTS)
 
+    def set_mass_check(self, every: int):
+        """Periodic mass check every `every` steps (0: off); see sim_set_mass_check."""
+        _check(load().sim_set_mass_check(self.h, int(every)), self.h)
+        return self
+
     def mass(self) -> np.ndarray:
         return sim_read_state(self.h, MASS)
 
@@ -348,6 +357,11 @@ class Simulation:
 
     def bfs_levels(self, root: int, n_neurons: int):
         return sim_bfs_levels(self.h, root, n_neurons)
+
+    def set_tape_limit(self, max_bytes: int):
+        """Bytes the reverse sweep may record (0: library default); see the header."""
+        _check(load().sim_adjoint_set_tape_limit(self.h, int(max_bytes)), self.h)
+        return self
 
     def adjoint_backward(self):
         n_q = sum(len(s.source_q) for s in self.sc.species)

@@ -135,10 +135,13 @@ __device__ __forceinline__ int contact_in_list(const float4* pts, int n, float r
 // those of p - R and p + R.  The bounds are widened by kCellSlack cells to absorb the FP32
 // rounding of (p +- R) / cell, so the search stays exact; usually one or two cells per axis.
 constexpr float kCellSlack = 1e-3f;
+// The bounds are clamped as floats before the conversion, so a NaN or infinite tip gives an
+// empty range (lo > hi) instead of an undefined conversion.
 __device__ __forceinline__ void target_cell_range(float p, const TargetGrid& tg, int n, int& lo,
                                                   int& hi) {
-    lo = max((int)floorf(fmaf(p - tg.r, tg.inv_cell, -kCellSlack)), 0);
-    hi = min((int)floorf(fmaf(p + tg.r, tg.inv_cell, kCellSlack)), n - 1);
+    lo = (int)fminf(fmaxf(floorf(fmaf(p - tg.r, tg.inv_cell, -kCellSlack)), 0.0f), (float)n);
+    hi = (int)fminf(fmaxf(floorf(fmaf(p + tg.r, tg.inv_cell, kCellSlack)), -1.0f),
+                    (float)(n - 1));
 }
 
 // Nearest target with squared distance strictly below r2; ties on the squared distance go

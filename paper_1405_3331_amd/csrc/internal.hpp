@@ -111,8 +111,7 @@ struct ConeOrder3D {
     float4* dir[2] = {};
     uint32_t* key[2] = {};
     int32_t* slot[2] = {};
-    void* temp = nullptr;
-    size_t temp_bytes = 0;
+    int32_t* scratch = nullptr;   // counting-sort histograms (sort_pairs)
     int cur = 0;
     int n = 0;
     int shift = 2;
@@ -185,20 +184,28 @@ struct GraphBuffers {
     int32_t* edges = nullptr;          // [M]      (E_a; the first row_start[N] are used)
     int32_t* level = nullptr;          // [N]
     int32_t* grew = nullptr;           // [1]
-    void* temp = nullptr;              // radix-sort scratch
-    size_t temp_bytes = 0;
+    int32_t* scratch = nullptr;        // counting-sort histograms (sort_pairs)
     int n_neurons = 0;
 };
-size_t graph_sort_temp_bytes(int n_cones, int n_neurons);
 hipError_t launch_adjacency(const GraphBuffers& g, const int32_t* status, const int32_t* target,
                             int n_cones, int n_neurons, hipStream_t stream);
 hipError_t launch_bfs_init(int32_t* level, int n, int root, hipStream_t stream);
 hipError_t launch_bfs_level(const int32_t* row_start, const int32_t* edges, int n, int depth,
                             int32_t* level, int32_t* grew, hipStream_t stream);
 
-// Sum of a field in FP64 (deterministic two-pass reduction) into *out (device).
+// Stable sort of n (key, value) pairs by the low key_bits bits of the keys (every key must
+// be below 2^key_bits) with the project's counting passes (kernels_sort.hip).  keys/vals
+// hold the input; keys_alt/vals_alt (same sizes) are the other half of each pass's
+// ping-pong; *in_alt tells which pair holds the result.  scratch holds
+// sort_pairs_scratch_bytes(n) bytes.
+size_t sort_pairs_scratch_bytes(int n);
+hipError_t sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
+                      int n, int key_bits, int32_t* scratch, hipStream_t stream, bool* in_alt);
+
+// Sum of a field in FP64 (deterministic two-pass reduction) into *out (device); when
+// nonfinite is given, a non-finite sum sets *nonfinite = 1 (device).
 hipError_t launch_mass(const float* field, int64_t n, double* partial, int n_partial,
-                       double* out, hipStream_t stream);
+                       double* out, hipStream_t stream, int32_t* nonfinite = nullptr);
 constexpr int kMassPartials = 1024;
 
 }  // namespace cuesim

@@ -1,20 +1,19 @@
 // kernels_cones3d.hip -- the 3D cone step over cones held in spatial order.
 //
-// A 3D cone samples 32 cells per species around its tip (Sec. 3.4 gradient, trilinear).  In
+// A 3D cone samples 32 cells per species around its tip (Sec. 3.5 gradient steering; trilinear).  In
 // the caller's order neighbouring threads sit anywhere in the volume, so a wavefront touches
 // a separate set of cache lines per cone and uses a few bytes of each.  Here the active
 // cones are kept sorted by the Morton code of their tip cell (coarsened by `shift` bits per
 // axis): a workgroup then covers one compact region, its gathers share lines in L1/L2, and
 // the cone state itself streams as two aligned float4 per cone (tip x, y, z, id; heading).
-// Cones move at most step_len per step, so the order is refreshed every few steps (radix
-// sort of the keys, then a gather of the state), not every step.
+// Cones move at most step_len per step, so the order is refreshed every few steps (the
+// project's stable counting sort of the keys, kernels_sort.hip, then a gather of the state),
+// not every step.
 //
 // Stopped cones leave the order: the step writes their final tip, heading, status, target
 // and event step straight into the caller-order arrays and marks the ordered copy id = -1;
 // a refresh moves them behind the active ones.  The caller-order tips and headings of the
 // active cones are brought up to date only when the state is read (order3d_end).
-#include <hipcub/hipcub.hpp>
-
 #include "internal.hpp"
 
 namespace cuesim {
@@ -38,9 +37,9 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every 
     return v;
 }
 
+// Cell of a coordinate, clamped to the grid (as a float first: a NaN tip maps to cell 0).
 __device__ __forceinline__ uint32_t cell_coord(float p, float inv_dx, int n) {
-    const int c = (int)floorf(p * inv_dx);
-    return (uint32_t)min(max(c, 0), n - 1);
+    return (uint32_t)fminf(fmaxf(floorf(p * inv_dx), 0.0f), (float)(n - 1));
 }
 
 __device__ __forceinline__ uint32_t order_key(const ConeRules& r, float x, float y, float z,
@@ -242,17 +241,17 @@ int axis_bits(int n, int shift) {
     return bits;
 }
 
-// Radix sort of (key, slot) from buffer 0 into buffer 1, then the state gather into the
-// other half of the ping-pong.
+// Stable counting sort of (key, slot) (buffers 0 and 1 ping-pong), then the state gather
+// into the other half of the state's ping-pong.
 hipError_t sort_and_gather(ConeOrder3D& o, hipStream_t stream) {
-    size_t bytes = o.temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(o.temp, bytes, o.key[0], o.key[1],
-                                                      o.slot[0], o.slot[1], o.n, 0,
-                                                      o.end_bit, stream);
+    bool in_alt = false;
+    hipError_t e = sort_pairs(o.key[0], o.slot[0], o.key[1], o.slot[1], o.n, o.end_bit,
+                              o.scratch, stream, &in_alt);
     if (e != hipSuccess) return e;
     const int nxt = o.cur ^ 1;
-    hipLaunchKernelGGL(k_gather3d, dim3(blocks_for(o.n)), dim3(kThreads), 0, stream, o.slot[1],
-                       o.n, o.tip[o.cur], o.dir[o.cur], o.tip[nxt], o.dir[nxt]);
+    hipLaunchKernelGGL(k_gather3d, dim3(blocks_for(o.n)), dim3(kThreads), 0, stream,
+                       o.slot[in_alt ? 1 : 0], o.n, o.tip[o.cur], o.dir[o.cur], o.tip[nxt],
+                       o.dir[nxt]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     o.cur = nxt;
     return hipSuccess;
@@ -276,12 +275,7 @@ hipError_t order3d_allocate(ConeOrder3D& o, int n, int nx, int ny, int nz) {
             (e = hipMalloc((void**)&o.slot[b], (size_t)n * sizeof(int32_t))) != hipSuccess)
             return e;
     }
-    size_t bytes = 0;
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, o.key[0], o.key[1], o.slot[0],
-                                           o.slot[1], n, 0, o.end_bit);
-    if (e != hipSuccess) return e;
-    o.temp_bytes = std::max<size_t>(bytes, 1);
-    return hipMalloc(&o.temp, o.temp_bytes);
+    return hipMalloc((void**)&o.scratch, sort_pairs_scratch_bytes(n));
 }
 
 void order3d_release(ConeOrder3D& o) {
@@ -291,7 +285,7 @@ void order3d_release(ConeOrder3D& o) {
         if (o.key[b]) (void)hipFree(o.key[b]);
         if (o.slot[b]) (void)hipFree(o.slot[b]);
     }
-    if (o.temp) (void)hipFree(o.temp);
+    if (o.scratch) (void)hipFree(o.scratch);
     o = ConeOrder3D{};
 }
 

@@ -5,15 +5,14 @@
 // neuron owning the target.  The adjacency list is the paper's pair of arrays: V_a (for
 // every neuron the start of its list) and E_a (the lists, neuron after neuron).  Within a
 // neuron's list the edges are in increasing cone index, so the list is unique.  It is
-// built with a stable radix sort of (owner, cone) pairs (non-edges carry the key n_neurons
-// and sort last), a count per neuron and an exclusive scan.
+// built with the project's stable counting sort of (owner, cone) pairs (kernels_sort.hip;
+// non-edges carry the key n_neurons and sort last), a count per neuron and an exclusive
+// scan.
 //
 // The traversal expands one level per launch with one thread per vertex, as in the paper's
 // kernel: a vertex at level d labels its unlabelled neighbours d + 1.  Reading the level
 // itself as the frontier flag keeps the expansion level-synchronous (a vertex labelled
 // d + 1 during the launch is not expanded in it).
-#include <hipcub/hipcub.hpp>
-
 #include "internal.hpp"
 
 namespace cuesim {
@@ -102,34 +101,27 @@ int key_bits(int n_neurons) {
 
 }  // namespace
 
-size_t graph_sort_temp_bytes(int n_cones, int n_neurons) {
-    size_t bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const int32_t*)nullptr,
-                                             (int32_t*)nullptr, (const int32_t*)nullptr,
-                                             (int32_t*)nullptr, n_cones, 0, key_bits(n_neurons));
-    return bytes;
-}
-
 hipError_t launch_adjacency(const GraphBuffers& g, const int32_t* status, const int32_t* target,
                             int n_cones, int n_neurons, hipStream_t stream) {
     hipError_t e = hipMemsetAsync(g.degree, 0, (size_t)n_neurons * sizeof(int32_t), stream);
     if (e != hipSuccess) return e;
+    const int32_t* sorted_cone = g.cone;
     if (n_cones > 0) {
         hipLaunchKernelGGL(k_edge_keys, dim3(graph_blocks(n_cones)), dim3(kGraphThreads), 0,
                            stream, status, g.owner, n_cones, n_neurons, g.key, g.cone, g.degree);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        size_t bytes = g.temp_bytes;
-        e = hipcub::DeviceRadixSort::SortPairs(g.temp, bytes, g.key, g.key_sorted, g.cone,
-                                               g.cone_sorted, n_cones, 0, key_bits(n_neurons),
-                                               stream);
+        bool in_alt = false;
+        e = sort_pairs((uint32_t*)g.key, g.cone, (uint32_t*)g.key_sorted, g.cone_sorted,
+                       n_cones, key_bits(n_neurons), g.scratch, stream, &in_alt);
         if (e != hipSuccess) return e;
+        if (in_alt) sorted_cone = g.cone_sorted;
     }
     hipLaunchKernelGGL(k_row_start, dim3(1), dim3(kScanThreads), 0, stream, g.degree, n_neurons,
                        g.row_start);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n_cones > 0) {
         hipLaunchKernelGGL(k_fill_edges, dim3(graph_blocks(n_cones)), dim3(kGraphThreads), 0,
-                           stream, g.cone_sorted, target, g.target_owner, g.row_start,
+                           stream, sorted_cone, target, g.target_owner, g.row_start,
                            n_neurons, g.edges);
         e = hipGetLastError();
     }

@@ -74,12 +74,17 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_partial(const float* __re
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
+// The total goes to *out; a non-finite total also raises *nonfinite (when given).
 __global__ __launch_bounds__(kMassThreads) void k_mass_final(const double* __restrict__ partial,
-                                                              int n, double* __restrict__ out) {
+                                                              int n, double* __restrict__ out,
+                                                              int32_t* __restrict__ nonfinite) {
     double acc = 0.0;
     for (int x = threadIdx.x; x < n; x += kMassThreads) acc += partial[x];
     const double t = block_sum(acc);
-    if (threadIdx.x == 0) *out = t;
+    if (threadIdx.x == 0) {
+        *out = t;
+        if (nonfinite && !isfinite(t)) *nonfinite = 1;
+    }
 }
 
 }  // namespace
@@ -93,14 +98,14 @@ hipError_t launch_cones2d(const ConeRules& rules, const float* f0, const float* 
 }
 
 hipError_t launch_mass(const float* field, int64_t n, double* partial, int n_partial,
-                       double* out, hipStream_t stream) {
+                       double* out, hipStream_t stream, int32_t* nonfinite) {
     int blocks = (int)((n + kMassThreads - 1) / kMassThreads);
     if (blocks > n_partial) blocks = n_partial;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_mass_partial, dim3(blocks), dim3(kMassThreads), 0, stream, field, n,
                        partial);
     hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(kMassThreads), 0, stream, partial, blocks,
-                       out);
+                       out, nonfinite);
     return hipGetLastError();
 }
 

@@ -367,8 +367,9 @@ __device__ __forceinline__ void tile_cone_advance(float4& st, float2& sc, uint2&
     st = make_float4(x, y, th, __int_as_float(id));
 }
 
+// Cell of a coordinate, clamped to the grid (as a float first: a NaN tip maps to cell 0).
 __device__ __forceinline__ int cell_of(float p, float inv_dx, int n) {
-    return min(max((int)floorf(p * inv_dx), 0), n - 1);
+    return (int)fminf(fmaxf(floorf(p * inv_dx), 0.0f), (float)(n - 1));
 }
 
 // Destination tile of a cone's tip after a launch, restricted to the 3x3 neighbourhood of

@@ -68,6 +68,17 @@ struct sim_handle {
     int32_t* target_cells = nullptr;
     double* mass_partial = nullptr;
     double* mass_out = nullptr;
+    // periodic mass check: every mass_every steps (0: off) sim_step enqueues the FP64 mass of
+    // every species; a non-finite total raises the device flag mass_flag, copied to the
+    // pinned host word mass_flag_host behind the event mass_event.  `nonfinite` is sticky:
+    // set by a check that saw a non-finite total, cleared by a SIM_MASS read whose totals
+    // are all finite.
+    int64_t mass_every = 0;
+    int32_t* mass_flag = nullptr;
+    int32_t* mass_flag_host = nullptr;
+    hipEvent_t mass_event = nullptr;
+    bool mass_pending = false;
+    bool nonfinite = false;
 
     // temporal blocking
     int block_steps = 1;
@@ -92,6 +103,7 @@ struct sim_handle {
     std::vector<int32_t> src_merged_cell[SIM_MAX_SPECIES];   // merged, sorted by cell
     std::vector<float> src_merged_q[SIM_MAX_SPECIES];        // their amounts / dx^dim
     AdjointRun* adj = nullptr;
+    int64_t adj_tape_limit = 0;   // bytes the reverse sweep may record (0: half the free memory)
     GraphBuffers graph = {};                                 // last sim_connectivity
     int graph_cones = 0;
 
@@ -183,7 +195,7 @@ void graph_release(sim_handle* h) {
     dfree(g.edges);
     dfree(g.level);
     dfree(g.grew);
-    if (g.temp) (void)hipFree(g.temp);
+    if (g.scratch) (void)hipFree(g.scratch);
     g = GraphBuffers{};
 }
 
@@ -202,6 +214,11 @@ void release(sim_handle* h) {
     dfree(h->target_cells);
     dfree(h->mass_partial);
     dfree(h->mass_out);
+    dfree(h->mass_flag);
+    if (h->mass_flag_host) (void)hipHostFree(h->mass_flag_host);
+    h->mass_flag_host = nullptr;
+    if (h->mass_event) (void)hipEventDestroy(h->mass_event);
+    h->mass_event = nullptr;
     tiled_release(h->tiled);
     order3d_release(h->order3d);
     field3d_release(h->field3d);
@@ -209,6 +226,19 @@ void release(sim_handle* h) {
     drop_events(h);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     h->stream = nullptr;
+}
+
+// Fold a finished periodic mass check into the sticky flag (never waits).
+void poll_mass_check(sim_handle* h) {
+    if (!h->mass_pending || hipEventQuery(h->mass_event) != hipSuccess) return;
+    h->mass_pending = false;
+    if (*(volatile int32_t*)h->mass_flag_host) h->nonfinite = true;
+}
+
+sim_status nonfinite_fail(sim_handle* h) {
+    return fail(h, SIM_ENONFINITE,
+                "a mass check found a non-finite total: replace the state (sim_write_state) "
+                "and read SIM_MASS to clear");
 }
 
 int dir_width(int dim) { return dim == 2 ? 1 : 3; }
@@ -599,8 +629,13 @@ sim_status create_impl(const sim_params* p, void* hip_stream, int force_cpl, sim
     if (st != SIM_OK) return bail(st);
     h->target_host.assign(p->target_pos, p->target_pos + (size_t)p->n_targets * p->dim);
     if ((e = dalloc(&h->mass_partial, kMassPartials)) != hipSuccess ||
-        (e = dalloc(&h->mass_out, SIM_MAX_SPECIES)) != hipSuccess)
+        (e = dalloc(&h->mass_out, SIM_MAX_SPECIES)) != hipSuccess ||
+        (e = dalloc(&h->mass_flag, 1)) != hipSuccess ||
+        (e = hipMemset(h->mass_flag, 0, sizeof(int32_t))) != hipSuccess ||
+        (e = hipHostMalloc((void**)&h->mass_flag_host, sizeof(int32_t))) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->mass_event, hipEventDisableTiming)) != hipSuccess)
         return bail(device_fail(h, e, "mass buffers"));
+    *h->mass_flag_host = 0;
 
     // temporal blocking plan
     h->block_steps = p->block_steps == 0 ? kDefaultBlockSteps : p->block_steps;
@@ -722,12 +757,40 @@ sim_status sim_step(sim_handle* h, int64_t n_steps) {
     if (n_steps < 0) return fail(h, SIM_EINVAL, "n_steps < 0");
     if (h->step + n_steps > 2147483647LL)
         return fail(h, SIM_EINVAL, "step count would exceed 2^31-1");
+    poll_mass_check(h);
+    if (h->nonfinite) return nonfinite_fail(h);
     if (n_steps == 0) return SIM_OK;
-    if (h->block_steps > 1) return tiled_steps(h, n_steps);
-    for (int64_t i = 0; i < n_steps; ++i) {
-        sim_status st = plain_step(h);
+    while (n_steps > 0) {
+        // with the periodic mass check on, stop at the next multiple of mass_every
+        int64_t n = n_steps;
+        if (h->mass_every > 0) n = std::min(n, h->mass_every - h->step % h->mass_every);
+        sim_status st = SIM_OK;
+        if (h->block_steps > 1) {
+            st = tiled_steps(h, n);
+        } else {
+            for (int64_t i = 0; i < n && st == SIM_OK; ++i) st = plain_step(h);
+        }
         if (st != SIM_OK) return st;
+        n_steps -= n;
+        if (h->mass_every > 0 && h->step % h->mass_every == 0) {
+            for (int s = 0; s < h->n_species; ++s)
+                HIP_TRY(h, launch_mass(h->field[s][h->cur[s]], h->n_cells, h->mass_partial,
+                                       kMassPartials, h->mass_out + s, h->stream,
+                                       h->mass_flag));
+            HIP_TRY(h, hipMemcpyAsync(h->mass_flag_host, h->mass_flag, sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(h, hipEventRecord(h->mass_event, h->stream));
+            h->mass_pending = true;
+        }
     }
+    return SIM_OK;
+}
+
+sim_status sim_set_mass_check(sim_handle* h, int64_t every) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    if (every < 0) return fail(h, SIM_EINVAL, "every < 0");
+    h->mass_every = every;
     return SIM_OK;
 }
 
@@ -811,8 +874,19 @@ sim_status sim_read_state(sim_handle* h, sim_item what, int32_t index, void* dst
             HIP_TRY(h, hipMemcpy(m, h->mass_out, h->n_species * sizeof(double),
                                  hipMemcpyDeviceToHost));
             const double vol = std::pow(h->dx, h->dim);
-            for (int s = 0; s < h->n_species; ++s) m[s] *= vol;
+            bool finite = true;
+            for (int s = 0; s < h->n_species; ++s) {
+                m[s] *= vol;
+                finite = finite && std::isfinite(m[s]);
+            }
             std::memcpy(dst, m, need);
+            // this check supersedes any earlier one: the flag follows what it found
+            HIP_TRY(h, hipMemsetAsync(h->mass_flag, 0, sizeof(int32_t), h->stream));
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            *h->mass_flag_host = 0;
+            h->mass_pending = false;
+            h->nonfinite = !finite;
+            if (!finite) return nonfinite_fail(h);
             return SIM_OK;
         }
         case SIM_STEP:
@@ -913,6 +987,8 @@ sim_status sim_synchronize(sim_handle* h) {
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    poll_mass_check(h);
+    if (h->nonfinite) return nonfinite_fail(h);
     return SIM_OK;
 }
 
@@ -1071,7 +1147,8 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     if (hipMemGetInfo(&free_bytes, &total_bytes) != hipSuccess) free_bytes = 0;
     const size_t whole_bytes = ((size_t)(n_run + 1) * ns * cells + (size_t)K * ns * cells) * 4 +
                                (size_t)n_run * std::max<size_t>(Ms, 1) * 16;
-    const bool whole = n_seg > 1 && whole_bytes < free_bytes / 2;
+    const size_t tape_limit = h->adj_tape_limit > 0 ? (size_t)h->adj_tape_limit : free_bytes / 2;
+    const bool whole = n_seg > 1 && whole_bytes < tape_limit;
     const int64_t window = whole ? n_run : K;
     float* tape = nullptr;
     float4* tape_cones = nullptr;
@@ -1233,6 +1310,13 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     return SIM_OK;
 }
 
+sim_status sim_adjoint_set_tape_limit(sim_handle* h, int64_t max_bytes) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (max_bytes < 0) return fail(h, SIM_EINVAL, "max_bytes < 0");
+    h->adj_tape_limit = max_bytes;
+    return SIM_OK;
+}
+
 // ------------------------------------------------------------------------------------
 // Connectivity: adjacency list of the contacts and breadth-first levels
 // ------------------------------------------------------------------------------------
@@ -1256,7 +1340,6 @@ sim_status sim_connectivity(sim_handle* h, int32_t n_neurons, const int32_t* con
     GraphBuffers& g = h->graph;
     const size_t Ms = (size_t)std::max(M, 1), N = (size_t)n_neurons;
     g.n_neurons = n_neurons;
-    g.temp_bytes = graph_sort_temp_bytes(M, n_neurons);
     hipError_t e;
     if ((e = dalloc(&g.owner, Ms)) != hipSuccess ||
         (e = dalloc(&g.target_owner, (size_t)std::max(T, 1))) != hipSuccess ||
@@ -1266,7 +1349,7 @@ sim_status sim_connectivity(sim_handle* h, int32_t n_neurons, const int32_t* con
         (e = dalloc(&g.degree, N)) != hipSuccess || (e = dalloc(&g.row_start, N + 1)) != hipSuccess ||
         (e = dalloc(&g.edges, Ms)) != hipSuccess || (e = dalloc(&g.level, N)) != hipSuccess ||
         (e = dalloc(&g.grew, 1)) != hipSuccess ||
-        (g.temp_bytes > 0 && (e = hipMalloc(&g.temp, g.temp_bytes)) != hipSuccess)) {
+        (e = hipMalloc((void**)&g.scratch, sort_pairs_scratch_bytes(M))) != hipSuccess) {
         graph_release(h);
         if (e == hipErrorOutOfMemory) return fail(h, SIM_ENOMEM, "connectivity buffers");
         return device_fail(h, e, "connectivity allocation");

@@ -10,12 +10,22 @@ or to a contact sphere within tau = 1e-4 L, two in-range targets within tau, or 
 exactly anti-parallel pull); flagged cones are excluded from the exact event comparison.
 
 Full runs (no restarts) additionally meet cones whose tip error grows by the dynamics, not
-by the implementation: a cone steered around a source can amplify FP32 rounding
-differences by orders of magnitude within a hundred steps.  `FullRun` classifies a cone
-over the tip bound as amplified only if the same cone, restarted on the GPU from the
-oracle's state WINDOW steps earlier, stays within the bound over that window (the windowed
-check that is the hard gate); otherwise the comparison fails.  Amplified cones are then
-left out of the tip and event comparisons, like flagged ones.
+by the implementation: a cone steered around a source, or heading straight down the
+gradient (where the capped turn's side flips with the sign of a tiny cross product), can
+amplify FP32 rounding differences by orders of magnitude within tens of steps.  `FullRun`
+classifies a cone over the tip bound as
+  amplified        if the same cone, restarted on the GPU from the oracle's state at the
+                   last multiple of WINDOW = 100 steps, stays within the bound until now
+                   (the windowed check), or else as
+  ill-conditioned  if the FP64 oracle itself, restarted from that state with the cone's
+                   tip moved by one FP32 rounding step (relative 2^-23, either way), ends
+                   further than the bound from its own unperturbed run: the trajectory
+                   cannot be resolved to the tolerance from FP32 data at all;
+otherwise the comparison fails.  Both kinds are left out of the tip and event comparisons.
+
+Events are compared over ALL cones: a cone whose stop event (status, target, step) or tip
+differs must be one the oracle flagged, amplified or ill-conditioned, and the flagged cones
+that differ are bounded (`check_exclusions`).  `FullRun.summary()` counts every exclusion.
 """
 from __future__ import annotations
 
@@ -56,12 +66,16 @@ def compare(sim, ref, sc):
         same = ((c["status"] == ref.status) & (c["target"] == ref.target) &
                 (c["event_step"] == ref.event_step))
         out["event_mismatch"] = np.nonzero(ok & ~same)[0]
+        out["all_event_mismatch"] = np.nonzero(~same)[0]
         out["n_flagged"] = int((~ok).sum())
+        out["n_events_checked"] = int((ok & (ref.status != 0)).sum())
     else:
         out["tip_max"] = 0.0
         out["heading_max"] = 0.0
         out["event_mismatch"] = np.zeros(0, dtype=np.int64)
+        out["all_event_mismatch"] = np.zeros(0, dtype=np.int64)
         out["n_flagged"] = 0
+        out["n_events_checked"] = 0
     return out
 
 
@@ -83,7 +97,9 @@ def assert_parity(m, field_tol=FIELD_TOL, tip_tol=TIP_TOL, where=""):
     assert len(m["event_mismatch"]) == 0, (where, m["event_mismatch"][:10])
 
 
-WINDOW = 20
+# restart interval of the windowed tip check: the GPU restarted from the oracle's state
+# every 100 steps stays within the tip bound (the hard gate)
+WINDOW = 100
 
 
 def _snapshot(ref):
@@ -102,7 +118,11 @@ class FullRun:
         self.ref = oracle.OracleSim(sc)
         self.sim = B.Simulation(sc, block_steps=block_steps)
         self.amplified = np.zeros(sc.n_cones, dtype=bool)
+        self.ill_conditioned = np.zeros(sc.n_cones, dtype=bool)
+        self.flagged_differ = np.zeros(sc.n_cones, dtype=bool)
         self.worst = {"field": 0.0, "tip": 0.0}
+        self.last = None
+        self.snap = None
 
     def _windowed_error(self, snap, cones, steps):
         """Tip error of `cones` after `steps` steps from the oracle state `snap`."""
@@ -116,30 +136,108 @@ class FullRun:
         sim.close()
         return np.abs(pos[cones] - ref.pos[cones]).max(axis=1) / self.sc.side
 
+    def _oracle_sensitivity(self, snap, cones, steps):
+        """Largest tip change of `cones` after `steps` oracle steps from `snap` when their tips
+        start one FP32 rounding step (relative 2^-23) away, either way (oracle only)."""
+        base = oracle.OracleSim(self.sc)
+        base.set_state(**snap)
+        base.step(steps)
+        worst = np.zeros(len(cones))
+        for sign in (1.0, -1.0):
+            st = dict(snap)
+            st["pos"] = snap["pos"].copy()
+            st["pos"][cones] *= 1.0 + sign * 2.0 ** -23
+            ref = oracle.OracleSim(self.sc)
+            ref.set_state(**st)
+            ref.step(steps)
+            d = np.abs(ref.pos[cones] - base.pos[cones]).max(axis=1) / self.sc.side
+            worst = np.maximum(worst, d)
+        return worst
+
     def advance(self, steps, where=""):
-        snap, last = None, 0
-        while steps > 0:   # in windows of at most WINDOW steps, remembering the last start
-            last = min(WINDOW, steps)
-            snap = _snapshot(self.ref)
-            self.ref.step(last)
-            self.sim.step(last)
-            steps -= last
+        # step in pieces that end on multiples of WINDOW, keeping the oracle's state at the
+        # last such restart point before the current step
+        while steps > 0:
+            cur = self.ref.step_count
+            if cur % WINDOW == 0 or self.snap is None:
+                self.snap = _snapshot(self.ref)
+            n = min(steps, WINDOW - cur % WINDOW)
+            self.ref.step(n)
+            self.sim.step(n)
+            steps -= n
+        snap, last = self.snap, self.ref.step_count - self.snap["step"]
         m = compare(self.sim, self.ref, self.sc)
         assert max(m["field"]) <= FIELD_TOL, (where, m["field"])
-        ok = (self.ref.flag_step < 0) & ~self.amplified
-        over = np.nonzero(ok & (m["tip_all"] > TIP_TOL))[0] if self.sc.n_cones else []
+        if not self.sc.n_cones:
+            self.worst["field"] = max(self.worst["field"], max(m["field"]))
+            self.last = m
+            return m
+        flagged = self.ref.flag_step >= 0
+        same_event = np.ones(self.sc.n_cones, dtype=bool)
+        same_event[m["all_event_mismatch"]] = False
+        # unflagged cones over the tip bound: amplified or ill-conditioned, else a failure
+        over = np.nonzero(~flagged & ~self.amplified & (m["tip_all"] > TIP_TOL))[0]
         if len(over):
             werr = self._windowed_error(snap, over, last)
-            assert np.all(werr <= TIP_TOL), (where, "windowed", over[werr > TIP_TOL], werr.max())
+            bad = over[werr > TIP_TOL]
+            if len(bad):
+                sens = self._oracle_sensitivity(snap, bad, last)
+                assert np.all(sens > TIP_TOL), (where, "windowed", bad[sens <= TIP_TOL],
+                                                werr.max(), sens.min())
+                self.ill_conditioned[bad] = True
             self.amplified[over] = True
-            ok[over] = False
-        if self.sc.n_cones:
-            assert (m["tip_all"][ok].max() if ok.any() else 0.0) <= TIP_TOL, where
-            mismatch = np.setdiff1d(m["event_mismatch"], np.nonzero(self.amplified)[0])
-            assert len(mismatch) == 0, (where, mismatch[:10])
+        kept = ~flagged & ~self.amplified
+        assert (m["tip_all"][kept].max() if kept.any() else 0.0) <= TIP_TOL, where
+        mismatch = np.nonzero(kept & ~same_event)[0]
+        assert len(mismatch) == 0, (where, mismatch[:10])
+        # flagged cones are compared too; those that differ (event or tip) are counted
+        differ = flagged & ~self.amplified & (~same_event | (m["tip_all"] > TIP_TOL))
+        self.flagged_differ |= differ
         self.worst["field"] = max(self.worst["field"], max(m["field"]))
-        self.worst["tip"] = max(self.worst["tip"], float(m["tip_all"][ok].max()) if ok.any() else 0.0)
+        self.worst["tip"] = max(self.worst["tip"], float(m["tip_all"][kept].max()) if kept.any() else 0.0)
+        self.last = m
         return m
+
+    def summary(self):
+        """Counts of what the comparison left out and of what it checked exactly."""
+        M = self.sc.n_cones
+        flagged = self.ref.flag_step >= 0
+        stopped = self.ref.status != 0
+        kept = ~flagged & ~self.amplified
+        m = self.last
+        mism = m["all_event_mismatch"] if m is not None and M else np.zeros(0, dtype=np.int64)
+        return {
+            "cones": M,
+            "flagged": int(flagged.sum()),
+            "flagged_differ": int(self.flagged_differ.sum()),
+            "amplified": int((self.amplified & ~flagged & ~self.ill_conditioned).sum()),
+            "ill_conditioned": int((self.ill_conditioned & ~flagged).sum()),
+            "stopped": int(stopped.sum()),
+            "events_checked": int((kept & stopped).sum()),
+            "all_mismatch": [int(i) for i in mism],
+            "tip_all_max": float(m["tip_all"].max()) if m is not None and M else 0.0,
+        }
 
     def close(self):
         self.sim.close()
+
+
+def describe(summary):
+    s = summary
+    return (f"cones {s['cones']}: flagged {s['flagged']} (differing {s['flagged_differ']}), "
+            f"amplified {s['amplified']}, ill-conditioned {s['ill_conditioned']}; stop events "
+            f"{s['stopped']}, all-cone event mismatches {len(s['all_mismatch'])} "
+            f"{s['all_mismatch'][:20]}; largest tip error over all cones {s['tip_all_max']:.2e} L")
+
+
+def check_exclusions(summary, max_differ=None, max_amplified=None, where=""):
+    """Bound the flagged cones whose event or tip differs (default: 0.01% of the cones, at
+    least 1) and the amplified + ill-conditioned cones (default: 2% of the cones, at least
+    1)."""
+    s = summary
+    if max_differ is None:
+        max_differ = max(1, s["cones"] // 10000)
+    if max_amplified is None:
+        max_amplified = max(1, s["cones"] // 50)
+    assert s["flagged_differ"] <= max_differ, (where, describe(s))
+    assert s["amplified"] + s["ill_conditioned"] <= max_amplified, (where, describe(s))

@@ -686,6 +686,27 @@ def pin_adjoint_fd(lib_path=LIB, n_species=1, steps=60):
         assert abs(got - fd) <= 2e-5 * scale, (kind, s, m, got, fd)
 
 
+def pin_adjoint_magnitude(lib_path=LIB):
+    """The summand magnitudes the oracle reports with its gradient (the scale of the terms
+    each component cancels, used as the GPU comparison's tolerance scale): at least the
+    component's absolute value (triangle inequality), exactly homogeneous in the loss
+    weights, and zero where the gradient has no terms at all (gain 0)."""
+    sc = _adjoint_case(2)
+    M = sc.n_cones
+    assign = np.arange(M) % sc.target_pos.shape[0]
+    w = np.linspace(0.5, 1.5, M)
+    _, dq, dD, dk, mag = OracleSim(sc, lib_path=lib_path).adjoint(50, assign, w, magnitude=True)
+    g = np.concatenate([dq, dD, dk])
+    assert mag.shape == g.shape and np.all(mag >= np.abs(g) * (1 - 1e-12))
+    assert np.all(mag > 0)
+    _, _, _, _, mag2 = OracleSim(sc, lib_path=lib_path).adjoint(50, assign, 2.0 * w,
+                                                                magnitude=True)
+    assert np.allclose(mag2, 2.0 * mag, rtol=1e-12, atol=0.0)
+    sc.turn_gain = 0.0
+    _, _, _, _, mag0 = OracleSim(sc, lib_path=lib_path).adjoint(30, assign, w, magnitude=True)
+    assert not mag0.any()
+
+
 def pin_adjoint_no_coupling(lib_path=LIB):
     """With gain 0 the tips do not feel the field: every gradient is exactly zero, while
     the loss itself is the direct-guidance one."""

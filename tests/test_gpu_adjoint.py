@@ -10,9 +10,41 @@ from paper_1405_3331_amd import binding as B, scenarios
 
 pytestmark = pytest.mark.gpu
 
-# FP32 forward + reverse against FP64: the tips agree to ~1e-6 of the domain over these
-# runs, and the gradient's relative error stays within 1e-3 of its largest component.
-GRAD_TOL = 1e-3
+# Gradient tolerance, per component (FP32 forward + reverse against the FP64 oracle):
+#   |got_i - want_i| <= GRAD_TOL * magnitude_i
+# where magnitude_i is the oracle's sum of the absolute values of the terms component i adds
+# up (its sum over steps and cells of |a c|, |a Lap c|, or |a| at the source cell).  A sum
+# of terms each correct to a relative error e is correct to e * magnitude: the bound holds
+# every component to 1e-4 of its own terms, however much they cancel (dL/dk of a single
+# species can be a thousand times smaller than its terms).  The terms' relative error comes
+# from the FP32 adjoint field, whose cone samples move with the tips (FP32 tips agree with
+# the oracle's to ~1e-6 of the domain, i.e. the interpolation fractions to ~1e-4).
+GRAD_TOL = 1e-4
+
+
+def _groups(n_q, ns):
+    g = [("dL/dq", slice(0, n_q))]
+    for s in range(ns):
+        g.append((f"dL/dD[{s}]", slice(n_q + s, n_q + s + 1)))
+        g.append((f"dL/dk[{s}]", slice(n_q + ns + s, n_q + ns + s + 1)))
+    return g
+
+
+def check_gradient(got, want, magnitude, n_q, ns, where=""):
+    """Per-component check; prints each group's worst component and returns the worst
+    error per group as a fraction of the component's magnitude."""
+    worst = {}
+    for name, sl in _groups(n_q, ns):
+        g, w, mag = got[sl], want[sl], magnitude[sl]
+        err = np.abs(g - w)
+        frac = err / np.maximum(mag, 1e-300)
+        i = int(np.argmax(frac))
+        worst[name] = float(frac[i])
+        print(f"[adjoint] {where} {name}: worst component {i}: got {g[i]:.6e} want {w[i]:.6e} "
+              f"(terms {mag[i]:.3e}): error {frac[i]:.2e} of the terms, "
+              f"{err[i] / max(abs(w[i]), 1e-300):.2e} of the value", flush=True)
+        assert np.all(err <= GRAD_TOL * mag), (where, name, i, g[i], w[i], mag[i])
+    return worst
 
 
 @pytest.fixture(autouse=True)
@@ -26,28 +58,52 @@ def _case(n_species=1, n=(96, 80), cones=48, seed=4):
                                    cones, 12, 1.0, 0.5, 10.0, math.pi / 30.0, 0.1, seed=seed)
 
 
-def _compare(sc, steps, every, block_steps=0):
+def _run_gpu(sc, steps, every, assign, w, block_steps, tape_limit):
+    sim = B.Simulation(sc, block_steps=block_steps)
+    if tape_limit:
+        sim.set_tape_limit(tape_limit)
+    L = sim.adjoint(steps, assign, w, every)
+    c = sim.cones()
+    dq, dD, dk = sim.adjoint_backward()
+    sim.close()
+    return L, c, np.concatenate([dq, dD, dk])
+
+
+def _compare(sc, steps, every, block_steps=0, tape_limit=0):
+    """GPU gradient against the oracle's on the same branch of the run.  A cone whose stop
+    event differs between the two runs (allowed only for a near-tie the oracle flagged, at
+    most 0.01% of the cones) is on another branch: both sides are re-run with that cone's
+    weight set to 0, which removes it from the loss and the gradient (cones do not
+    interact), so every remaining cone is compared on the same branch."""
     M = sc.n_cones
     assign = np.arange(M) % sc.target_pos.shape[0]
     w = np.linspace(0.5, 1.5, M)
-    ref = oracle.OracleSim(sc)
-    L_ref, dq_ref, dD_ref, dk_ref = ref.adjoint(steps, assign, w)
-    sim = B.Simulation(sc, block_steps=block_steps)
-    L = sim.adjoint(steps, assign, w, every)
-    c = sim.cones()
-    # the comparison is meaningful only on the same branch: identical stop events
-    np.testing.assert_array_equal(c["status"], ref.status)
-    np.testing.assert_array_equal(c["event_step"], ref.event_step)
-    dq, dD, dk = sim.adjoint_backward()
-    sim.close()
-    got = np.concatenate([dq, dD, dk])
+    for attempt in range(2):
+        ref = oracle.OracleSim(sc)
+        L_ref, dq_ref, dD_ref, dk_ref, mag = ref.adjoint(steps, assign, w, magnitude=True)
+        L, c, got = _run_gpu(sc, steps, every, assign, w, block_steps, tape_limit)
+        differ = np.nonzero((c["status"] != ref.status) | (c["event_step"] != ref.event_step) |
+                            (c["target"] != ref.target))[0]
+        if len(differ) == 0:
+            break
+        assert attempt == 0 and np.all(ref.flag_step[differ] >= 0), (differ, ref.flag_step[differ])
+        assert len(differ) <= max(1, M // 10000), differ
+        print(f"[adjoint] cones {differ.tolist()} stop differently (flagged near-ties): "
+              f"weight 0", flush=True)
+        w = w.copy()
+        w[differ] = 0.0
     want = np.concatenate([dq_ref, dD_ref, dk_ref])
-    err = np.abs(got - want).max() / np.abs(want).max()
-    print(f"[adjoint] steps={steps} every={every} loss rel {abs(L - L_ref) / L_ref:.2e} "
-          f"grad rel {err:.2e}", flush=True)
+    where = f"steps={steps} every={every} tape_limit={tape_limit}"
+    print(f"[adjoint] {where} loss rel {abs(L - L_ref) / L_ref:.2e}", flush=True)
     assert abs(L - L_ref) <= 1e-5 * L_ref
-    assert err <= GRAD_TOL, (got, want)
-    return got
+    check_gradient(got, want, mag, len(dq_ref), len(sc.species), where)
+    return got, mag
+
+
+def _same_gradient(a, b, tol):
+    """Two GPU gradients of the same run, per component against the size of its terms."""
+    (ga, mag), (gb, _) = a, b
+    assert np.all(np.abs(ga - gb) <= tol * mag), np.max(np.abs(ga - gb) / mag)
 
 
 @pytest.mark.parametrize("n_species", [1, 2])
@@ -93,15 +149,27 @@ def test_checkpoint_spacing_does_not_change_the_gradient():
     a = _compare(sc, 90, 90)   # whole run recorded once
     b = _compare(sc, 90, 7)    # many short segments
     c = _compare(sc, 90, 1)    # one-step segments: single-step kernels only
-    assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
-    assert np.abs(a - c).max() <= 1e-5 * np.abs(a).max()
+    _same_gradient(a, b, 1e-6)
+    _same_gradient(a, c, 1e-6)
+
+
+@pytest.mark.parametrize("n_species", [1, 2])
+def test_segment_rerun_path_matches_whole_run_path(n_species):
+    """A one-byte tape limit forces the checkpoint-and-recompute sweep (each segment's
+    fields and cone steps re-run from its own checkpoint, just before it is reversed) on a
+    run of four ragged segments (35, 35, 35, 25): the same gradient as the sweep that re-runs
+    the whole run once, and as the oracle."""
+    sc = _case(n_species, seed=13)
+    a = _compare(sc, 130, 35)
+    b = _compare(sc, 130, 35, tape_limit=1)
+    _same_gradient(a, b, 1e-6)
 
 
 def test_tiled_forward_and_plain_forward_agree():
     sc = _case(1, seed=9)
     a = _compare(sc, 60, 25, block_steps=1)
     b = _compare(sc, 60, 25, block_steps=8)
-    assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
+    _same_gradient(a, b, 1e-6)
 
 
 def test_zero_steps_and_zero_weights():
@@ -168,8 +236,8 @@ def test_torch_autograd_function():
 
 def test_full_size_gradient_matches_oracle():
     """The gradient workload at full size (1024^2, 8192 cones, 32 sources, 256 targets) in the
-    launch configuration bench.py times, over 60 steps in three checkpoint segments (the last
-    ragged), against the oracle's FP64 reverse sweep of the same run.  (Finite differences of
-    the FP32 forward run are no check at this size: rounding noise in 8192 tips outweighs the
-    loss change of any perturbation small enough to stay linear.)"""
-    _compare(scenarios.adjoint(), 60, 25)
+    launch configuration bench.py times, over 400 steps in four checkpoint segments of 100,
+    against the oracle's FP64 reverse sweep of the same run, each component on its own scale.
+    (Finite differences of the FP32 forward run are no check at this size: rounding noise in
+    8192 tips outweighs the loss change of any perturbation small enough to stay linear.)"""
+    _compare(scenarios.adjoint(), 400, 100)

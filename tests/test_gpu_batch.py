@@ -118,4 +118,7 @@ def test_full_size_batch():
         print(f"[gpu] member {i}: side {scs[i].nx}, {scs[i].n_cones} cones, worst field "
               f"{run.worst['field']:.2e} tip {run.worst['tip']:.2e}, amplified "
               f"{int(run.amplified.sum())}", flush=True)
+        summary = run.summary()
+        print(f"[gpu] member {i}: {parity.describe(summary)}", flush=True)
+        parity.check_exclusions(summary, where=f"member {i}")
         run.sim.close()

@@ -25,10 +25,12 @@ def _say(msg):
     print(f"[gpu] {msg}", flush=True)
 
 
-def run_pair(sc, steps, block_steps=0, check_every=None):
+def run_pair(sc, steps, block_steps=0, check_every=None, max_differ=None, max_amplified=None):
     """Advance oracle and GPU side by side without restarts; check parity at every
     checkpoint (cones whose tip error grows by the dynamics are classified by a windowed
-    re-run, see parity.FullRun)."""
+    re-run, see parity.FullRun).  Events and tips are compared over all cones; the flagged
+    cones that differ and the amplified ones are counted, printed and bounded
+    (parity.check_exclusions)."""
     run = parity.FullRun(sc, block_steps)
     check_every = check_every or steps
     done = 0
@@ -38,6 +40,9 @@ def run_pair(sc, steps, block_steps=0, check_every=None):
         done += n
     if run.amplified.any():
         _say(f"amplified cones (windowed parity held): {np.nonzero(run.amplified)[0].tolist()}")
+    summary = run.summary()
+    _say(parity.describe(summary))
+    parity.check_exclusions(summary, max_differ, max_amplified)
     return run.sim, run.ref, run.worst
 
 
@@ -212,8 +217,10 @@ def test_events_sorted_and_consistent():
 
 
 def test_headline_size_short_run_elementwise():
-    """The 2048^2 headline workload at full size in the default launch configuration: 20
-    steps compared element by element with the oracle."""
+    """The 2048^2 headline workload at full size in the default launch configuration: 30
+    steps compared element by element with the oracle.  At this size tau = 1e-4 L is 0.2
+    cells, so most stop events fall within tau of a tie; they are compared over ALL cones,
+    flagged ones included, and at most 0.01% of the cones may differ."""
     sc = S.headline()
     block = autotune.apply(sc)   # the depth and tile shape bench.py uses
     _say(f"headline 2048^2, 65536 cones, 30 steps, block_steps {block}")

@@ -107,3 +107,7 @@ def test_connectivity_and_bfs():
 
 def test_snr_turn_law():
     pins.pin_snr_law()
+
+
+def test_adjoint_summand_magnitudes():
+    pins.pin_adjoint_magnitude()
