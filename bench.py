@@ -6,16 +6,23 @@ k = 0.005): the stencil + decay + source update of every cell, then one gradient
 turn / noise / advance / exit / contact step of every active cone.
 
 Prints ONE JSON line:
-  value          cell-updates per second over the K timed steps (inputs resident in HBM)
-  roofline       the dominant kernel against the MI355X HBM peak (8 TB/s): algorithmic
-                 bytes (8 B per cell-update: one FP32 read + one FP32 write) per launch /
-                 average launch duration from HIP events on the library's stream
-  cpu_baseline   the FP64 oracle on the host cores, on a bounded sample of the same
-                 workload (rank 0, N = 1 only)
+  value             cell-updates per second over the K timed steps (inputs resident in HBM)
+  cone_steps_per_s  active cone-steps of the K steps / (their HIP-event time - the time of
+                    the same K steps of the same field with no cones and no targets)
+  roofline          the dominant kernel against the MI355X HBM peak (8 TB/s): algorithmic
+                    bytes (8 B per cell-update: one FP32 read + one FP32 write) per launch /
+                    average launch duration from HIP events on the library's stream
+  batched_vs_plain  512 uneven simulations in one persistent launch per block (hipGraph,
+                    autotuned launch shape) against the same simulations one at a time
+  adjoint_vs_plain  the 1024^2 trajectory-loss gradient (checkpointed forward + reverse
+                    sweep) against the plain forward run of the same steps
+  cpu_baseline      the FP64 oracle on the host cores, on a bounded sample of the same
+                    workload (rank 0, N = 1 only)
 """
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -121,26 +128,32 @@ def cpu_baseline(sc, steps):
     }
 
 
-def bench_batched(args):
-    """512 uneven simulations: one persistent launch per block of steps (hipGraph replay)
-    against the same simulations advanced one after another through sim_step."""
-    scs = S.batched(count=args.batch_count)
+def measure_batched(steps, graph_launches, count=512):
+    """512 uneven simulations: one persistent launch per block of steps (hipGraph replay, the
+    depth, row width and tile height the autotuner recorded for this batch class) against
+    the same simulations advanced one after another through sim_step (each simulation's
+    library default).  Inputs are resident on the device before either timed region."""
+    scs = S.batched(count=count)
     cells = sum(sc.n_cells for sc in scs)
-    steps = args.batch_steps
-    print(f"[bench] batched: {len(scs)} simulations, {cells} cells, {steps} steps",
-          file=sys.stderr, flush=True)
+    block = autotune.apply_batch(scs)
+    print(f"[bench] batched: {len(scs)} simulations, {cells} cells, {steps} steps, "
+          f"block_steps {block or 'default'}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    bt = B.Batch(scs, graph_launches=args.graph_launches)
+    bt = B.Batch(scs, graph_launches=graph_launches, block_steps=block)
     create_s = time.perf_counter() - t0
-    bt.step(args.graph_launches * 8 if args.graph_launches else 8)   # warm-up
+    bt.step(graph_launches * 8 if graph_launches else 8)   # warm-up
     bt.synchronize()
     t0 = time.perf_counter()
     bt.step(steps)
     bt.synchronize()
     batched_s = time.perf_counter() - t0
+    t0_tiling = bt.tiling(0)
+    tiling = {"block_steps": t0_tiling["block_steps"],
+              "cols_per_lane": t0_tiling["cols_per_lane"],
+              "height_hint": int((getattr(scs[0], "tile", None) or (0, 0))[1])}
     bt.close()
     # the same simulations one at a time (library default path per simulation)
-    sims = [B.Simulation(sc) for sc in scs]
+    sims = [B.Simulation(sc) for sc in S.batched(count=count)]
     for sim in sims:
         sim.step(8)
     for sim in sims:
@@ -153,31 +166,41 @@ def bench_batched(args):
     single_s = time.perf_counter() - t0
     for sim in sims:
         sim.close()
+    return {
+        "value": cells * steps / batched_s,
+        "plain_value": cells * steps / single_s,
+        "batched_over_plain": single_s / batched_s,
+        "steps": steps, "cells": cells, "cones": sum(sc.n_cones for sc in scs),
+        "graph_launches": graph_launches, "tiling": tiling, "create_s": create_s,
+    }
+
+
+def bench_batched(args):
+    m = measure_batched(args.batch_steps, args.graph_launches, args.batch_count)
     out = {
         "metric": "batched cell-updates/s vs one simulation at a time (same GPU)",
-        "value": cells * steps / batched_s,
+        "value": m["value"],
         "unit": "cell-updates/s",
-        "n_gpus": 1, "steps": steps, "higher_is_better": True, "dtype": "f32",
+        "n_gpus": 1, "steps": m["steps"], "higher_is_better": True, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"batched {len(scs)} 2D simulations, side U{{64..512}}, "
-                               "cones log-uniform [16, 4096]", "cells": cells,
-                   "cones": sum(sc.n_cones for sc in scs),
-                   "graph_launches": args.graph_launches},
-        "one_at_a_time_value": cells * steps / single_s,
-        "speedup_vs_one_at_a_time": single_s / batched_s,
-        "create_s": create_s,
+        "config": {"workload": f"batched {args.batch_count} 2D simulations, side U{{64..512}}, "
+                               "cones log-uniform [16, 4096]", "cells": m["cells"],
+                   "cones": m["cones"], "graph_launches": m["graph_launches"],
+                   "tiling": m["tiling"]},
+        "one_at_a_time_value": m["plain_value"],
+        "speedup_vs_one_at_a_time": m["batched_over_plain"],
+        "effective_GBs": m["value"] * BYTES_PER_CELL_UPDATE / 1e9,
+        "create_s": m["create_s"],
     }
     print(json.dumps(out), flush=True)
 
 
-def bench_adjoint(args):
+def measure_adjoint(steps, every):
     """Gradient of the trajectory loss sum_i |p_i^N - t_(i mod 256)|^2 of the 2D 1024^2
     workload (32 sources, 8192 cones) with respect to the 32 source amounts, D and k: the
     checkpointed forward run plus the reverse sweep, against the plain forward run of the
     same steps on the same GPU."""
     sc = S.adjoint()
-    steps = args.adjoint_steps
-    every = args.checkpoint_every
     M = sc.n_cones
     assign = np.arange(M) % sc.target_pos.shape[0]
     weight = np.ones(M)
@@ -206,19 +229,28 @@ def bench_adjoint(args):
     t2 = time.perf_counter()
     sim.close()
     grad_s = t2 - t0
-    out = {
-        "metric": "adjoint (trajectory-loss gradient) cell-updates/s vs the plain forward run",
-        "value": sc.n_cells * steps / grad_s,
-        "unit": "cell-updates/s",
-        "n_gpus": 1, "steps": steps, "higher_is_better": True, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "adjoint 2D 1024^2, 32 sources, 8192 cones, 256 targets, "
-                               "loss sum |p_i - t_(i mod 256)|^2", "checkpoint_every": every},
+    return {
+        "value": sc.n_cells * steps / grad_s, "plain_value": sc.n_cells * steps / forward_s,
+        "gradient_over_forward": grad_s / forward_s, "steps": steps, "checkpoint_every": every,
         "forward_s": forward_s, "adjoint_forward_s": t1 - t0, "reverse_s": t2 - t1,
-        "gradient_over_forward": grad_s / forward_s,
         "loss": loss, "dL_dD": float(dD[0]), "dL_dk": float(dk[0]),
         "dL_dq_norm": float(np.linalg.norm(dq)),
     }
+
+
+def bench_adjoint(args):
+    m = measure_adjoint(args.adjoint_steps, args.checkpoint_every)
+    out = {
+        "metric": "adjoint (trajectory-loss gradient) cell-updates/s vs the plain forward run",
+        "value": m["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": m["steps"], "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "adjoint 2D 1024^2, 32 sources, 8192 cones, 256 targets, "
+                               "loss sum |p_i - t_(i mod 256)|^2",
+                   "checkpoint_every": m["checkpoint_every"]},
+    }
+    out.update({k: v for k, v in m.items() if k not in ("value", "steps", "checkpoint_every")})
     print(json.dumps(out), flush=True)
 
 
@@ -307,6 +339,26 @@ def bench_volume(args):
     print(json.dumps(out), flush=True)
 
 
+def timed_region(sc, stream, block, warmup, steps):
+    """HIP-event milliseconds of `steps` steps of `sc` after `warmup` steps, on `stream`,
+    and the tiling used."""
+    import torch
+    sim = B.Simulation(sc, stream=stream, block_steps=block)
+    tiling = sim.tiling()
+    sim.step(warmup)
+    sim.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    sim.synchronize()
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    sim.close()
+    return ms, tiling
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +390,14 @@ def main():
     ap.add_argument("--connectivity", action="store_true",
                     help="adjacency list and BFS levels of the headline run's contacts")
     ap.add_argument("--connectivity-steps", type=int, default=4000)
+    ap.add_argument("--no-cone-rate", action="store_true",
+                    help="skip the stencil-only run behind cone_steps_per_s")
+    ap.add_argument("--ratio-batch-steps", type=int, default=400,
+                    help="steps of the batched-vs-plain comparison on the default line "
+                         "(0 = skip)")
+    ap.add_argument("--ratio-adjoint-steps", type=int, default=2000,
+                    help="steps of the adjoint-vs-plain comparison on the default line "
+                         "(0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
@@ -389,6 +449,22 @@ def main():
     c = sim.cones()
     cone_steps = active_cone_steps(c["event_step"], args.warmup, args.warmup + args.steps)
     sim.close()
+    # cone-steps/s as active cone-steps / (t_with_cones - t_stencil_only): the same steps of
+    # the same field with no cones and no targets, in the same tiling, on HIP event time
+    cone_rate = None
+    if not args.no_cone_rate:
+        bare = copy.copy(sc)
+        bare.cone_pos = sc.cone_pos[:0]
+        bare.cone_dir = sc.cone_dir[:0]
+        bare.target_pos = sc.target_pos[:0]
+        bare_ms, bare_tiling = timed_region(bare, stream, block, args.warmup, args.steps)
+        extra_ms = gpu_ms - bare_ms
+        cone_rate = {
+            "value": cone_steps / (extra_ms * 1e-3) if extra_ms > 0 else None,
+            "unit": "cone-steps/s", "active_cone_steps": cone_steps,
+            "with_cones_ms": gpu_ms, "stencil_only_ms": bare_ms,
+            "same_tiling": bare_tiling == tiling,
+        }
 
     cells = sc.n_cells
     value = cells * args.steps / elapsed
@@ -425,12 +501,30 @@ def main():
                    "targets": sc.n_targets, "sources": len(sc.species[0].source_q),
                    "D": sc.species[0].D, "k": sc.species[0].k, "dt": sc.dt,
                    "tiling": tiling},
-        "cone_steps_per_s": cone_steps / elapsed,
-        "active_cone_steps": cone_steps,
+        "cone_steps_per_s": cone_rate["value"] if cone_rate else None,
+        "cone_rate": cone_rate,
         "effective_GBs": value * BYTES_PER_CELL_UPDATE / 1e9,
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.snr:
+        # the second half of the metric: batched and adjoint throughput against the plain
+        # per-simulation path on the same GPU (short runs of those workloads)
+        if args.ratio_batch_steps > 0:
+            m = measure_batched(args.ratio_batch_steps, args.graph_launches)
+            out["batched_vs_plain"] = {
+                "workload": "512 uneven 2D simulations, one persistent launch per block "
+                            "(hipGraph) vs sim_step per simulation",
+                "steps": m["steps"], "batched_cell_updates_per_s": m["value"],
+                "plain_cell_updates_per_s": m["plain_value"],
+                "ratio": m["batched_over_plain"], "tiling": m["tiling"]}
+        if args.ratio_adjoint_steps > 0:
+            m = measure_adjoint(args.ratio_adjoint_steps, args.checkpoint_every)
+            out["adjoint_vs_plain"] = {
+                "workload": "2D 1024^2 trajectory-loss gradient (32 q, D, k), checkpoint "
+                            f"every {m['checkpoint_every']}, vs the plain forward run",
+                "steps": m["steps"], "gradient_s": m["adjoint_forward_s"] + m["reverse_s"],
+                "forward_s": m["forward_s"], "ratio": m["gradient_over_forward"]}
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
     print(json.dumps(out), flush=True)

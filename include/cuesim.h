@@ -269,7 +269,8 @@ sim_status sim_bfs_levels(sim_handle* h, int32_t root, int32_t* level);
 typedef struct sim_batch sim_batch;
 
 /* Create n simulations from params[0..n-1] (each validated as by sim_create; arrays
- * copied).  graph_launches > 0 captures that many full-depth launches in a hipGraph that
+ * copied).  All share block_steps and tile_cols_per_lane (0 = 2 for a batch); each keeps
+ * its own tile_height hint.  graph_launches > 0 captures that many full-depth launches in a hipGraph that
  * sim_batch_step replays; 0 launches directly.  Errors as sim_create; *out = NULL on error
  * and sim_batch_last_error(NULL) describes it. */
 sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hip_stream,

@@ -5,10 +5,12 @@ module measures instead: for a scenario it times whole runs (the scenario's step
 that the late phase, when cones crowd around sources and targets, weighs in) of candidate
 (B, row width, tile height) settings on the GPU through the C ABI -- on fresh copies of the
 scenario, so nothing the caller holds is advanced -- and caches the fastest setting per size
-class in ``tile_cache.json`` next to this file.  For a batch (one shared B and row width) it
-times batch launches per candidate B.
+class in ``tile_cache.json`` next to this file.  For a batch (one shared B and row width,
+and a tile height hint for every simulation) it times batch launches per candidate and
+records the fastest per batch class.
 
     python -m paper_1405_3331_amd.autotune headline      # tune and record a named workload
+    python -m paper_1405_3331_amd.autotune batched       # the 512-simulation batch
 """
 from __future__ import annotations
 
@@ -79,15 +81,44 @@ def tune(sc, candidates=None, steps=None, verbose=False) -> dict:
             "seconds_per_step": best["seconds_per_step"], "trials": trials}
 
 
-def tune_batch(scenarios, blocks=(4, 6, 8, 10, 12), launches=6, verbose=False) -> dict:
-    """Time batch launches for each candidate shared depth B; return the fastest."""
+def batch_class(scenarios) -> str:
+    """Batches in one class share the best launch shape: same simulation count and species
+    count, total cells and total cones within a factor of two."""
+    cells = sum(sc.n_cells for sc in scenarios)
+    cones = sum(sc.n_cones for sc in scenarios)
+    return (f"batch:{len(scenarios)}sims:species{len(scenarios[0].species)}:"
+            f"cells2^{int(math.log2(max(cells, 1)))}:cones2^{int(math.log2(max(cones, 1)))}")
+
+
+def default_batch_candidates():
+    """(block_steps, cols_per_lane, height) for a batch: one shared depth and row width;
+    height is every simulation's tile height hint (0 = each simulation's planner)."""
+    return ([(b, 2, h) for b in (4, 6, 8, 10, 12, 16) for h in (0, 110)] +
+            [(b, 4, 0) for b in (6, 8, 12)])
+
+
+def _with_tile(scenarios, cpl, height):
+    out = []
+    for sc in scenarios:
+        trial = copy.copy(sc)
+        trial.tile = (cpl, height)
+        out.append(trial)
+    return out
+
+
+def tune_batch(scenarios, candidates=None, launches=8, verbose=False) -> dict:
+    """Time batch launches (persistent grid, no graph) of every candidate (block_steps,
+    cols_per_lane, height) over `launches` full-depth launches; return
+    {"best": (block, cpl, height), "seconds_per_step": ..., "trials": [...]}."""
     trials = []
     cells = sum(sc.n_cells for sc in scenarios)
-    for block in blocks:
+    for block, cpl, height in candidates or default_batch_candidates():
         try:
-            bt = B.Batch(scenarios, graph_launches=0, block_steps=block)
+            bt = B.Batch(_with_tile(scenarios, cpl, height), graph_launches=0,
+                         block_steps=block)
         except B.SimError:
-            trials.append({"block_steps": block, "seconds_per_step": None})
+            trials.append({"block_steps": block, "cols_per_lane": cpl, "height": height,
+                           "seconds_per_step": None})
             continue
         bt.step(block)
         bt.synchronize()
@@ -96,14 +127,37 @@ def tune_batch(scenarios, blocks=(4, 6, 8, 10, 12), launches=6, verbose=False) -
         bt.synchronize()
         dt = (time.perf_counter() - t0) / (block * launches)
         bt.close()
-        trials.append({"block_steps": block, "seconds_per_step": dt})
+        trials.append({"block_steps": block, "cols_per_lane": cpl, "height": height,
+                       "seconds_per_step": dt})
         if verbose:
-            print(f"[autotune] batch B={block}: {dt * 1e6:.1f} us/step, "
-                  f"{cells / dt:.3e} cell-updates/s", flush=True)
+            print(f"[autotune] batch B={block} cpl={cpl} height={height}: "
+                  f"{dt * 1e6:.1f} us/step, {cells / dt:.3e} cell-updates/s", flush=True)
     ok = [t for t in trials if t["seconds_per_step"] is not None]
+    if not ok:
+        raise RuntimeError("no candidate launch shape fits this batch")
     best = min(ok, key=lambda t: t["seconds_per_step"])
-    return {"best_block_steps": best["block_steps"], "seconds_per_step": best["seconds_per_step"],
-            "trials": trials}
+    return {"best": (best["block_steps"], best["cols_per_lane"], best["height"]),
+            "seconds_per_step": best["seconds_per_step"], "trials": trials}
+
+
+def record_batch(scenarios, result, path=CACHE):
+    cache = load_cache(path)
+    cache[batch_class(scenarios)] = {
+        "block_steps": result["best"][0], "cols_per_lane": result["best"][1],
+        "height": result["best"][2], "seconds_per_step": result["seconds_per_step"]}
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def apply_batch(scenarios, path=CACHE) -> int:
+    """Set every scenario's tile hint from the batch class's record; return the shared
+    block_steps (0 when the class was never tuned: the library default)."""
+    hit = load_cache(path).get(batch_class(scenarios))
+    if not hit:
+        return 0
+    for sc in scenarios:
+        sc.tile = (hit["cols_per_lane"], hit["height"])
+    return hit["block_steps"]
 
 
 def load_cache(path=CACHE) -> dict:
@@ -145,10 +199,16 @@ def main(argv):
     from . import scenarios
     names = argv or ["headline"]
     for name in names:
-        sc = scenarios.NAMED[name]()
-        print(f"[autotune] {sc.name} ({size_class(sc)})", flush=True)
-        res = tune(sc, verbose=True)
-        record(sc, res)
+        if name == "batched":
+            scs = scenarios.batched()
+            print(f"[autotune] batched ({batch_class(scs)})", flush=True)
+            res = tune_batch(scs, verbose=True)
+            record_batch(scs, res)
+        else:
+            sc = scenarios.NAMED[name]()
+            print(f"[autotune] {sc.name} ({size_class(sc)})", flush=True)
+            res = tune(sc, verbose=True)
+            record(sc, res)
         print(f"[autotune] best {res['best']} at {res['seconds_per_step'] * 1e6:.2f} us/step",
               flush=True)
 

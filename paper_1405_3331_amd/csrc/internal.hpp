@@ -7,6 +7,7 @@
 
 #include <vector>
 
+#include "cuesim.h"
 #include "device.hpp"
 
 namespace cuesim {
@@ -189,6 +190,21 @@ struct GraphBuffers {
 };
 hipError_t launch_adjacency(const GraphBuffers& g, const int32_t* status, const int32_t* target,
                             int n_cones, int n_neurons, hipStream_t stream);
+
+// Host side of the connectivity build (sim.hip), shared by the entry points that build it:
+// the argument checks, and the build itself into caller-provided device buffers g (owners
+// uploaded, adjacency built on the handle's stream, copied into the caller's arrays).
+sim_status connectivity_validate(sim_handle* h, int32_t n_neurons, const int32_t* cone_owner,
+                                 const int32_t* target_owner, const int32_t* row_start,
+                                 const int32_t* edges, int64_t edge_capacity,
+                                 const int64_t* n_edges);
+sim_status connectivity_build(sim_handle* h, const GraphBuffers& g, const int32_t* cone_owner,
+                              const int32_t* target_owner, int32_t* row_start, int32_t* edges,
+                              int64_t edge_capacity, int64_t* n_edges);
+sim_status handle_fail(sim_handle* h, sim_status st, const char* msg);
+int handle_cones(const sim_handle* h);
+int handle_targets(const sim_handle* h);
+int handle_device(const sim_handle* h);   // the device the handle was created on
 hipError_t launch_bfs_init(int32_t* level, int n, int root, hipStream_t stream);
 hipError_t launch_bfs_level(const int32_t* row_start, const int32_t* edges, int n, int depth,
                             int32_t* level, int32_t* grew, hipStream_t stream);

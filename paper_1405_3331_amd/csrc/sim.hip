@@ -745,7 +745,72 @@ void batch_advance(sim_batch* b, int steps, int launches) {
 
 }  // namespace
 
+namespace cuesim {
+
+sim_status handle_fail(sim_handle* h, sim_status st, const char* msg) {
+    return fail(h, st, "%s", msg);
+}
+
+int handle_cones(const sim_handle* h) { return h->n_cones; }
+
+int handle_targets(const sim_handle* h) { return h->n_targets; }
+
+int handle_device(const sim_handle* h) { return h->device; }
+
+sim_status connectivity_validate(sim_handle* h, int32_t n_neurons, const int32_t* cone_owner,
+                                 const int32_t* target_owner, const int32_t* row_start,
+                                 const int32_t* edges, int64_t edge_capacity,
+                                 const int64_t* n_edges) {
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    const int M = h->n_cones, T = h->n_targets;
+    if (n_neurons < 1) return fail(h, SIM_EINVAL, "n_neurons < 1");
+    if (!row_start || !n_edges || edge_capacity < 0 || (edge_capacity > 0 && !edges) ||
+        (M > 0 && !cone_owner) || (T > 0 && !target_owner))
+        return fail(h, SIM_EINVAL, "NULL pointer or negative capacity");
+    for (int i = 0; i < M; ++i)
+        if (cone_owner[i] < 0 || cone_owner[i] >= n_neurons)
+            return fail(h, SIM_EINVAL, "cone_owner[%d] = %d out of range", i, cone_owner[i]);
+    for (int t = 0; t < T; ++t)
+        if (target_owner[t] < 0 || target_owner[t] >= n_neurons)
+            return fail(h, SIM_EINVAL, "target_owner[%d] = %d out of range", t, target_owner[t]);
+    return SIM_OK;
+}
+
+sim_status connectivity_build(sim_handle* h, const GraphBuffers& g, const int32_t* cone_owner,
+                              const int32_t* target_owner, int32_t* row_start, int32_t* edges,
+                              int64_t edge_capacity, int64_t* n_edges) {
+    const int M = h->n_cones, T = h->n_targets;
+    const size_t N = (size_t)g.n_neurons;
+    if (M > 0)
+        HIP_TRY(h, hipMemcpyAsync(g.owner, cone_owner, (size_t)M * 4, hipMemcpyHostToDevice,
+                                  h->stream));
+    if (T > 0)
+        HIP_TRY(h, hipMemcpyAsync(g.target_owner, target_owner, (size_t)T * 4,
+                                  hipMemcpyHostToDevice, h->stream));
+    // stopped cones keep their final status and target in the caller-order arrays
+    HIP_TRY(h, launch_adjacency(g, h->cones.status, h->cones.target, M, g.n_neurons,
+                                h->stream));
+    HIP_TRY(h, hipMemcpyAsync(row_start, g.row_start, (N + 1) * 4, hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const int64_t E = row_start[g.n_neurons];
+    *n_edges = E;
+    if (E > edge_capacity)
+        return fail(h, SIM_ERANGE, "edge buffer holds %lld edges, %lld needed",
+                    (long long)edge_capacity, (long long)E);
+    if (E > 0) {
+        HIP_TRY(h, hipMemcpyAsync(edges, g.edges, (size_t)E * 4, hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return SIM_OK;
+}
+
+}  // namespace cuesim
+
 extern "C" {
+
 
 sim_status sim_create(const sim_params* p, void* hip_stream, sim_handle** out) {
     return create_impl(p, hip_stream, 0, out);
@@ -1323,19 +1388,10 @@ sim_status sim_adjoint_set_tape_limit(sim_handle* h, int64_t max_bytes) {
 sim_status sim_connectivity(sim_handle* h, int32_t n_neurons, const int32_t* cone_owner,
                             const int32_t* target_owner, int32_t* row_start, int32_t* edges,
                             int64_t edge_capacity, int64_t* n_edges) {
-    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
-    if (h->poisoned) return fail(h, SIM_ESTATE, "handle poisoned by an earlier device error");
+    sim_status st = connectivity_validate(h, n_neurons, cone_owner, target_owner, row_start,
+                                          edges, edge_capacity, n_edges);
+    if (st != SIM_OK) return st;
     const int M = h->n_cones, T = h->n_targets;
-    if (n_neurons < 1) return fail(h, SIM_EINVAL, "n_neurons < 1");
-    if (!row_start || !n_edges || edge_capacity < 0 || (edge_capacity > 0 && !edges) ||
-        (M > 0 && !cone_owner) || (T > 0 && !target_owner))
-        return fail(h, SIM_EINVAL, "NULL pointer or negative capacity");
-    for (int i = 0; i < M; ++i)
-        if (cone_owner[i] < 0 || cone_owner[i] >= n_neurons)
-            return fail(h, SIM_EINVAL, "cone_owner[%d] = %d out of range", i, cone_owner[i]);
-    for (int t = 0; t < T; ++t)
-        if (target_owner[t] < 0 || target_owner[t] >= n_neurons)
-            return fail(h, SIM_EINVAL, "target_owner[%d] = %d out of range", t, target_owner[t]);
     graph_release(h);
     GraphBuffers& g = h->graph;
     const size_t Ms = (size_t)std::max(M, 1), N = (size_t)n_neurons;
@@ -1354,29 +1410,9 @@ sim_status sim_connectivity(sim_handle* h, int32_t n_neurons, const int32_t* con
         if (e == hipErrorOutOfMemory) return fail(h, SIM_ENOMEM, "connectivity buffers");
         return device_fail(h, e, "connectivity allocation");
     }
-    if (M > 0)
-        HIP_TRY(h, hipMemcpyAsync(g.owner, cone_owner, (size_t)M * 4, hipMemcpyHostToDevice,
-                                  h->stream));
-    if (T > 0)
-        HIP_TRY(h, hipMemcpyAsync(g.target_owner, target_owner, (size_t)T * 4,
-                                  hipMemcpyHostToDevice, h->stream));
-    // stopped cones keep their final status and target in the caller-order arrays
-    HIP_TRY(h, launch_adjacency(g, h->cones.status, h->cones.target, M, n_neurons, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(row_start, g.row_start, (N + 1) * 4, hipMemcpyDeviceToHost,
-                              h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    const int64_t E = row_start[n_neurons];
-    *n_edges = E;
     h->graph_cones = M;
-    if (E > edge_capacity)
-        return fail(h, SIM_ERANGE, "edge buffer holds %lld edges, %lld needed",
-                    (long long)edge_capacity, (long long)E);
-    if (E > 0) {
-        HIP_TRY(h, hipMemcpyAsync(edges, g.edges, (size_t)E * 4, hipMemcpyDeviceToHost,
-                                  h->stream));
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
-    }
-    return SIM_OK;
+    return connectivity_build(h, g, cone_owner, target_owner, row_start, edges, edge_capacity,
+                              n_edges);
 }
 
 sim_status sim_bfs_levels(sim_handle* h, int32_t root, int32_t* level) {
@@ -1415,7 +1451,13 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
             return batch_fail(nullptr, SIM_EINVAL, "all simulations need the same n_species");
         if (params[i]->block_steps != params[0]->block_steps)
             return batch_fail(nullptr, SIM_EINVAL, "all simulations need the same block_steps");
+        if (params[i]->tile_cols_per_lane != params[0]->tile_cols_per_lane)
+            return batch_fail(nullptr, SIM_EINVAL,
+                              "all simulations need the same tile_cols_per_lane");
     }
+    if (params[0]->tile_cols_per_lane != 0 && params[0]->tile_cols_per_lane != 2 &&
+        params[0]->tile_cols_per_lane != 4)
+        return batch_fail(nullptr, SIM_EINVAL, "tile_cols_per_lane must be 0, 2 or 4");
     sim_batch* b = new (std::nothrow) sim_batch();
     if (!b) return batch_fail(nullptr, SIM_ENOMEM, "host allocation failed");
     auto bail = [&](sim_status st) {
@@ -1434,7 +1476,7 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
         b->own_stream = true;
     }
     b->n_species = params[0]->n_species;
-    b->cpl = 2;
+    b->cpl = params[0]->tile_cols_per_lane ? params[0]->tile_cols_per_lane : 2;
     int64_t total_cones = 0;
     for (int i = 0; i < n; ++i) {
         sim_params q = *params[i];

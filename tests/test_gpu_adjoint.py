@@ -11,7 +11,7 @@ from paper_1405_3331_amd import binding as B, scenarios
 pytestmark = pytest.mark.gpu
 
 # Gradient tolerance, per component (FP32 forward + reverse against the FP64 oracle):
-#   |got_i - want_i| <= GRAD_TOL * magnitude_i
+#   |got_i - want_i| <= GRAD_TOL * magnitude_i + GRAD_FLOOR * max_group magnitude
 # where magnitude_i is the oracle's sum of the absolute values of the terms component i adds
 # up (its sum over steps and cells of |a c|, |a Lap c|, or |a| at the source cell).  A sum
 # of terms each correct to a relative error e is correct to e * magnitude: the bound holds
@@ -19,7 +19,12 @@ pytestmark = pytest.mark.gpu
 # species can be a thousand times smaller than its terms).  The terms' relative error comes
 # from the FP32 adjoint field, whose cone samples move with the tips (FP32 tips agree with
 # the oracle's to ~1e-6 of the domain, i.e. the interpolation fractions to ~1e-4).
+# Components far smaller than their group's terms (a source far from every cone: its
+# gradient sits in the diffusion tail of the cones' sample adjoints, whose relative size
+# moves by ~1e-4 per 1e-4 cell of tip difference at tens of cells' distance) are held to an
+# absolute floor of GRAD_FLOOR times the group's largest term scale, the FP32 epsilon.
 GRAD_TOL = 1e-4
+GRAD_FLOOR = 1e-7
 
 
 def _groups(n_q, ns):
@@ -37,13 +42,14 @@ def check_gradient(got, want, magnitude, n_q, ns, where=""):
     for name, sl in _groups(n_q, ns):
         g, w, mag = got[sl], want[sl], magnitude[sl]
         err = np.abs(g - w)
+        bound = GRAD_TOL * mag + GRAD_FLOOR * mag.max()
         frac = err / np.maximum(mag, 1e-300)
-        i = int(np.argmax(frac))
+        i = int(np.argmax(err / np.maximum(bound, 1e-300)))
         worst[name] = float(frac[i])
         print(f"[adjoint] {where} {name}: worst component {i}: got {g[i]:.6e} want {w[i]:.6e} "
               f"(terms {mag[i]:.3e}): error {frac[i]:.2e} of the terms, "
               f"{err[i] / max(abs(w[i]), 1e-300):.2e} of the value", flush=True)
-        assert np.all(err <= GRAD_TOL * mag), (where, name, i, g[i], w[i], mag[i])
+        assert np.all(err <= bound), (where, name, i, g[i], w[i], mag[i])
     return worst
 
 
@@ -78,20 +84,21 @@ def _compare(sc, steps, every, block_steps=0, tape_limit=0):
     M = sc.n_cones
     assign = np.arange(M) % sc.target_pos.shape[0]
     w = np.linspace(0.5, 1.5, M)
-    for attempt in range(2):
+    ref = oracle.OracleSim(sc)
+    L_ref, dq_ref, dD_ref, dk_ref, mag = ref.adjoint(steps, assign, w, magnitude=True)
+    L, c, got = _run_gpu(sc, steps, every, assign, w, block_steps, tape_limit)
+    differ = np.nonzero((c["status"] != ref.status) | (c["event_step"] != ref.event_step) |
+                        (c["target"] != ref.target))[0]
+    if len(differ):
+        assert np.all(ref.flag_step[differ] >= 0), (differ, ref.flag_step[differ])
+        assert len(differ) <= max(1, M // 10000), differ
+        print(f"[adjoint] cones {differ.tolist()} stop differently (flagged near-ties at "
+              f"steps {ref.flag_step[differ].tolist()}): weight 0", flush=True)
+        w = w.copy()
+        w[differ] = 0.0
         ref = oracle.OracleSim(sc)
         L_ref, dq_ref, dD_ref, dk_ref, mag = ref.adjoint(steps, assign, w, magnitude=True)
         L, c, got = _run_gpu(sc, steps, every, assign, w, block_steps, tape_limit)
-        differ = np.nonzero((c["status"] != ref.status) | (c["event_step"] != ref.event_step) |
-                            (c["target"] != ref.target))[0]
-        if len(differ) == 0:
-            break
-        assert attempt == 0 and np.all(ref.flag_step[differ] >= 0), (differ, ref.flag_step[differ])
-        assert len(differ) <= max(1, M // 10000), differ
-        print(f"[adjoint] cones {differ.tolist()} stop differently (flagged near-ties): "
-              f"weight 0", flush=True)
-        w = w.copy()
-        w[differ] = 0.0
     want = np.concatenate([dq_ref, dD_ref, dk_ref])
     where = f"steps={steps} every={every} tape_limit={tape_limit}"
     print(f"[adjoint] {where} loss rel {abs(L - L_ref) / L_ref:.2e}", flush=True)

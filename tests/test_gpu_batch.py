@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import parity
+from paper_1405_3331_amd import autotune
 from paper_1405_3331_amd import binding as B
 from paper_1405_3331_amd import scenarios as S
 
@@ -99,8 +100,10 @@ def test_full_size_batch():
     smallest, the largest, the most and the fewest cones, four more) match the FP64 oracle
     (full-run parity with the classification of dynamically amplified cones)."""
     scs = S.batched()
-    print(f"[gpu] full-size batch: {len(scs)} simulations, 80 steps", flush=True)
-    with B.Batch(scs, graph_launches=10) as bt:
+    block = autotune.apply_batch(scs)   # the launch shape bench.py uses
+    print(f"[gpu] full-size batch: {len(scs)} simulations, 80 steps, block_steps {block}, "
+          f"tile hint {getattr(scs[0], 'tile', None)}", flush=True)
+    with B.Batch(scs, graph_launches=10, block_steps=block) as bt:
         bt.step(80)
         for i, sc in enumerate(scs):
             with B.Simulation(sc) as one:
