@@ -253,6 +253,18 @@ sim_status sim_connectivity(sim_handle* h, int32_t n_neurons, const int32_t* con
                             const int32_t* target_owner, int32_t* row_start, int32_t* edges,
                             int64_t edge_capacity, int64_t* n_edges);
 
+/* sim_connectivity for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * result and errors, but every device buffer comes from one fixed array in the library
+ * (about 10.6 MB per GPU, held until the process ends) and the call allocates nothing.
+ * Limits: at most 262144 cones, 262144 targets and 262144 neurons, else SIM_EINVAL before
+ * any device work.  The graph is not kept for sim_bfs_levels.  All calls on one GPU share
+ * the array: calls that overlap on one GPU (from several threads or handles) race. */
+sim_status sim_connectivity_noalloc(sim_handle* h, int32_t n_neurons,
+                                    const int32_t* cone_owner, const int32_t* target_owner,
+                                    int32_t* row_start, int32_t* edges, int64_t edge_capacity,
+                                    int64_t* n_edges);
+
 /* Level-synchronous breadth-first traversal of the last sim_connectivity graph from root
  * (one device launch per level, one thread per vertex): level[n_neurons] (host) receives
  * the number of edges on a shortest path from root, -1 where unreachable.  SIM_ESTATE if no

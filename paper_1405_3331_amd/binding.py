@@ -33,7 +33,7 @@ EXPORTED = ["sim_create", "sim_step", "sim_set_mass_check", "sim_read_state",
             "sim_batch_create", "sim_batch_step", "sim_batch_read_state",
             "sim_batch_synchronize", "sim_batch_destroy", "sim_batch_last_error",
             "sim_adjoint_run", "sim_adjoint_backward", "sim_adjoint_set_tape_limit",
-            "sim_connectivity", "sim_bfs_levels"]
+            "sim_connectivity", "sim_connectivity_noalloc", "sim_bfs_levels"]
 
 
 class SimError(RuntimeError):
@@ -107,6 +107,8 @@ def load(path: str = LIBRARY):
     lib.sim_adjoint_set_tape_limit.argtypes = [H, C.c_int64]
     lib.sim_connectivity.argtypes = [H, C.c_int32, _ip, _ip, _ip, _ip, C.c_int64,
                                      C.POINTER(C.c_int64)]
+    lib.sim_connectivity_noalloc.argtypes = [H, C.c_int32, _ip, _ip, _ip, _ip, C.c_int64,
+                                             C.POINTER(C.c_int64)]
     lib.sim_bfs_levels.argtypes = [H, C.c_int32, _ip]
     for name in EXPORTED:
         if not name.endswith("last_error"):
@@ -274,17 +276,19 @@ def sim_adjoint_backward(h, n_q: int, n_species: int):
     return dq[:n_q], dD, dk
 
 
-def sim_connectivity(h, n_neurons: int, cone_owner, target_owner):
-    """(row_start [n_neurons + 1], edges [n_edges]) of the connections made so far."""
+def sim_connectivity(h, n_neurons: int, cone_owner, target_owner, noalloc: bool = False):
+    """(row_start [n_neurons + 1], edges [n_edges]) of the connections made so far
+    (noalloc: through sim_connectivity_noalloc, which allocates no device memory)."""
     owner = np.ascontiguousarray(cone_owner, dtype=np.int32)
     towner = np.ascontiguousarray(target_owner, dtype=np.int32)
     row_start = np.zeros(n_neurons + 1, dtype=np.int32)
     n_edges = C.c_int64(0)
     cap = max(int(owner.size), 1)
     edges = np.zeros(cap, dtype=np.int32)
-    _check(load().sim_connectivity(h, int(n_neurons), owner.ctypes.data_as(_ip),
-                                   towner.ctypes.data_as(_ip), row_start.ctypes.data_as(_ip),
-                                   edges.ctypes.data_as(_ip), cap, C.byref(n_edges)), h)
+    fn = load().sim_connectivity_noalloc if noalloc else load().sim_connectivity
+    _check(fn(h, int(n_neurons), owner.ctypes.data_as(_ip), towner.ctypes.data_as(_ip),
+              row_start.ctypes.data_as(_ip), edges.ctypes.data_as(_ip), cap,
+              C.byref(n_edges)), h)
     return row_start, edges[: n_edges.value].copy()
 
 
