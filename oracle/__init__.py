@@ -46,7 +46,7 @@ class _State(C.Structure):
     _fields_ = [
         ("step", C.c_int64), ("field", _dp * 2), ("n_cones", C.c_int32),
         ("pos", _dp), ("dir", _dp), ("status", _ip), ("target", _ip),
-        ("event_step", _ip), ("flag_step", _ip),
+        ("event_step", _ip), ("flag_step", _ip), ("cap_margin", _dp),
     ]
 
 
@@ -82,7 +82,8 @@ def load(path: str = LIBRARY):
         lib.oracle_bfs_levels.restype = C.c_int
     if hasattr(lib, "oracle_adjoint"):
         lib.oracle_adjoint.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.c_int64,
-                                       C.POINTER(C.c_int32), _dp, _dp, _dp, _dp, _dp, _dp]
+                                       C.POINTER(C.c_int32), _dp, _dp, _dp, _dp, _dp, _dp,
+                                       _dp]
         lib.oracle_adjoint.restype = C.c_int
     if path == LIBRARY:
         _lib = lib
@@ -204,6 +205,7 @@ class OracleSim:
         self.target = np.full(M, -1, dtype=np.int32)
         self.event_step = np.full(M, -1, dtype=np.int32)
         self.flag_step = np.full(M, -1, dtype=np.int32)
+        self.cap_margin = np.full(M, np.inf)
         self.step_count = 0
         self._bind_state()
 
@@ -219,6 +221,7 @@ class OracleSim:
         st.target = _ptr(self.target, C.c_int32)
         st.event_step = _ptr(self.event_step, C.c_int32)
         st.flag_step = _ptr(self.flag_step, C.c_int32)
+        st.cap_margin = _ptr(self.cap_margin, C.c_double)
         self.state = st
 
     # -- stepping --------------------------------------------------------------------
@@ -240,12 +243,14 @@ class OracleSim:
             self.fields[s][...] = out[s]
         return self
 
-    def adjoint(self, n_steps: int, assign, weight, magnitude=False):
+    def adjoint(self, n_steps: int, assign, weight, magnitude=False, cone_adjoint=False):
         """Run n_steps forward (advancing this simulation) and return the trajectory loss
         sum_i weight[i] |p_i^N - target[assign[i]]|^2 with its gradient along the run's
         branch: (loss, dL/dq [all sources, species 0 first], dL/dD [species], dL/dk).  With
         magnitude=True a fifth item holds, for every component in the order
-        (dL/dq..., dL/dD..., dL/dk...), the same sum over the absolute values of its terms."""
+        (dL/dq..., dL/dD..., dL/dk...), the same sum over the absolute values of its terms;
+        with cone_adjoint=True a further item holds dL/d(x, y, theta) of every cone at the
+        start of the run ([M, 3])."""
         assign = np.ascontiguousarray(assign, dtype=np.int32)
         weight = np.ascontiguousarray(weight, dtype=np.float64)
         assert assign.shape == (self.pos.shape[0],) and weight.shape == assign.shape
@@ -256,19 +261,25 @@ class OracleSim:
         loss = np.zeros(1)
         ns = self.params.n_species
         mag = np.zeros(nq + 2 * ns)
+        acone = np.zeros((max(self.pos.shape[0], 1), 3))
         self.state.step = self.step_count
         rc = self.lib.oracle_adjoint(C.byref(self.params), C.byref(self.state), int(n_steps),
                                      _ptr(assign, C.c_int32), _ptr(weight, C.c_double),
                                      _ptr(loss, C.c_double), _ptr(dq, C.c_double),
                                      _ptr(dD, C.c_double), _ptr(dk, C.c_double),
-                                     _ptr(mag, C.c_double) if magnitude else None)
+                                     _ptr(mag, C.c_double) if magnitude else None,
+                                     _ptr(acone, C.c_double) if cone_adjoint else None)
         if rc == -2:
             raise ValueError("oracle_adjoint: 2D only")
         if rc != 0:
             raise MemoryError("oracle_adjoint: allocation failed")
         self.step_count = int(self.state.step)
         out = (float(loss[0]), dq[:nq].copy(), dD[:ns].copy(), dk[:ns].copy())
-        return out + (mag,) if magnitude else out
+        if magnitude:
+            out += (mag,)
+        if cone_adjoint:
+            out += (acone[: self.pos.shape[0]].copy(),)
+        return out
 
     # -- reading ---------------------------------------------------------------------
     def mass(self, s: int = 0) -> float:

@@ -235,8 +235,20 @@ static double domain_length(const oracle_params* p, int a)
     return (double)axis_size(p, a) * p->dx;
 }
 
+/* Distance of an uncapped turn angle from the cap, kept as a running minimum (recorded
+   only; it does not change the trajectory).  A turn this close to the cap can take the
+   other side of it under rounding, which switches the turn's derivative. */
+static void note_cap_margin(const oracle_params* p, double angle, double* cap_margin)
+{
+    if (cap_margin) {
+        double m = fabs(fabs(angle) - p->max_turn);
+        if (m < *cap_margin) *cap_margin = m;
+    }
+}
+
 /* C2 (2D): rotate heading angle theta toward theta + angle(h + gain*g), capped. */
-static double turn_2d(const oracle_params* p, double theta, const double g[3], int* ambiguous)
+static double turn_2d(const oracle_params* p, double theta, const double g[3], int* ambiguous,
+                      double* cap_margin)
 {
     double hx = cos(theta), hy = sin(theta);
     double cross = hx * g[1] - hy * g[0];      /* sine part (Sec. 3.5, Eq. 7 discussion) */
@@ -246,13 +258,15 @@ static double turn_2d(const oracle_params* p, double theta, const double g[3], i
     if (y == 0.0) y = 0.0;                     /* -0 -> +0: anti-parallel turns by +cap */
     if (x < 0.0 && fabs(y) <= 1e-5 * fabs(x)) *ambiguous = 1;
     double delta = atan2(y, x);
+    note_cap_margin(p, delta, cap_margin);
     if (delta > p->max_turn) delta = p->max_turn;
     if (delta < -p->max_turn) delta = -p->max_turn;
     return theta + delta;
 }
 
 /* C2 (3D): rotate h toward h + gain*g in the plane they span, by at most max_turn. */
-static void turn_3d(const oracle_params* p, double h[3], const double g[3], int* ambiguous)
+static void turn_3d(const oracle_params* p, double h[3], const double g[3], int* ambiguous,
+                    double* cap_margin)
 {
     double along = g[0] * h[0] + g[1] * h[1] + g[2] * h[2];
     double perp[3] = {g[0] - along * h[0], g[1] - along * h[1], g[2] - along * h[2]};
@@ -262,6 +276,7 @@ static void turn_3d(const oracle_params* p, double h[3], const double g[3], int*
     if (perp_norm == 0.0)
         return;
     double phi = atan2(p->turn_gain * perp_norm, x);
+    note_cap_margin(p, phi, cap_margin);
     if (phi > p->max_turn) phi = p->max_turn;
     double c = cos(phi), s = sin(phi);
     for (int a = 0; a < 3; ++a)
@@ -365,7 +380,8 @@ static void step_one_cone(const oracle_params* p, oracle_state* s, int i,
             theta = turn_snr_2d(p, s->dir[i], g, c, z[0], &ambiguous);
             theta += p->noise_sigma * z[1];
         } else {
-            theta = turn_2d(p, s->dir[i], g, &ambiguous);
+            theta = turn_2d(p, s->dir[i], g, &ambiguous,
+                            s->cap_margin ? s->cap_margin + i : NULL);
             theta += p->noise_sigma * z[0];
         }
         theta -= 2.0 * ORACLE_PI * floor((theta + ORACLE_PI) / (2.0 * ORACLE_PI));
@@ -375,7 +391,7 @@ static void step_one_cone(const oracle_params* p, oracle_state* s, int i,
         h[2] = 0.0;
     } else {
         double* hd = s->dir + (int64_t)i * 3;
-        turn_3d(p, hd, g, &ambiguous);
+        turn_3d(p, hd, g, &ambiguous, s->cap_margin ? s->cap_margin + i : NULL);
         noise_3d(p, hd, z);
         h[0] = hd[0]; h[1] = hd[1]; h[2] = hd[2];
     }
@@ -613,7 +629,8 @@ static void cone_reverse_2d(const oracle_params* p, const double* const fields[2
 
 int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
                    const int32_t* assign, const double* weight, double* loss,
-                   double* dL_dq, double* dL_dD, double* dL_dk, double* magnitude)
+                   double* dL_dq, double* dL_dD, double* dL_dk, double* magnitude,
+                   double* cone_adjoint)
 {
     if (p->dim != 2)
         return -2;
@@ -723,6 +740,8 @@ int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
             memcpy(a, aprev, (size_t)cells * sizeof(double));
         }
     }
+    if (cone_adjoint)
+        memcpy(cone_adjoint, acone, (size_t)M * 3 * sizeof(double));
     free(tape_c); free(tape_cone); free(afield); free(lap); free(aprev); free(acone);
     return 0;
 }

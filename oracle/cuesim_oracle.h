@@ -59,6 +59,8 @@ typedef struct oracle_state {
     int32_t* target;             /* contacted target, -1 if none */
     int32_t* event_step;         /* step at which status changed, -1 if none */
     int32_t* flag_step;          /* first step with a near-tie margin <= flag_tol, -1 if none */
+    double* cap_margin;          /* may be NULL: per cone, the smallest distance (rad) of an
+                                    uncapped vector-law turn angle from max_turn so far */
 } oracle_state;
 
 /* Philox4x32-10 bijection (Salmon et al., SC'11). */
@@ -91,10 +93,14 @@ int oracle_run(const oracle_params* p, oracle_state* s, int64_t n_steps);
  * magnitude (may be NULL; [n_q + 2 n_species], ordered like dL_dq, dL_dD, dL_dk) receives
  * the same sums taken over the absolute values of their terms: the size of the terms each
  * gradient component cancels, which bounds the rounding error a lower-precision
- * evaluation of that component can carry. */
+ * evaluation of that component can carry.  cone_adjoint (may be NULL; [M][3]) receives
+ * the derivative of L with respect to every cone's state (x, y, theta) at the start of the
+ * run: set against the loss's own derivative at the tips, it measures how strongly the run
+ * amplifies a perturbation of that cone. */
 int oracle_adjoint(const oracle_params* p, oracle_state* s, int64_t n_steps,
                    const int32_t* assign, const double* weight, double* loss,
-                   double* dL_dq, double* dL_dD, double* dL_dk, double* magnitude);
+                   double* dL_dq, double* dL_dD, double* dL_dk, double* magnitude,
+                   double* cone_adjoint);
 
 /* Adjacency list of the connections (a cone with status CONTACT links its owner neuron to
  * the owner of its target): row_start[n_neurons + 1] (V_a) and edges (E_a, capacity

@@ -1,8 +1,9 @@
 """Build the HIP library ``libcuesim.so`` for gfx950 in-tree.
 
 hipcc compiles every ``csrc/*.hip`` translation unit for the MI355X (gfx950) with packed
-FP32 instructions disabled and no fast-math, and links them with the host side of the C
-ABI into one shared library next to this file.
+FP32 instructions disabled and no fast-math, the system C++ compiler the host-only
+``csrc/*.cpp`` ones (parameter validation), and hipcc links them into one shared library
+next to this file.
 """
 import glob
 import os
@@ -23,8 +24,13 @@ HIPCC_FLAGS = [
 ]
 
 
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I", INCLUDE, "-I", CSRC]
+
+
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    """HIP translation units (device and host code) and plain host C++ ones."""
+    return (sorted(glob.glob(os.path.join(CSRC, "*.hip"))) +
+            sorted(glob.glob(os.path.join(CSRC, "*.cpp"))))
 
 
 def build(verbose=False, jobs=8):
@@ -36,7 +42,10 @@ def build(verbose=False, jobs=8):
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", src, "-o", obj]
+        if src.endswith(".cpp"):   # host-only code: the system C++ compiler
+            cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, "-c", src, "-o", obj]
+        else:
+            cmd = [hipcc, *HIPCC_FLAGS, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True)))

@@ -14,6 +14,7 @@
 
 #include "cuesim.h"
 #include "internal.hpp"
+#include "validate.hpp"
 #include "tiled.hpp"
 
 using namespace cuesim;
@@ -25,8 +26,6 @@ thread_local std::string g_create_error;
 // Steps between refreshes of the spatial order of 3D cones (a cone moves step_len per step;
 // 8, 16, 32 and 64 were measured at 256^3, 32 was fastest).
 constexpr int kOrderRefresh = 32;
-
-bool finite(double v) { return std::isfinite(v); }
 
 }  // namespace
 
@@ -243,91 +242,12 @@ sim_status nonfinite_fail(sim_handle* h) {
 
 int dir_width(int dim) { return dim == 2 ? 1 : 3; }
 
-// Validate the parameter struct.  Returns SIM_OK or an error with g_create_error set.
+// Validate the parameter struct (validate.cpp).  Returns SIM_OK or an error with
+// g_create_error set.
 sim_status validate(const sim_params* p) {
-    if (!p) return fail(nullptr, SIM_EINVAL, "params is NULL");
-    if (p->struct_size != sizeof(sim_params))
-        return fail(nullptr, SIM_EINVAL, "struct_size %u != sizeof(sim_params) %zu",
-                    p->struct_size, sizeof(sim_params));
-    if (p->dim != 2 && p->dim != 3) return fail(nullptr, SIM_EINVAL, "dim must be 2 or 3");
-    const int nz = p->dim == 3 ? p->nz : 1;
-    if (p->nx < 2 || p->ny < 2 || (p->dim == 3 && p->nz < 2))
-        return fail(nullptr, SIM_EINVAL, "every axis needs at least 2 cells");
-    const double cells = (double)p->nx * p->ny * nz;
-    if (cells > 2147483647.0) return fail(nullptr, SIM_EINVAL, "grid has more than 2^31-1 cells");
-    if (!finite(p->dx) || !finite(p->dt) || p->dx <= 0 || p->dt <= 0)
-        return fail(nullptr, SIM_EINVAL, "dx and dt must be finite and positive");
-    if (p->n_species < 1 || p->n_species > SIM_MAX_SPECIES)
-        return fail(nullptr, SIM_EINVAL, "n_species must be 1 or 2");
-    for (int s = 0; s < p->n_species; ++s) {
-        if (!finite(p->D[s]) || p->D[s] < 0 || !finite(p->k[s]) || p->k[s] < 0 ||
-            !finite(p->sign[s]))
-            return fail(nullptr, SIM_EINVAL, "species %d: D, k must be finite >= 0, sign finite", s);
-        const double r = p->D[s] * p->dt / (p->dx * p->dx);
-        if (r > 1.0 / (2.0 * p->dim))
-            return fail(nullptr, SIM_ECFL, "species %d: D dt / dx^2 = %g exceeds 1/(2 dim) = %g",
-                        s, r, 1.0 / (2.0 * p->dim));
-        if (2.0 * p->dim * r + p->k[s] * p->dt > 1.0)
-            return fail(nullptr, SIM_ECFL, "species %d: 2 dim r + k dt = %g exceeds 1", s,
-                        2.0 * p->dim * r + p->k[s] * p->dt);
-        if (p->n_sources[s] < 0 || (p->n_sources[s] > 0 && (!p->source_cell[s] || !p->source_q[s])))
-            return fail(nullptr, SIM_EINVAL, "species %d: bad source arrays", s);
-        for (int m = 0; m < p->n_sources[s]; ++m) {
-            if (p->source_cell[s][m] < 0 || (double)p->source_cell[s][m] >= cells)
-                return fail(nullptr, SIM_EINVAL, "species %d source %d: cell %d out of range", s,
-                            m, p->source_cell[s][m]);
-            if (!std::isfinite(p->source_q[s][m]))
-                return fail(nullptr, SIM_EINVAL, "species %d source %d: q not finite", s, m);
-        }
-        if (p->init_field[s])
-            for (int64_t x = 0; x < (int64_t)cells; ++x)
-                if (!std::isfinite(p->init_field[s][x]))
-                    return fail(nullptr, SIM_EINVAL, "species %d: init_field not finite", s);
-    }
-    if (p->n_cones < 0 || (p->n_cones > 0 && (!p->cone_pos || !p->cone_dir)))
-        return fail(nullptr, SIM_EINVAL, "bad cone arrays");
-    const double L[3] = {p->nx * p->dx, p->ny * p->dx, nz * p->dx};
-    for (int i = 0; i < p->n_cones; ++i) {
-        for (int a = 0; a < p->dim; ++a) {
-            const float v = p->cone_pos[(int64_t)i * p->dim + a];
-            if (!std::isfinite(v) || v < 0.0f || (double)v >= L[a])
-                return fail(nullptr, SIM_EINVAL, "cone %d: position outside the domain", i);
-        }
-        if (p->dim == 2) {
-            if (!std::isfinite(p->cone_dir[i]))
-                return fail(nullptr, SIM_EINVAL, "cone %d: heading not finite", i);
-        } else {
-            const float* h = p->cone_dir + (int64_t)i * 3;
-            const double n2 = (double)h[0] * h[0] + (double)h[1] * h[1] + (double)h[2] * h[2];
-            if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > 1e-3)
-                return fail(nullptr, SIM_EINVAL, "cone %d: heading is not a unit vector", i);
-        }
-    }
-    if (p->n_targets < 0 || (p->n_targets > 0 && !p->target_pos))
-        return fail(nullptr, SIM_EINVAL, "bad target arrays");
-    for (int64_t t = 0; t < (int64_t)p->n_targets * p->dim; ++t)
-        if (!std::isfinite(p->target_pos[t]))
-            return fail(nullptr, SIM_EINVAL, "target coordinates must be finite");
-    if (!finite(p->contact_radius) || p->contact_radius < 0 || !finite(p->step_len) ||
-        p->step_len < 0 || !finite(p->turn_gain) || !finite(p->max_turn) || p->max_turn < 0 ||
-        p->max_turn > M_PI || !finite(p->noise_sigma) || p->noise_sigma < 0)
-        return fail(nullptr, SIM_EINVAL,
-                    "contact_radius, step_len >= 0; max_turn in [0, pi]; noise_sigma >= 0");
-    if (p->block_steps < 0 || p->block_steps > 32)
-        return fail(nullptr, SIM_EINVAL, "block_steps must be in [0, 32]");
-    if (p->tile_cols_per_lane != 0 && p->tile_cols_per_lane != 2 && p->tile_cols_per_lane != 4)
-        return fail(nullptr, SIM_EINVAL, "tile_cols_per_lane must be 0, 2 or 4");
-    if (p->tile_height < 0 || p->tile_height > 4096)
-        return fail(nullptr, SIM_EINVAL, "tile_height must be in [0, 4096]");
-    if (p->turn_law != SIM_TURN_VECTOR && p->turn_law != SIM_TURN_SNR)
-        return fail(nullptr, SIM_EINVAL, "turn_law must be SIM_TURN_VECTOR or SIM_TURN_SNR");
-    if (p->turn_law == SIM_TURN_SNR &&
-        (p->dim != 2 || !finite(p->snr_scale) || !finite(p->cone_width) || p->cone_width < 0 ||
-         !finite(p->kd) || !(p->kd > 0) || !finite(p->c_min) || !finite(p->c_max) ||
-         !(p->c_min > 0) || p->c_max < p->c_min))
-        return fail(nullptr, SIM_EINVAL,
-                    "SNR turn law: 2D only; finite snr_scale, cone_width >= 0, kd > 0, "
-                    "0 < c_min <= c_max");
+    char msg[512];
+    const sim_status st = validate_params(p, msg, sizeof msg);
+    if (st != SIM_OK) return fail(nullptr, st, "%s", msg);
     return SIM_OK;
 }
 
