@@ -50,27 +50,41 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
     hist[tid * n_tiles + tile] = count[tid];
 }
 
-// Exclusive scan of a[0..n) in place by one workgroup: each thread sums a contiguous chunk,
-// the chunk sums are scanned in LDS, then each thread rewrites its chunk.
+// Exclusive scan of a[0..n) in place by one workgroup, kScanPer entries per thread at a
+// time: each thread loads its run of kScanPer consecutive entries into registers (all
+// loads issued before any is used), the run totals are scanned in LDS, and each thread
+// writes its run back; longer arrays take several such rounds, carrying the total.
+constexpr int kScanPer = 32;
+
 __global__ __launch_bounds__(kScanThreads) void k_sort_scan(int32_t* __restrict__ a, int n) {
     __shared__ int32_t part[kScanThreads];
-    const int per = (n + kScanThreads - 1) / kScanThreads;
-    const int lo = min((int)threadIdx.x * per, n), hi = min(lo + per, n);
-    int32_t sum = 0;
-    for (int v = lo; v < hi; ++v) sum += a[v];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int32_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __shared__ int32_t carry_in;
+    if (threadIdx.x == 0) carry_in = 0;
+    for (int base = 0; base < n; base += kScanThreads * kScanPer) {
+        const int lo = base + (int)threadIdx.x * kScanPer;
+        int32_t v[kScanPer];
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) v[u] = lo + u < n ? a[lo + u] : 0;
+        int32_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) sum += v[u];
+        part[threadIdx.x] = sum;
         __syncthreads();
-        part[threadIdx.x] += add;
+        for (int off = 1; off < kScanThreads; off <<= 1) {
+            const int32_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        int32_t at = carry_in + part[threadIdx.x] - sum;
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            if (lo + u < n) a[lo + u] = at;
+            at += v[u];
+        }
+        __syncthreads();   // every thread has read carry_in and part
+        if (threadIdx.x == kScanThreads - 1) carry_in = at;
         __syncthreads();
-    }
-    int32_t at = part[threadIdx.x] - sum;
-    for (int v = lo; v < hi; ++v) {
-        const int32_t t = a[v];
-        a[v] = at;
-        at += t;
     }
 }
 
