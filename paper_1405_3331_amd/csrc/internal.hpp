@@ -133,6 +133,34 @@ hipError_t launch_cones3d_ordered(const ConeRules& r, const float* f0, const flo
 // Tips and headings of the still-active ordered cones back into the caller-order arrays.
 hipError_t order3d_end(const ConeOrder3D& o, ConeArrays cones, hipStream_t stream);
 
+// Sample adjoints of one reverse step held as 64-bit fixed-point sums, so that the sum in a
+// cell does not depend on the order in which the cones' contributions arrive (integer
+// addition is associative): value = q * 2^(e - kFixedBits), where 2^e bounds the step's
+// largest |contribution| (step_max[t] holds its FP32 bits, 0 for a step without any).
+// Every contribution is at most 2^kFixedBits in magnitude after scaling, so up to
+// 2^(62 - kFixedBits) of them can meet in one cell without overflow.
+constexpr int kFixedBits = 40;
+
+__device__ __forceinline__ int fixed_exponent(uint32_t max_bits) {
+    if (max_bits == 0u) return 0;
+    int e;
+    (void)frexpf(__uint_as_float(max_bits), &e);   // max = f 2^e, 0.5 <= f < 1
+    return e;
+}
+
+struct FixedStep {
+    const long long* q;   // one species' sums of the step, one per cell
+    double inv;           // 2^(e - kFixedBits)
+    __device__ __forceinline__ float operator[](size_t x) const {
+        return (float)((double)q[x] * inv);
+    }
+};
+
+__device__ __forceinline__ FixedStep fixed_step(const long long* q, const uint32_t* step_max,
+                                                int t) {
+    return FixedStep{q, ldexp(1.0, fixed_exponent(step_max[t]) - kFixedBits)};
+}
+
 // Reverse pass of the 2D step (kernels_adjoint.hip).  Field adjoint grids have
 // adjoint_field_blocks(nx, ny) workgroups, each owning one slot of acc_D / acc_k.
 // A segment's fields are `fields + (t * n_species + s) * cells` for t = 0..len.
@@ -147,28 +175,39 @@ hipError_t launch_cones_segments2d(const ConeRules& rules, const float* fields, 
                                    int every, int n_steps, uint32_t n0, const float* ckpt_pos,
                                    const float* ckpt_dir, const int32_t* ckpt_int, int M,
                                    float4* tape, hipStream_t stream);
+// Reverse of a segment's cone steps: each cone's gradient samples' adjoints (12 cells per
+// species and step) are written to the segment's records, rec_at / rec_v
+// [len][n][n_species][12]; then the largest |contribution| of every step goes to
+// step_max[len] (cleared by the call) and the records are added into the fixed-point sums
+// e[len][n_species][cells] (cleared by the call) with that step's scale.
 hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fields,
                                          size_t cells, int n_species, uint32_t seg0, int len,
-                                         float* e, const float4* tape, const int32_t* status,
-                                         const int32_t* event_step, float* acone, int n,
-                                         hipStream_t stream);
-hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* e_in,
-                                  const float* c, float* a_out, StencilCoef coef, double* acc_D,
-                                  double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
+                                         int32_t* rec_at, float* rec_v, uint32_t* step_max,
+                                         long long* e, const float4* tape,
+                                         const int32_t* status, const int32_t* event_step,
+                                         float* acone, int n, hipStream_t stream);
+// One reverse field step with the sample adjoints of step t: e + (t * n_species) * cells
+// holds the species' fixed-point sums (e points at this species' first step).
+hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const long long* e_in,
+                                  const uint32_t* step_max, int t, const float* c,
+                                  float* a_out, StencilCoef coef, double* acc_D, double* acc_k,
+                                  const int32_t* q_cell, int n_q, double* acc_q,
                                   hipStream_t stream);
-// Two reverse steps per launch (n, then n - 1): a_in = a^{n+1}, e1/e0 = e^{n+1}/e^n,
+// Two reverse steps per launch (n, then n - 1): a_in = a^{n+1}, e1/e0 = e^{n+1}/e^n (the
+// fixed-point sums of segment steps t1 / t0),
 // c1/c0 = c^n/c^{n-1}, a_out = a^{n-1}; adjoint_pair_blocks(nx, ny) boxes own acc_D/acc_k
 // slots, and the sources are listed per box (adjoint_pair_sources: q_start[box] ..
 // q_start[box + 1] - 1 index q_index, the source numbers m of q_cell / acc_q).
 int adjoint_pair_blocks(int nx, int ny);
 void adjoint_pair_sources(int nx, int ny, const std::vector<int32_t>& cells,
                           std::vector<int32_t>& start, std::vector<int32_t>& index);
-hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const float* e1,
-                                       const float* e0, const float* c1, const float* c0,
-                                       float* a_out, StencilCoef coef, double* acc_D,
-                                       double* acc_k, const int32_t* q_start,
-                                       const int32_t* q_index, const int32_t* q_cell,
-                                       double* acc_q, hipStream_t stream);
+hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const long long* e1,
+                                       const long long* e0, const uint32_t* step_max, int t1,
+                                       int t0, const float* c1, const float* c0, float* a_out,
+                                       StencilCoef coef, double* acc_D, double* acc_k,
+                                       const int32_t* q_start, const int32_t* q_index,
+                                       const int32_t* q_cell, double* acc_q,
+                                       hipStream_t stream);
 hipError_t launch_adjoint_seed2d(const float* pos, const float* tip_target, const float* weight,
                                  float* acone, double* partial, int n, hipStream_t stream);
 

@@ -13,8 +13,13 @@
 //                             once, one thread per segment and cone);
 //   k_cone_adjoint_segment2d  walks the steps backwards carrying each cone's adjoint of
 //                             (p, theta) through advance, capped turn and interpolated
-//                             gradient; the gradient samples' adjoints are scattered into
-//                             e^{n+1}, one buffer per step (12 cells per species per cone);
+//                             gradient, and records its gradient samples' adjoints (12
+//                             cells and values per species, cone and step);
+//   k_sample_max, k_sample_add  add the records of every step into e^{n+1}, one buffer of
+//                             64-bit fixed-point sums per step and species, scaled by the
+//                             step's largest contribution: integer additions, so the sums
+//                             (and the whole gradient) do not depend on the order in which
+//                             the cones' contributions arrive;
 //   k_field_adjoint2d_rows    (kernels_field2d.hip) one launch per step: with
 //                             b = a^{n+1} + e^{n+1}, a^n = b + r Lap b - k dt b (the
 //                             zero-flux Laplacian is symmetric, so the adjoint stencil is
@@ -22,8 +27,6 @@
 //                             per-workgroup FP64 sums of b Lap c^n (for dL/dD) and b c^n (for
 //                             dL/dk) plus b at every source cell (dL/dq).
 // HBM bytes per cell of the reverse field step: a^{n+1}, e^{n+1} and c^n read, a^n written.
-#include <type_traits>
-
 #include "internal.hpp"
 
 namespace cuesim {
@@ -53,9 +56,14 @@ struct Scatter2D {
     float v[12];
 };
 
-__device__ __forceinline__ void scatter_add(float* __restrict__ af, const Scatter2D& s) {
+// Record of one sample's adjoints: rec_at / rec_v + ((t * n + i) * n_species + s) * 12.
+__device__ __forceinline__ void write_record(int32_t* __restrict__ at, float* __restrict__ v,
+                                             const Scatter2D& s) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) atomicAdd(&af[s.at[k]], s.v[k]);
+    for (int k = 0; k < 12; k += 4) {
+        *(int4*)(at + k) = make_int4(s.at[k], s.at[k + 1], s.at[k + 2], s.at[k + 3]);
+        *(float4*)(v + k) = make_float4(s.v[k], s.v[k + 1], s.v[k + 2], s.v[k + 3]);
+    }
 }
 
 // Reverse of the interpolated central-difference gradient of one species at (x, y), from
@@ -249,30 +257,30 @@ __global__ __launch_bounds__(kSegThreads) void k_cones_segments2d(ConeRules r, S
     }
 }
 
-// Reverse of one segment's cone steps, one thread per cone from the last step to the first.
-// status/event_step are the final ones of the run: a cone stopped at step n takes part in
-// steps < n only.  The adjoint of the sample of step t goes to e + t * n_species * cells.
+// Last step of a segment (from step seg0, len steps) in which cone i takes part: status and
+// event_step are the run's final ones, and a cone stopped at step n takes part in steps < n
+// only (-1: none of the segment's).
+__device__ __forceinline__ int last_step(const Segment2D& seg, const int32_t* status,
+                                         const int32_t* event_step, int i) {
+    const int64_t last = status[i] == kActive ? INT64_MAX : (int64_t)event_step[i];
+    return (int)max<int64_t>(min<int64_t>(seg.len - 1, last - 1 - (int64_t)seg.seg0), -1);
+}
+
+// Reverse of one segment's cone steps, one thread per cone from the last step to the first;
+// the adjoints of step t's gradient samples are recorded (write_record) for k_sample_add.
+// The state of the step before is loaded one step ahead.
 template <int NS>
 __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
-    ConeRules r, Segment2D seg, float* __restrict__ e, const float4* __restrict__ tape,
-    const int32_t* __restrict__ status, const int32_t* __restrict__ event_step,
-    float* __restrict__ acone, int n) {
+    ConeRules r, Segment2D seg, int32_t* __restrict__ rec_at, float* __restrict__ rec_v,
+    const float4* __restrict__ tape, const int32_t* __restrict__ status,
+    const int32_t* __restrict__ event_step, float* __restrict__ acone, int n) {
     const int i = blockIdx.x * kSegThreads + threadIdx.x;
     if (i >= n) return;
-    // steps < last take part (all steps when the cone is still active)
-    const int64_t last = status[i] == kActive ? INT64_MAX : (int64_t)event_step[i];
     float apx = acone[3 * i], apy = acone[3 * i + 1], ath = acone[3 * i + 2];
-    // steps t <= t_hi take part; the state of the step before is loaded one step ahead, and
-    // a step's scatter is issued once the next step's samples have arrived, so no load waits
-    // on the scatter's atomics
-    const int t_hi = (int)min<int64_t>(seg.len - 1, last - 1 - (int64_t)seg.seg0);
+    const int t_hi = last_step(seg, status, event_step, i);
     if (t_hi >= 0) {
         float4 st = tape[(size_t)t_hi * n + i];
-        Scatter2D pending[NS];
-        float* pending_to = nullptr;
-        // one reverse step; FLUSH: first issue the previous step's scatter (every step but
-        // the first has one, so the loop body below has no branch on it)
-        auto reverse_step = [&](int t, auto flush) {
+        for (int t = t_hi; t >= 0; --t) {
             const float4 next = tape[(size_t)max(t - 1, 0) * n + i];
             const Footprint2D p0 =
                 footprint_2d(Field2D{seg.field(t + 1, 0), r.nx}, r, st.x, st.y);
@@ -282,26 +290,69 @@ __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
             CornerGradients2D g0, g1;
             float gx, gy;
             sample_2d<NS>(r, p0, p1, g0, g1, gx, gy);
-            if (decltype(flush)::value) {
-                // an empty barrier that needs the sampled gradient: the scatter is issued
-                // only after the samples have arrived (else its atomics join the load waits)
-                asm volatile("" ::"v"(gx), "v"(gy) : "memory");
-                scatter_add(pending_to, pending[0]);
-                if (NS > 1) scatter_add(pending_to + seg.cells, pending[NS - 1]);
-            }
+            Scatter2D out[NS];
             cone_adjoint_step<NS>(r, p0, p1, g0, g1, gx, gy, st, i, seg.seg0 + (uint32_t)t,
-                                  apx, apy, ath, pending);
-            pending_to = e + (size_t)t * seg.n_species * seg.cells;
+                                  apx, apy, ath, out);
+            const size_t rec = (((size_t)t * n + i) * NS) * 12;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) write_record(rec_at + rec + s * 12, rec_v + rec + s * 12,
+                                                      out[s]);
             st = next;
-        };
-        reverse_step(t_hi, std::false_type{});
-        for (int t = t_hi - 1; t >= 0; --t) reverse_step(t, std::true_type{});
-        scatter_add(pending_to, pending[0]);
-        if (NS > 1) scatter_add(pending_to + seg.cells, pending[NS - 1]);
+        }
     }
     acone[3 * i] = apx;
     acone[3 * i + 1] = apy;
     acone[3 * i + 2] = ath;
+}
+
+constexpr int kRecThreads = 256;
+
+// Largest |contribution| of every step of the segment: one thread per (cone, step), a
+// wavefront maximum, then one atomic maximum on the step's FP32 bits (non-negative floats
+// order like their bits) per wavefront.
+template <int NS>
+__global__ __launch_bounds__(kRecThreads) void k_sample_max(
+    Segment2D seg, const float* __restrict__ rec_v, const int32_t* __restrict__ status,
+    const int32_t* __restrict__ event_step, uint32_t* __restrict__ step_max, int n) {
+    const int i = blockIdx.x * kRecThreads + threadIdx.x;
+    const int t = blockIdx.y;
+    float m = 0.0f;
+    if (i < n && t <= last_step(seg, status, event_step, i)) {
+        const float4* v = (const float4*)(rec_v + (((size_t)t * n + i) * NS) * 12);
+#pragma unroll
+        for (int k = 0; k < 3 * NS; ++k) {
+            const float4 q = v[k];
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w))));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(&step_max[t], __float_as_uint(m));
+}
+
+// Every (cone, step) record added into the step's fixed-point sums: q = rint(v 2^(40 - e))
+// (the product is an exact power-of-two scaling in FP64), |q| <= 2^40.
+template <int NS>
+__global__ __launch_bounds__(kRecThreads) void k_sample_add(
+    Segment2D seg, const int32_t* __restrict__ rec_at, const float* __restrict__ rec_v,
+    const int32_t* __restrict__ status, const int32_t* __restrict__ event_step,
+    const uint32_t* __restrict__ step_max, unsigned long long* __restrict__ e, int n) {
+    const int i = blockIdx.x * kRecThreads + threadIdx.x;
+    const int t = blockIdx.y;
+    if (i >= n || t > last_step(seg, status, event_step, i)) return;
+    const double scale = ldexp(1.0, kFixedBits - fixed_exponent(step_max[t]));
+    const size_t rec = (((size_t)t * n + i) * NS) * 12;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        unsigned long long* dst = e + ((size_t)t * NS + s) * seg.cells;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double x = (double)rec_v[rec + s * 12 + k] * scale;
+            // (a non-finite contribution, possible only from non-finite fields, adds nothing
+            // rather than an undefined conversion)
+            const long long q = isfinite(x) ? (long long)rint(x) : 0;
+            if (q != 0) atomicAdd(dst + rec_at[rec + s * 12 + k], (unsigned long long)q);
+        }
+    }
 }
 
 // Loss at the final tips and the seed of the cone adjoints: a_p = 2 w (p - t), a_theta = 0.
@@ -349,18 +400,36 @@ hipError_t launch_cones_segments2d(const ConeRules& rules, const float* fields, 
 
 hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fields,
                                          size_t cells, int n_species, uint32_t seg0, int len,
-                                         float* e, const float4* tape, const int32_t* status,
-                                         const int32_t* event_step, float* acone, int n,
-                                         hipStream_t stream) {
-    if (n == 0 || len == 0) return hipSuccess;
+                                         int32_t* rec_at, float* rec_v, uint32_t* step_max,
+                                         long long* e, const float4* tape,
+                                         const int32_t* status, const int32_t* event_step,
+                                         float* acone, int n, hipStream_t stream) {
+    if (len == 0) return hipSuccess;
+    hipError_t err = hipMemsetAsync(e, 0, sizeof(long long) * (size_t)len * n_species * cells,
+                                    stream);
+    if (err != hipSuccess || n == 0) return err;
+    if ((err = hipMemsetAsync(step_max, 0, sizeof(uint32_t) * (size_t)len, stream)) !=
+        hipSuccess)
+        return err;
     const Segment2D seg{fields, cells, n_species, seg0, len};
     const dim3 grid((n + kSegThreads - 1) / kSegThreads);
-    if (n_species > 1)
+    const dim3 rec_grid((n + kRecThreads - 1) / kRecThreads, len);
+    unsigned long long* eu = (unsigned long long*)e;
+    if (n_species > 1) {
         hipLaunchKernelGGL(k_cone_adjoint_segment2d<2>, grid, dim3(kSegThreads), 0, stream,
-                           rules, seg, e, tape, status, event_step, acone, n);
-    else
+                           rules, seg, rec_at, rec_v, tape, status, event_step, acone, n);
+        hipLaunchKernelGGL(k_sample_max<2>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
+                           status, event_step, step_max, n);
+        hipLaunchKernelGGL(k_sample_add<2>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_at,
+                           rec_v, status, event_step, step_max, eu, n);
+    } else {
         hipLaunchKernelGGL(k_cone_adjoint_segment2d<1>, grid, dim3(kSegThreads), 0, stream,
-                           rules, seg, e, tape, status, event_step, acone, n);
+                           rules, seg, rec_at, rec_v, tape, status, event_step, acone, n);
+        hipLaunchKernelGGL(k_sample_max<1>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
+                           status, event_step, step_max, n);
+        hipLaunchKernelGGL(k_sample_add<1>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_at,
+                           rec_v, status, event_step, step_max, eu, n);
+    }
     return hipGetLastError();
 }
 

@@ -130,7 +130,8 @@ __device__ double block_sum_fp64(double v) {
 // Reverse step of one species; box b of the launch owns acc_D[b] and acc_k[b].  Box 0 also
 // adds b at every source cell into acc_q.
 __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
-    const float* __restrict__ a_in, const float* __restrict__ e_in, const float* __restrict__ c,
+    const float* __restrict__ a_in, const long long* __restrict__ e_q,
+    const uint32_t* __restrict__ step_max, int t, const float* __restrict__ c,
     float* __restrict__ a_out, int nx, int ny, int tx, int ty, int per_xcd, StencilCoef k,
     double* __restrict__ acc_D, double* __restrict__ acc_k, const int32_t* __restrict__ q_cell,
     int n_q, double* __restrict__ acc_q) {
@@ -138,10 +139,11 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
     if (box >= tx * ty) return;   // whole workgroup: the barriers below stay uniform
     const int bx = box % tx, by = box / tx;
     const int i = bx * kRX + threadIdx.x;
+    const FixedStep e_in = fixed_step(e_q, step_max, t);
     double pD = 0.0, pk = 0.0;
     if (i < nx) {
         const float* ca = a_in + i;
-        const float* ce = e_in + i;
+        const FixedStep ce{e_in.q + i, e_in.inv};
         const float* cc = c + i;
         float* dst = a_out + i;
         const int dw = i > 0 ? -1 : 0, de = i < nx - 1 ? 1 : 0;
@@ -313,8 +315,10 @@ __global__ __launch_bounds__(kRX) void k_field2d_pair(Field2DPairArgs a) {
 // exactly those of the single step.
 struct FieldAdjointPairArgs {
     const float* a_in;    // a^{n+1}
-    const float* e1;      // e^{n+1}
-    const float* e0;      // e^n
+    const long long* e1;  // e^{n+1}, fixed-point sums of segment step t1
+    const long long* e0;  // e^n, of segment step t0
+    const uint32_t* step_max;
+    int t1, t0;
     const float* c1;      // c^n
     const float* c0;      // c^{n-1}
     float* a_out;         // a^{n-1}
@@ -355,6 +359,8 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairAr
     const int xi = min(max(x0 - 2 + xcol, 0), nx - 1);
     const int ri = tid == 0 ? x0 - 1 : x0 + kRX;             // ring column, threads 0, 1
     const int rci = min(max(ri, 0), nx - 1);
+    const FixedStep e1 = fixed_step(a.e1, a.step_max, a.t1);
+    const FixedStep e0 = fixed_step(a.e0, a.step_max, a.t0);
     float va[kPH], ve[kPH], xa[kPH], xe[kPH];
     float en[kQH], xen[kQH], c1v[kQH], c0v[kQH];
     float c1w[kPY], c1e[kPY], c0w[kPY], c0e[kPY];
@@ -362,21 +368,21 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairAr
     for (int u = 0; u < kPH; ++u) {
         const size_t at = (size_t)brow[u] * nx;
         va[u] = a.a_in[at + ci];
-        ve[u] = a.e1[at + ci];
+        ve[u] = e1[at + ci];
     }
     if (tid < 4) {
 #pragma unroll
         for (int u = 0; u < kPH; ++u) {
             const size_t at = (size_t)brow[u] * nx;
             xa[u] = a.a_in[at + xi];
-            xe[u] = a.e1[at + xi];
+            xe[u] = e1[at + xi];
         }
     }
 #pragma unroll
-    for (int r = 0; r < kQH; ++r) en[r] = a.e0[(size_t)brow[r + 1] * nx + ci];
+    for (int r = 0; r < kQH; ++r) en[r] = e0[(size_t)brow[r + 1] * nx + ci];
     if (tid < 2) {
 #pragma unroll
-        for (int r = 0; r < kQH; ++r) xen[r] = a.e0[(size_t)brow[r + 1] * nx + rci];
+        for (int r = 0; r < kQH; ++r) xen[r] = e0[(size_t)brow[r + 1] * nx + rci];
     }
 #pragma unroll
     for (int r = 0; r < kQH; ++r) {
@@ -657,17 +663,21 @@ void adjoint_pair_sources(int nx, int ny, const std::vector<int32_t>& cells,
     start[nb] = (int32_t)index.size();
 }
 
-hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const float* e1,
-                                       const float* e0, const float* c1, const float* c0,
-                                       float* a_out, StencilCoef coef, double* acc_D,
-                                       double* acc_k, const int32_t* q_start,
-                                       const int32_t* q_index, const int32_t* q_cell,
-                                       double* acc_q, hipStream_t stream) {
+hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const long long* e1,
+                                       const long long* e0, const uint32_t* step_max, int t1,
+                                       int t0, const float* c1, const float* c0, float* a_out,
+                                       StencilCoef coef, double* acc_D, double* acc_k,
+                                       const int32_t* q_start, const int32_t* q_index,
+                                       const int32_t* q_cell, double* acc_q,
+                                       hipStream_t stream) {
     const Tiles2D t = tiles_for(nx, ny, kPY);
     FieldAdjointPairArgs a{};
     a.a_in = a_in;
     a.e1 = e1;
     a.e0 = e0;
+    a.step_max = step_max;
+    a.t1 = t1;
+    a.t0 = t0;
     a.c1 = c1;
     a.c0 = c0;
     a.a_out = a_out;
@@ -688,15 +698,16 @@ hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const 
     return hipGetLastError();
 }
 
-hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const float* e_in,
-                                  const float* c, float* a_out, StencilCoef coef, double* acc_D,
-                                  double* acc_k, const int32_t* q_cell, int n_q, double* acc_q,
+hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const long long* e_in,
+                                  const uint32_t* step_max, int t, const float* c,
+                                  float* a_out, StencilCoef coef, double* acc_D, double* acc_k,
+                                  const int32_t* q_cell, int n_q, double* acc_q,
                                   hipStream_t stream) {
-    const Tiles2D t = tiles_for(nx, ny, kAY);
-    const int per_xcd = (t.tx * t.ty + kXcds - 1) / kXcds;
+    const Tiles2D tl = tiles_for(nx, ny, kAY);
+    const int per_xcd = (tl.tx * tl.ty + kXcds - 1) / kXcds;
     hipLaunchKernelGGL(k_field_adjoint2d_rows, dim3(per_xcd * kXcds), dim3(kRX), 0, stream,
-                       a_in, e_in, c, a_out, nx, ny, t.tx, t.ty, per_xcd, coef, acc_D, acc_k,
-                       q_cell, n_q, acc_q);
+                       a_in, e_in, step_max, t, c, a_out, nx, ny, tl.tx, tl.ty, per_xcd, coef,
+                       acc_D, acc_k, q_cell, n_q, acc_q);
     return hipGetLastError();
 }
 

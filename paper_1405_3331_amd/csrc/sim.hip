@@ -1137,7 +1137,10 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     const int64_t window = whole ? n_run : K;
     float* tape = nullptr;
     float4* tape_cones = nullptr;
-    float* scatter = nullptr;
+    long long* scatter = nullptr;   // fixed-point sample adjoints [K][species][cells]
+    int32_t* rec_at = nullptr;      // one segment's sample records [K][M][species][12]
+    float* rec_v = nullptr;
+    uint32_t* step_max = nullptr;   // [K]
     float* afield = nullptr;
     double* acc = nullptr;
     int32_t* q_cell = nullptr;
@@ -1147,6 +1150,9 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         dfree(tape);
         dfree(tape_cones);
         dfree(scatter);
+        dfree(rec_at);
+        dfree(rec_v);
+        dfree(step_max);
         dfree(afield);
         dfree(acc);
         dfree(q_cell);
@@ -1169,6 +1175,9 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     if ((e = dalloc(&tape, (size_t)(window + 1) * ns * cells)) != hipSuccess ||
         (e = dalloc(&tape_cones, (size_t)window * std::max<size_t>(Ms, 1))) != hipSuccess ||
         (e = dalloc(&scatter, (size_t)K * ns * cells)) != hipSuccess ||
+        (e = dalloc(&rec_at, (size_t)K * std::max<size_t>(Ms, 1) * ns * 12)) != hipSuccess ||
+        (e = dalloc(&rec_v, (size_t)K * std::max<size_t>(Ms, 1) * ns * 12)) != hipSuccess ||
+        (e = dalloc(&step_max, (size_t)K)) != hipSuccess ||
         (e = dalloc(&afield, (size_t)2 * ns * cells)) != hipSuccess ||
         (e = dalloc(&acc, acc_n)) != hipSuccess ||
         (e = dalloc(&q_cell, (size_t)std::max(nq_all, 1))) != hipSuccess ||
@@ -1246,10 +1255,10 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
             t_base = t0;
             ADJ_TRY(rerun(j, t0, len, 1));
         }
-        // the segment's cone adjoints, scattering the samples' adjoints per step
-        ADJ_TRY(hipMemsetAsync(scatter, 0, (size_t)len * ns * cells * sizeof(float), h->stream));
+        // the segment's cone adjoints, their samples' adjoints summed per step and cell
         ADJ_TRY(launch_cone_adjoint_segment2d(h->rules, field_at(t0, 0), cells, ns,
-                                              (uint32_t)(a->n0 + t0), len, scatter,
+                                              (uint32_t)(a->n0 + t0), len, rec_at, rec_v,
+                                              step_max, scatter,
                                               tape_cones + (size_t)(t0 - t_base) * Ms,
                                               h->cones.status, h->cones.event_step, a->acone,
                                               M, h->stream));
@@ -1258,8 +1267,8 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         for (; t >= 1; t -= 2) {
             for (int s = 0; s < ns; ++s)
                 ADJ_TRY(launch_field_adjoint2d_pair(
-                    nx, ny, afield_at(s, cur), scatter_at(t, s), scatter_at(t - 1, s),
-                    field_at(t0 + t, s), field_at(t0 + t - 1, s), afield_at(s, cur ^ 1),
+                    nx, ny, afield_at(s, cur), scatter_at(t, s), scatter_at(t - 1, s), step_max,
+                    t, t - 1, field_at(t0 + t, s), field_at(t0 + t - 1, s), afield_at(s, cur ^ 1),
                     h->coef[s], acc_D + (size_t)s * fb, acc_k + (size_t)s * fb,
                     q_start + (size_t)s * (nbp + 1), q_index, q_cell + q_off[s],
                     acc_q + q_off[s], h->stream));
@@ -1268,7 +1277,8 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         if (t == 0) {
             for (int s = 0; s < ns; ++s)
                 ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), scatter_at(t, s),
-                                               field_at(t0 + t, s), afield_at(s, cur ^ 1),
+                                               step_max, t, field_at(t0 + t, s),
+                                               afield_at(s, cur ^ 1),
                                                h->coef[s], acc_D + (size_t)s * fb,
                                                acc_k + (size_t)s * fb, q_cell + q_off[s],
                                                n_q[s], acc_q + q_off[s], h->stream));
