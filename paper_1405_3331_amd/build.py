@@ -1,9 +1,11 @@
 """Build the HIP library ``libcuesim.so`` for gfx950 in-tree.
 
 hipcc compiles every ``csrc/*.hip`` translation unit for the MI355X (gfx950) with packed
-FP32 instructions disabled and no fast-math, the system C++ compiler the host-only
-``csrc/*.cpp`` ones (parameter validation), and hipcc links them into one shared library
-next to this file.
+FP32 instructions disabled, no fast-math and no floating-point contraction: every fused
+multiply-add is an explicit ``fmaf`` in the source, so an expression rounds the same way in
+every kernel it is inlined into and the per-step, tiled and batched paths agree bit for
+bit.  The system C++ compiler builds the host-only ``csrc/*.cpp`` ones (parameter
+validation), and hipcc links them into one shared library next to this file.
 """
 import glob
 import os
@@ -19,7 +21,7 @@ ARCH = "gfx950"
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
-    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

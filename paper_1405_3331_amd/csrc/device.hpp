@@ -37,19 +37,79 @@ __device__ __forceinline__ float unit_open(uint32_t x) {
     return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;
 }
 
+// ------------------------------------------------------------------------------------
+// sin and cos on a reduced argument |a| <= pi/4 (with a little slack): the Taylor series to
+// a^9 and a^10, whose truncation errors (below 1.8e-9 and 1.2e-10 at pi/4) lie far under
+// FP32 rounding, in Horner form.  Only fma, mul and add, so every kernel (and a host build)
+// gets the same bits.
+// ------------------------------------------------------------------------------------
+constexpr double kPiD = 3.14159265358979323846;
+
+__host__ __device__ __forceinline__ void sincos_reduced(float a, float& s, float& c) {
+    const float a2 = a * a;
+    float p = fmaf(a2, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
+    p = fmaf(a2, p, (float)(1.0 / 120.0));
+    p = fmaf(a2, p, (float)(-1.0 / 6.0));
+    s = fmaf(a * a2, p, a);
+    float q = fmaf(a2, (float)(-1.0 / 3628800.0), (float)(1.0 / 40320.0));
+    q = fmaf(a2, q, (float)(-1.0 / 720.0));
+    q = fmaf(a2, q, (float)(1.0 / 24.0));
+    q = fmaf(a2, q, -0.5f);
+    c = fmaf(a2, q, 1.0f);
+}
+
+// Rotate (s, c) = (sin a, cos a) by j quarter turns: the sine and cosine of a + j pi / 2.
+__host__ __device__ __forceinline__ void quarter_turns(float j, float& s, float& c) {
+    const int q = (int)j & 3;
+    const float s0 = (q & 1) ? c : s, c0 = (q & 1) ? s : c;
+    s = (q & 2) ? -s0 : s0;
+    c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// sin and cos of an angle in radians, |th| up to a few turns (headings are kept in
+// [-pi, pi)): j = rint(2 th / pi) quarter turns are taken off with pi / 2 split in two FP32
+// parts (Cody and Waite), leaving |a| <= pi / 4.
+__host__ __device__ __forceinline__ void sincos_angle(float th, float& s, float& c) {
+    constexpr float kHalfPiHi = (float)(kPiD / 2.0);
+    constexpr float kHalfPiLo = (float)(kPiD / 2.0 - (double)(float)(kPiD / 2.0));
+    const float j = rintf(th * (float)(2.0 / kPiD));
+    float a = fmaf(-j, kHalfPiHi, th);
+    a = fmaf(-j, kHalfPiLo, a);
+    sincos_reduced(a, s, c);
+    quarter_turns(j, s, c);
+}
+
+// sin and cos of 2 pi u for u in (0, 1]: 4u = j + 2 r with j = rint(4u) exactly, and
+// r = 2u - j / 2 in [-1/4, 1/4] exact as well (j / 2 is a multiple of a coarser power of two
+// than 2u), so the only rounding before the series is that of a = pi r.
+__host__ __device__ __forceinline__ void sincos_turn(float u, float& s, float& c) {
+    const float t = 2.0f * u;
+    const float j = rintf(2.0f * t);
+    const float r = fmaf(-0.5f, j, t);
+    sincos_reduced((float)kPiD * r, s, c);
+    quarter_turns(j, s, c);
+}
+
+// One Box-Muller pair from two Philox words: radius sqrt(-2 ln u0) from the first uniform,
+// angle 2 pi u1 from the second.  u0 lies in [2^-24, 1), a normal number, and -2 ln u0 in
+// (1e-7, 34), so the hardware base-2 logarithm and square root (about one ulp each) need no
+// range scaling.
+__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, float& z0, float& z1) {
+    const float r = __builtin_amdgcn_sqrtf((float)(-2.0 * 0.69314718055994530942) *
+                                           __builtin_amdgcn_logf(unit_open(w0)));
+    float s, c;
+    sincos_turn(unit_open(w1), s, c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
 struct NoiseKey {
     uint32_t k0, k1;       // seed low / high word
     uint32_t sim_index;    // fourth counter word
 };
 
-// One Box-Muller pair from two Philox words: radius from the first uniform, angle from
-// the second.
 __device__ __forceinline__ void normal_pair(uint32_t w0, uint32_t w1, float* z) {
-    float s, c;
-    const float r = sqrtf(-2.0f * logf(unit_open(w0)));
-    sincospif(2.0f * unit_open(w1), &s, &c);
-    z[0] = r * c;
-    z[1] = r * s;
+    box_muller(w0, w1, z[0], z[1]);
 }
 
 // 2D draws at most two deviates per step, so one Philox block, counter
@@ -74,17 +134,12 @@ template <int count>
 __device__ __forceinline__ void normals(const NoiseKey& key, uint32_t cone, uint32_t step,
                                         float* z) {
     const uint4 x = philox4x32_10(make_uint4(cone, step, 0u, key.sim_index), key.k0, key.k1);
-    float s, c;
-    const float r0 = sqrtf(-2.0f * logf(unit_open(x.x)));
-    sincospif(2.0f * unit_open(x.y), &s, &c);
-    z[0] = r0 * c;
-    if (count > 1) z[1] = r0 * s;
+    float z1, z3;
+    box_muller(x.x, x.y, z[0], z1);
+    if (count > 1) z[1] = z1;
     if (count > 2) {
-        const float r1 = sqrtf(-2.0f * logf(unit_open(x.z)));
-        float s1, c1;
-        sincospif(2.0f * unit_open(x.w), &s1, &c1);
-        z[2] = r1 * c1;
-        if (count > 3) z[3] = r1 * s1;
+        box_muller(x.z, x.w, z[2], z3);
+        if (count > 3) z[3] = z3;
     }
 }
 
@@ -111,6 +166,13 @@ __device__ __forceinline__ void closer(float d2, int idx, float& best_d2, int& b
     }
 }
 
+// Squared distance of an offset (dz unused in 2D).
+template <int dim>
+__device__ __forceinline__ float dist2(float dx, float dy, float dz) {
+    const float d2 = fmaf(dy, dy, dx * dx);
+    return dim == 3 ? fmaf(dz, dz, d2) : d2;
+}
+
 // Nearest target in a list (x, y, z, original index as bits), same rule as below.
 template <int dim>
 __device__ __forceinline__ int contact_in_list(const float4* pts, int n, float r2, float x,
@@ -119,13 +181,7 @@ __device__ __forceinline__ int contact_in_list(const float4* pts, int n, float r
     int best = -1;
     for (int k = 0; k < n; ++k) {
         const float4 t = pts[k];
-        const float ddx = x - t.x, ddy = y - t.y;
-        float d2 = ddx * ddx + ddy * ddy;
-        if (dim == 3) {
-            const float ddz = z - t.z;
-            d2 += ddz * ddz;
-        }
-        closer(d2, __float_as_int(t.w), best_d2, best);
+        closer(dist2<dim>(x - t.x, y - t.y, z - t.z), __float_as_int(t.w), best_d2, best);
     }
     return best;
 }
@@ -161,13 +217,8 @@ __device__ __forceinline__ int contact_target(const TargetGrid& tg, float x, flo
             const int hi = tg.cell_start[row + x_hi + 1];
             for (int k = lo; k < hi; ++k) {
                 const float4 t = tg.pts[k];
-                const float ddx = x - t.x, ddy = y - t.y;
-                float d2 = ddx * ddx + ddy * ddy;
-                if (dim == 3) {
-                    const float ddz = z - t.z;
-                    d2 += ddz * ddz;
-                }
-                closer(d2, __float_as_int(t.w), best_d2, best);
+                closer(dist2<dim>(x - t.x, y - t.y, z - t.z), __float_as_int(t.w), best_d2,
+                       best);
             }
         }
     return best;
@@ -265,10 +316,10 @@ __device__ __forceinline__ void gradient_from_2d(const Footprint2D& p,
     const float fx = p.fx, fy = p.fy;
     const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy);
     const float w01 = (1.0f - fx) * fy, w11 = fx * fy;
-    gx = w00 * g.gx00 + w10 * g.gx10 + w01 * g.gx01 + w11 * g.gx11;
-    gy = w00 * g.gy00 + w10 * g.gy10 + w01 * g.gy01 + w11 * g.gy11;
+    gx = fmaf(w11, g.gx11, fmaf(w01, g.gx01, fmaf(w10, g.gx10, w00 * g.gx00)));
+    gy = fmaf(w11, g.gy11, fmaf(w01, g.gy01, fmaf(w10, g.gy10, w00 * g.gy00)));
     // the interpolated concentration itself, from the same corners and weights
-    if (value) *value = w00 * p.a1 + w10 * p.a2 + w01 * p.b1 + w11 * p.b2;
+    if (value) *value = fmaf(w11, p.b2, fmaf(w01, p.b1, fmaf(w10, p.a2, w00 * p.a1)));
 }
 
 // Interpolated central-difference gradient of one species at (x, y).
@@ -343,9 +394,9 @@ __device__ __forceinline__ void gradient_from_3d(const ConeRules& r, const Corne
                 const float ex = (a ? p.xp[b][c] : p.blk[1][b][c]) - (a ? p.blk[0][b][c] : p.xm[b][c]);
                 const float ey = (b ? p.yp[a][c] : p.blk[a][1][c]) - (b ? p.blk[a][0][c] : p.ym[a][c]);
                 const float ez = (c ? p.zp[a][b] : p.blk[a][b][1]) - (c ? p.blk[a][b][0] : p.zm[a][b]);
-                gx += w * ex;
-                gy += w * ey;
-                gz += w * ez;
+                gx = fmaf(w, ex, gx);
+                gy = fmaf(w, ey, gy);
+                gz = fmaf(w, ez, gz);
             }
     gx *= r.half_inv_dx;
     gy *= r.half_inv_dx;
@@ -385,7 +436,7 @@ __device__ __forceinline__ float capped_turn(const ConeRules& r, float cross, fl
     if (r.tan_max > 0.0f) {
         if (along > 0.0f && fabsf(cross) < along * r.tan_max) {
             *capped = false;
-            const float t = cross / along;
+            const float t = cross * __builtin_amdgcn_rcpf(along);   // reciprocal: ~1 ulp
             const float t2 = t * t;
             float p = fmaf(t2, -1.0f / 11.0f, 1.0f / 9.0f);
             p = fmaf(t2, p, -1.0f / 7.0f);
@@ -411,15 +462,33 @@ __device__ __forceinline__ float snr_turn(const ConeRules& r, float s, float c, 
     if (!(conc >= r.c_min && conc <= r.c_max) || (gx == 0.0f && gy == 0.0f)) return 0.0f;
     const float gamma = conc * r.inv_kd;
     const float one = 1.0f + gamma;
-    const float snr = r.snr_coef / conc * sqrtf(gamma / (one * one * one)) * (s * gx - c * gy);
+    const float snr =
+        r.snr_coef / conc * sqrtf(gamma / (one * one * one)) * fmaf(s, gx, -(c * gy));
     return snr + z0 > 0.0f ? -r.max_turn : r.max_turn;
+}
+
+// The two terms of the vector-law turn toward h + gain*g, h = (c, s) the heading:
+// cross = gain (h x g) and along = 1 + gain (h . g), with cross = -0 replaced by +0 (an
+// anti-parallel pull turns by +cap).  Shared by the forward step and its reverse, which must
+// see the same branch.
+__device__ __forceinline__ void turn_terms(const ConeRules& r, float s, float c, float gx,
+                                           float gy, float& cross, float& along) {
+    cross = r.gain * fmaf(c, gy, -(s * gx));
+    along = fmaf(r.gain, fmaf(c, gx, s * gy), 1.0f);
+    if (cross == 0.0f) cross = 0.0f;
+}
+
+// A heading wrapped back into [-pi, pi).
+__device__ __forceinline__ float wrap_heading(float th) {
+    const float two_pi = 6.28318530717958647692f;
+    return fmaf(-two_pi, floorf((th + 3.14159265358979323846f) * (1.0f / two_pi)), th);
 }
 
 // One step of an active 2D cone: turn toward h + gain*g (capped) -- or by the SNR law's
 // decision, which also needs the concentration `conc` of species 0 at the tip -- noise,
 // advance, exit, contact.  z is the step's normal pair (noise_2d).  `contact` finds the
 // nearest target in range (GridContact, or a list staged in LDS).  (s, c) carry
-// sincosf(theta) in and sincosf of the new heading out, so a caller stepping a cone
+// sincos_angle(theta) in and that of the new heading out, so a caller stepping a cone
 // repeatedly evaluates it once per step.
 template <class Contact>
 __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, float gy,
@@ -429,20 +498,18 @@ __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, 
     float th;
     if (r.turn_law == 1) {
         th = theta + snr_turn(r, s, c, gx, gy, conc, z[0]);
-        th = th + r.sigma * z[1];
+        th = fmaf(r.sigma, z[1], th);
     } else {
-        float cross = r.gain * (c * gy - s * gx);
-        const float along = 1.0f + r.gain * (c * gx + s * gy);
-        if (cross == 0.0f) cross = 0.0f;   // -0 -> +0: an anti-parallel pull turns by +cap
+        float cross, along;
+        turn_terms(r, s, c, gx, gy, cross, along);
         bool capped;
         const float turn = capped_turn(r, cross, along, &capped);
         th = theta + turn;
-        th = th + r.sigma * z[0];
+        th = fmaf(r.sigma, z[0], th);
     }
-    const float two_pi = 6.28318530717958647692f;
-    th = th - two_pi * floorf((th + 3.14159265358979323846f) * (1.0f / two_pi));
+    th = wrap_heading(th);
     theta = th;
-    sincosf(th, &s, &c);
+    sincos_angle(th, s, c);
     x = fmaf(r.step_len, c, x);
     y = fmaf(r.step_len, s, y);
     ConeEvent ev{kActive, -1};
@@ -458,6 +525,11 @@ __device__ __forceinline__ ConeEvent cone_step_2d(const ConeRules& r, float gx, 
     return ev;
 }
 
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by,
+                                      float bz) {
+    return fmaf(az, bz, fmaf(ay, by, ax * bx));
+}
+
 // One step of an active 3D cone with unit heading (hx, hy, hz).
 template <class Contact>
 __device__ __forceinline__ ConeEvent cone_step_3d(const ConeRules& r, float gx, float gy,
@@ -466,36 +538,36 @@ __device__ __forceinline__ ConeEvent cone_step_3d(const ConeRules& r, float gx, 
                                                   float& hy, float& hz,
                                                   const Contact& contact) {
     // turn in the plane of h and g, toward h + gain*g, by at most max_turn
-    const float gh = gx * hx + gy * hy + gz * hz;
-    const float px = gx - gh * hx, py = gy - gh * hy, pz = gz - gh * hz;
-    const float pn = sqrtf(px * px + py * py + pz * pz);
+    const float gh = dot3(gx, gy, gz, hx, hy, hz);
+    const float px = fmaf(-gh, hx, gx), py = fmaf(-gh, hy, gy), pz = fmaf(-gh, hz, gz);
+    const float pn = sqrtf(dot3(px, py, pz, px, py, pz));
     if (pn > 0.0f) {
-        float phi = atan2f(r.gain * pn, 1.0f + r.gain * gh);
+        float phi = atan2f(r.gain * pn, fmaf(r.gain, gh, 1.0f));
         phi = fminf(phi, r.max_turn);
         float s, c;
-        sincosf(phi, &s, &c);
+        sincos_angle(phi, s, c);
         const float k = s / pn;
-        hx = c * hx + k * px;
-        hy = c * hy + k * py;
-        hz = c * hz + k * pz;
+        hx = fmaf(c, hx, k * px);
+        hy = fmaf(c, hy, k * py);
+        hz = fmaf(c, hz, k * pz);
     }
     // tangent-plane Gaussian rotation
     float zn[3];
     normals<3>(r.key, id, step, zn);
-    const float zh = zn[0] * hx + zn[1] * hy + zn[2] * hz;
-    const float wx = r.sigma * (zn[0] - zh * hx);
-    const float wy = r.sigma * (zn[1] - zh * hy);
-    const float wz = r.sigma * (zn[2] - zh * hz);
-    const float wn = sqrtf(wx * wx + wy * wy + wz * wz);
+    const float zh = dot3(zn[0], zn[1], zn[2], hx, hy, hz);
+    const float wx = r.sigma * fmaf(-zh, hx, zn[0]);
+    const float wy = r.sigma * fmaf(-zh, hy, zn[1]);
+    const float wz = r.sigma * fmaf(-zh, hz, zn[2]);
+    const float wn = sqrtf(dot3(wx, wy, wz, wx, wy, wz));
     if (wn > 0.0f) {
         float s, c;
-        sincosf(wn, &s, &c);
+        sincos_angle(wn, s, c);
         const float k = s / wn;
-        hx = c * hx + k * wx;
-        hy = c * hy + k * wy;
-        hz = c * hz + k * wz;
+        hx = fmaf(c, hx, k * wx);
+        hy = fmaf(c, hy, k * wy);
+        hz = fmaf(c, hz, k * wz);
     }
-    const float inv = 1.0f / sqrtf(hx * hx + hy * hy + hz * hz);
+    const float inv = 1.0f / sqrtf(dot3(hx, hy, hz, hx, hy, hz));
     hx *= inv;
     hy *= inv;
     hz *= inv;

@@ -85,22 +85,22 @@ __device__ __forceinline__ Scatter2D gradient_2d_reverse(const Footprint2D& p,
     const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy);
     const float w01 = (1.0f - fx) * fy, w11 = fx * fy;
     // position: d w / d f along each axis, times d f / d p = 1 / dx where not clamped
-    const float aw00 = agx * g.gx00 + agy * g.gy00, aw10 = agx * g.gx10 + agy * g.gy10;
-    const float aw01 = agx * g.gx01 + agy * g.gy01, aw11 = agx * g.gx11 + agy * g.gy11;
-    if (free_x) apx += r.inv_dx * ((1.0f - fy) * (aw10 - aw00) + fy * (aw11 - aw01));
-    if (free_y) apy += r.inv_dx * ((1.0f - fx) * (aw01 - aw00) + fx * (aw11 - aw10));
+    const float aw00 = fmaf(agy, g.gy00, agx * g.gx00), aw10 = fmaf(agy, g.gy10, agx * g.gx10);
+    const float aw01 = fmaf(agy, g.gy01, agx * g.gx01), aw11 = fmaf(agy, g.gy11, agx * g.gx11);
+    if (free_x) apx = fmaf(r.inv_dx, fmaf(fy, aw11 - aw01, (1.0f - fy) * (aw10 - aw00)), apx);
+    if (free_y) apy = fmaf(r.inv_dx, fmaf(fx, aw11 - aw10, (1.0f - fx) * (aw01 - aw00)), apy);
     // field: each loaded value's adjoint
     const float h = r.half_inv_dx;
     const float hx = h * agx, hy = h * agy;
     const int r0 = j0 * nx, r1 = r0 + nx;
     Scatter2D s;
     s.at[0] = r0 + p.im;      s.v[0] = -w00 * hx;
-    s.at[1] = r0 + i0;        s.v[1] = -w10 * hx - w01 * hy;
-    s.at[2] = r0 + i0 + 1;    s.v[2] = w00 * hx - w11 * hy;
+    s.at[1] = r0 + i0;        s.v[1] = fmaf(-w10, hx, -(w01 * hy));
+    s.at[2] = r0 + i0 + 1;    s.v[2] = fmaf(w00, hx, -(w11 * hy));
     s.at[3] = r0 + p.ip;      s.v[3] = w10 * hx;
     s.at[4] = r1 + p.im;      s.v[4] = -w01 * hx;
-    s.at[5] = r1 + i0;        s.v[5] = -w11 * hx + w00 * hy;
-    s.at[6] = r1 + i0 + 1;    s.v[6] = w01 * hx + w10 * hy;
+    s.at[5] = r1 + i0;        s.v[5] = fmaf(-w11, hx, w00 * hy);
+    s.at[6] = r1 + i0 + 1;    s.v[6] = fmaf(w01, hx, w10 * hy);
     s.at[7] = r1 + p.ip;      s.v[7] = w11 * hx;
     s.at[8] = p.jm * nx + i0; s.v[8] = -w00 * hy;
     s.at[9] = s.at[8] + 1;    s.v[9] = -w10 * hy;
@@ -130,33 +130,29 @@ __device__ __forceinline__ void cone_adjoint_step(const ConeRules& r, const Foot
                                                   Scatter2D* out) {
     const float x = st.x, y = st.y, th = st.z;
     float s, c;
-    sincosf(th, &s, &c);
-    float cross = r.gain * (c * gy - s * gx);
-    const float along = 1.0f + r.gain * (c * gx + s * gy);
-    if (cross == 0.0f) cross = 0.0f;
+    sincos_angle(th, s, c);
+    float cross, along;
+    turn_terms(r, s, c, gx, gy, cross, along);
     bool capped;
     const float turn = capped_turn(r, cross, along, &capped);
     float z[2];
     noise_2d(r.key, (uint32_t)i, step, z);
-    float thn = th + turn;
-    thn = thn + r.sigma * z[0];
-    const float two_pi = 6.28318530717958647692f;
-    thn = thn - two_pi * floorf((thn + 3.14159265358979323846f) * (1.0f / two_pi));
+    const float thn = wrap_heading(fmaf(r.sigma, z[0], th + turn));
     float sn, cn;
-    sincosf(thn, &sn, &cn);
+    sincos_angle(thn, sn, cn);
 
     // reverse: p' = p + s (cos theta', sin theta')
-    const float athn = ath + r.step_len * (cn * apy - sn * apx);
+    const float athn = fmaf(r.step_len, fmaf(cn, apy, -(sn * apx)), ath);
     // theta' = theta + turn(theta, g) + noise
     ath = athn;
     float agx = 0.0f, agy = 0.0f;
     if (!capped) {
-        const float den = along * along + cross * cross;
+        const float den = fmaf(along, along, cross * cross);
         const float a_cross = athn * along / den, a_along = -athn * cross / den;
-        const float dot = c * gx + s * gy;
-        ath += a_cross * (-r.gain * dot) + a_along * cross;
-        agx = r.gain * (a_along * c - a_cross * s);
-        agy = r.gain * (a_cross * c + a_along * s);
+        const float dot = fmaf(c, gx, s * gy);
+        ath = fmaf(a_cross, -r.gain * dot, fmaf(a_along, cross, ath));
+        agx = r.gain * fmaf(a_along, c, -(a_cross * s));
+        agy = r.gain * fmaf(a_cross, c, a_along * s);
     }
     out[0] = gradient_2d_reverse(p0, g0, r, x, y, r.sign0 * agx, r.sign0 * agy, apx, apy);
     if (NS > 1)
@@ -248,7 +244,7 @@ __global__ __launch_bounds__(kSegThreads) void k_cones_segments2d(ConeRules r, S
             gy = fmaf(r.sign1, hy, gy);
         }
         float sn, cs;
-        sincosf(th, &sn, &cs);
+        sincos_angle(th, sn, cs);
         float z[2];
         noise_2d(r.key, (uint32_t)i, set.n0 + (uint32_t)t, z);
         const ConeEvent ev = cone_step_2d(r, gx, gy, 0.0f, z, x, y, th, sn, cs,

@@ -55,7 +55,7 @@ Tiles2D tiles_for(int nx, int ny, int rows = kRY) {
 
 __device__ __forceinline__ float stencil2d(float c, float w, float e, float s, float n,
                                            const StencilCoef& k) {
-    const float lap = ((w + e) + (s + n)) - 4.0f * c;
+    const float lap = fmaf(-4.0f, c, (w + e) + (s + n));
     return fmaf(k.r, lap, fmaf(-k.kdt, c, c));
 }
 
@@ -170,9 +170,9 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
 #pragma unroll
             for (int u = 0; u < kAUnroll; ++u) {
                 dst[(size_t)(j + u) * nx] = stencil2d(b, bw[u], be[u], b_below, bu[u], k);
-                const float lap_c = ((vw[u] + ve[u]) + (v_below + vu[u])) - 4.0f * v;
-                pD += (double)b * (double)lap_c;
-                pk += (double)b * (double)v;
+                const float lap_c = fmaf(-4.0f, v, (vw[u] + ve[u]) + (v_below + vu[u]));
+                pD = fma((double)b, (double)lap_c, pD);
+                pk = fma((double)b, (double)v, pk);
                 b_below = b;
                 b = bu[u];
                 v_below = v;
@@ -183,9 +183,9 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_rows(
             const size_t at = (size_t)j * nx, up = (size_t)min(j + 1, ny - 1) * nx;
             const float b_up = total(up, 0), v_up = cc[up];
             dst[at] = stencil2d(b, total(at, dw), total(at, de), b_below, b_up, k);
-            const float lap_c = ((cc[at + dw] + cc[at + de]) + (v_below + v_up)) - 4.0f * v;
-            pD += (double)b * (double)lap_c;
-            pk += (double)b * (double)v;
+            const float lap_c = fmaf(-4.0f, v, (cc[at + dw] + cc[at + de]) + (v_below + v_up));
+            pD = fma((double)b, (double)lap_c, pD);
+            pk = fma((double)b, (double)v, pk);
             b_below = b;
             b = b_up;
             v_below = v;
@@ -423,10 +423,10 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairAr
             B2[r][tid + 1] = stencil2d(b, b1(w, j), b1(e, j), b1(i, js), b1(i, jn), a.k) + en[r];
             if (r >= 1 && r <= kPY) {
                 const float v = c1v[r];
-                const float lap_c = ((c1w[r - 1] + c1e[r - 1]) + (c1v[r - 1] + c1v[r + 1])) -
-                                    4.0f * v;
-                pD += (double)b * (double)lap_c;
-                pk += (double)b * (double)v;
+                const float lap_c =
+                    fmaf(-4.0f, v, (c1w[r - 1] + c1e[r - 1]) + (c1v[r - 1] + c1v[r + 1]));
+                pD = fma((double)b, (double)lap_c, pD);
+                pk = fma((double)b, (double)v, pk);
             }
         }
     }
@@ -457,9 +457,9 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairAr
             a.a_out[(size_t)j * nx + i] =
                 stencil2d(b, b2(w, j), b2(e, j), b2(i, js), b2(i, jn), a.k);
             const float v = c0v[r + 1];
-            const float lap_c = ((c0w[r] + c0e[r]) + (c0v[r] + c0v[r + 2])) - 4.0f * v;
-            pD += (double)b * (double)lap_c;
-            pk += (double)b * (double)v;
+            const float lap_c = fmaf(-4.0f, v, (c0w[r] + c0e[r]) + (c0v[r] + c0v[r + 2]));
+            pD = fma((double)b, (double)lap_c, pD);
+            pk = fma((double)b, (double)v, pk);
         }
     }
     const double sD = block_sum_fp64(pD);

@@ -44,7 +44,7 @@ Boxes boxes_for(int nx, int ny, int nz) {
 
 __device__ __forceinline__ float stencil(float c, float w, float e, float s, float n,
                                          float below, float above, const StencilCoef& k) {
-    const float lap = (((w + e) + (s + n)) + (below + above)) - 6.0f * c;
+    const float lap = fmaf(-6.0f, c, ((w + e) + (s + n)) + (below + above));
     return fmaf(k.r, lap, fmaf(-k.kdt, c, c));
 }
 

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_cones2d(ConeRules r, const float* __res
         gy = fmaf(r.sign1, hy, gy);
     }
     float sn, cs;
-    sincosf(th, &sn, &cs);
+    sincos_angle(th, sn, cs);
     float z[2];
     noise_2d(r.key, (uint32_t)i, step, z);
     const ConeEvent ev = cone_step_2d(r, gx, gy, conc, z, x, y, th, sn, cs,

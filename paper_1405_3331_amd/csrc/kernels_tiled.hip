@@ -42,7 +42,7 @@ constexpr int kMaxTileTargets = 256;        // targets staged in LDS per tile
 constexpr size_t kLdsBudget = 154 * 1024;   // dynamic LDS; the rest is static (targets,
                                             // re-bucketing counters)
 constexpr int kLoadBatch = 10;              // tile rows a wavefront has in flight at load
-constexpr int kConeSlots = 2;               // cones per thread held in registers
+constexpr int kConeSlots = 1;               // cones per thread held in registers
 constexpr int kPartCones = kConeSlots * kThreads;   // cones one work item steps
 constexpr size_t kStaticLds = kMaxTileTargets * 16 + 3 * 9 * 4 + 16;   // static LDS per tile
 constexpr int kGuardRows = 4;               // one above and three below each species plane
@@ -205,7 +205,7 @@ __device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CP
             if (gx0 + k == 0) w = ck;
             if (gx0 + k == nx - 1) e = ck;
         }
-        const float lap = ((w + e) + (comp(s, k) + comp(n, k))) - 4.0f * ck;
+        const float lap = fmaf(-4.0f, ck, (w + e) + (comp(s, k) + comp(n, k)));
         set_comp(nv, k, fmaf(cf.r, lap, fmaf(-cf.kdt, ck, ck)));
     }
     return nv;
@@ -306,6 +306,57 @@ struct TileContact {
     }
 };
 
+// The gradient footprint of a tip read from the LDS tile.  Its 12 cells lie between one
+// cell before and two after the corner cell (i0, j0) along each axis, so one base address
+// and constant offsets reach them all; at a grid wall the outer cell is the wall cell itself
+// (the zero-flux ghost), substituted afterwards.  The base is clamped so that every read
+// stays inside the tile: a tip bucketed to the tile never needs the clamp (the halo covers
+// its footprint), and with it no tip can read outside the tile.  The values are those the
+// per-cell accessor (LdsField2D) returns.
+__device__ __forceinline__ Footprint2D footprint_lds(const LdsField2D& f, const ConeRules& r,
+                                                    float x, float y) {
+    Footprint2D p;
+    corner(x, r.inv_dx, r.nx, p.i0, p.fx);
+    corner(y, r.inv_dx, r.ny, p.j0, p.fy);
+    p.im = max(p.i0 - 1, 0);
+    p.ip = min(p.i0 + 2, r.nx - 1);
+    p.jm = max(p.j0 - 1, 0);
+    p.jp = min(p.j0 + 2, r.ny - 1);
+    const int W = f.width;
+    const int lx = min(max(p.i0 - f.x0, 1), W - 3);
+    const int ly = min(max(p.j0 - f.y0, 1), f.height - 3);
+    const float* b = f.L + ly * W + lx;
+    p.a0 = b[-1];
+    p.a1 = b[0];
+    p.a2 = b[1];
+    p.a3 = b[2];
+    p.b0 = b[W - 1];
+    p.b1 = b[W];
+    p.b2 = b[W + 1];
+    p.b3 = b[W + 2];
+    p.c0 = b[-W];
+    p.c1 = b[1 - W];
+    p.d0 = b[2 * W];
+    p.d1 = b[2 * W + 1];
+    if (p.im == p.i0) {   // left wall
+        p.a0 = p.a1;
+        p.b0 = p.b1;
+    }
+    if (p.ip == p.i0 + 1) {   // right wall
+        p.a3 = p.a2;
+        p.b3 = p.b2;
+    }
+    if (p.jm == p.j0) {   // bottom wall
+        p.c0 = p.a1;
+        p.c1 = p.a2;
+    }
+    if (p.jp == p.j0 + 1) {   // top wall
+        p.d0 = p.b1;
+        p.d1 = p.b2;
+    }
+    return p;
+}
+
 // The cone step in two parts.  The first samples the signed gradient g at the tip from the
 // LDS field (the only part that reads the field); the second turns, adds noise, advances
 // and tests exit and contact using g and registers only, so it may run while the next
@@ -317,12 +368,15 @@ __device__ __forceinline__ float3 tile_cone_gradient(const float4& st, const Lds
                                                      const ConeRules& rules) {
     float gxv = 0.0f, gyv = 0.0f, conc = 0.0f;
     if (__float_as_int(st.w) < 0) return make_float3(gxv, gyv, conc);
-    gradient_2d(f0, rules, st.x, st.y, gxv, gyv, rules.turn_law == 1 ? &conc : nullptr);
+    const Footprint2D p0 = footprint_lds(f0, rules, st.x, st.y);
+    gradient_from_2d(p0, corner_gradients_2d(p0, rules), gxv, gyv,
+                     rules.turn_law == 1 ? &conc : nullptr);
     gxv *= rules.sign0;
     gyv *= rules.sign0;
     if (NS > 1) {
         float hx, hy;
-        gradient_2d(f1, rules, st.x, st.y, hx, hy);
+        const Footprint2D p1 = footprint_lds(f1, rules, st.x, st.y);
+        gradient_from_2d(p1, corner_gradients_2d(p1, rules), hx, hy, nullptr);
         gxv = fmaf(rules.sign1, hx, gxv);
         gyv = fmaf(rules.sign1, hy, gyv);
     }
@@ -464,7 +518,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
             }
         }
     }
-    // sincosf of every heading, carried alongside the cone from sub-step to sub-step, and
+    // sin and cos of every heading, carried alongside the cone from sub-step to sub-step, and
     // the second half of the current Philox block
     float2 trig[kConeSlots];
     uint2 spare[kConeSlots];
@@ -472,7 +526,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     for (int k = 0; k < kConeSlots; ++k) {
         trig[k] = make_float2(0.0f, 1.0f);
         spare[k] = make_uint2(0u, 0u);
-        if (threadIdx.x + k * kThreads < n_cones) sincosf(mine[k].z, &trig[k].x, &trig[k].y);
+        if (threadIdx.x + k * kThreads < n_cones) sincos_angle(mine[k].z, trig[k].x, trig[k].y);
     }
     if (threadIdx.x < 9) {
         dest_count[threadIdx.x] = 0;
@@ -486,12 +540,19 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     // for every wavefront in scalar registers and kept monotone.
     int ybeg = 0, yend = 0;
     {
-        const int c0 = min(kWaves, (n_cones + 63) / 64);                 // slot-0 waves
-        const int c1 = min(kWaves, (max(n_cones - kThreads, 0) + 63) / 64);   // slot-1 waves
-        const float per = (float)(HL + a.cone_rows * (c0 + c1)) / kWaves;
+        int cw[kConeSlots];   // wavefronts holding a cone in slot k
+        int slots = 0;
+#pragma unroll
+        for (int k = 0; k < kConeSlots; ++k) {
+            cw[k] = min(kWaves, (max(n_cones - k * kThreads, 0) + 63) / 64);
+            slots += cw[k];
+        }
+        const float per = (float)(HL + a.cone_rows * slots) / kWaves;
         int prev = 0;
         for (int w = 1; w <= kWaves; ++w) {
-            const int used = a.cone_rows * (min(w, c0) + min(w, c1));
+            int used = 0;
+#pragma unroll
+            for (int k = 0; k < kConeSlots; ++k) used += a.cone_rows * min(w, cw[k]);
             const int b = w == kWaves ? HL : min(max((int)rintf(w * per) - used, prev), HL);
             if (w == wave) ybeg = b;       // wavefront w's strip is [b(w), b(w + 1))
             if (w == wave + 1) yend = b;
@@ -750,7 +811,7 @@ namespace {
 // Best tile plan by the cost model, restricted to row width 64 * only_cpl and loaded height
 // only_height when those are non-zero.
 TiledPlan plan_search(int dim, int nx, int ny, int nz, int n_species, double step_cells,
-                      int block_steps, int only_cpl, int only_height) {
+                      int block_steps, int n_cones, int only_cpl, int only_height) {
     TiledPlan best;
     best.dim = dim;
     best.nx = nx;
@@ -787,9 +848,13 @@ TiledPlan plan_search(int dim, int nx, int ny, int nz, int n_species, double ste
                 const int resident = std::max(1, std::min(2, (int)(per_cu_lds / (lds + kStaticLds))));
                 // per-step cost in cell-updates per compute unit: each tile's loaded area
                 // per sub-step plus its load/store per launch; one resident tile per CU
-                // hides latency poorly
+                // hides latency poorly.  Cones gather (attracted to the sources), and a tile
+                // holding more than kPartCones of them takes extra workgroups: keep room
+                // for a quarter of the cones in full parts beside one workgroup per tile,
+                // or the launch runs in two generations.
+                const int spare = std::min(tiles, ceil_div(n_cones, 4 * kPartCones));
                 double cost = (double)per_cu * W * HL * (1.0 + 2.0 / B) / B;
-                if (resident < 2 || per_cu > resident) cost *= 1.25;
+                if (resident < 2 || ceil_div(tiles + spare, 256) > resident) cost *= 1.25;
                 if (cost < best_cost * 0.999) {
                     best_cost = cost;
                     best.block_steps = B;
@@ -818,13 +883,12 @@ TiledPlan plan_search(int dim, int nx, int ny, int nz, int n_species, double ste
 
 TiledPlan tiled_plan(int dim, int nx, int ny, int nz, int n_species, double step_cells,
                      int block_steps, int n_cones, int force_cpl, int force_height) {
-    (void)n_cones;
     if (force_cpl != 0 || force_height != 0) {
         const TiledPlan forced = plan_search(dim, nx, ny, nz, n_species, step_cells,
-                                             block_steps, force_cpl, force_height);
+                                             block_steps, n_cones, force_cpl, force_height);
         if (forced.block_steps > 1) return forced;
     }
-    return plan_search(dim, nx, ny, nz, n_species, step_cells, block_steps, 0, 0);
+    return plan_search(dim, nx, ny, nz, n_species, step_cells, block_steps, n_cones, 0, 0);
 }
 
 hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
