@@ -37,8 +37,9 @@ def size_class(sc) -> str:
 
 def default_candidates():
     """(block_steps, cols_per_lane, height) triples; height 0 = the planner's choice.  The
-    explicit heights keep two tiles resident per compute unit (LDS) at either row width."""
-    return ([(b, 2, h) for b in (6, 8, 10, 12, 14, 16) for h in (0, 110, 130, 150)] +
+    explicit heights keep two tiles resident per compute unit (LDS) at either row width;
+    144 rows is the tallest 64 x 2-column tile that does."""
+    return ([(b, 2, h) for b in (6, 8, 10, 12, 14, 16) for h in (0, 110, 130, 138, 144)] +
             [(b, 4, h) for b in (6, 8, 12, 16) for h in (0, 70)])
 
 
