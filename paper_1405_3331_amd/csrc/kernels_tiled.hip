@@ -123,34 +123,52 @@ __device__ __forceinline__ void gstore(GlobalPtr<float4> p, float4 v) {
 }
 
 // One tile row segment of CPL floats per lane: row gy, columns gx0 .. gx0 + CPL - 1 of the
-// field.  Every load is issued (indices clamped into the grid, so no lane branches around
-// it) and a cell outside the grid is replaced by zero afterwards.  With `aligned` (the
-// segment starts at a multiple of CPL and the row length is one) the segment lies wholly
-// inside or wholly outside the grid's columns and is one naturally aligned vector load.
+// field, read at indices clamped into the grid, so every lane loads and nothing branches
+// between the loads of a batch; cells outside the grid are zeroed when the segment is
+// stored (store_row).  With ALIGNED (the segment starts at a multiple of CPL and the row
+// length is one) the segment lies wholly inside or wholly outside the grid's columns and is
+// one naturally aligned vector load.
 template <int CPL>
 using RowVec = float __attribute__((ext_vector_type(CPL)));
 
-template <int CPL>
-__device__ __forceinline__ typename Row<CPL>::T load_row(GlobalPtr<const float> f, int nx,
-                                                         int ny, int gy, int gx0,
-                                                         const bool (&col_in)[CPL],
-                                                         bool aligned) {
-    typename Row<CPL>::T v;
-    const bool row_in = (unsigned)gy < (unsigned)ny;
+template <int CPL, bool ALIGNED>
+__device__ __forceinline__ RowVec<CPL> load_row(GlobalPtr<const float> f, int nx, int ny,
+                                                int gy, int gx0) {
     const size_t at = (size_t)min(max(gy, 0), ny - 1) * nx;
-    if (aligned) {
-        const RowVec<CPL> x = *(GlobalPtr<const RowVec<CPL>>)(f + at + min(max(gx0, 0), nx - CPL));
-        const bool in = row_in && col_in[0];
+    if (ALIGNED) return *(GlobalPtr<const RowVec<CPL>>)(f + at + min(max(gx0, 0), nx - CPL));
+    RowVec<CPL> v;
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) set_comp(v, k, in ? x[k] : 0.0f);
-        return v;
-    }
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-        const float x = f[at + min(max(gx0 + k, 0), nx - 1)];
-        set_comp(v, k, row_in && col_in[k] ? x : 0.0f);
-    }
+    for (int k = 0; k < CPL; ++k) v[k] = f[at + min(max(gx0 + k, 0), nx - 1)];
     return v;
+}
+
+// Load a tile plane (HL rows from grid row y0) into LDS rows 0 .. HL-1 at `dst`, the rows
+// strided over the wavefronts, kLoadBatch rows in flight per wavefront: the batch's loads
+// are all issued before the first is used.  A batch running past the tile re-reads its last
+// row and parks the copy in guard row HL, which is never meaningful.  Cells outside the grid
+// read as zero; cells inside never use them (they take their own value for out-of-grid
+// neighbours).
+template <int CPL, bool ALIGNED>
+__device__ __forceinline__ void load_tile(float* dst, GlobalPtr<const float> f, int nx, int ny,
+                                          int y0, int HL, int gx0, int cx, int wave,
+                                          const bool (&col_in)[CPL]) {
+    using V = typename Row<CPL>::T;
+    constexpr int W = 64 * CPL;
+    for (int ly0 = wave; ly0 < HL; ly0 += kLoadBatch * kWaves) {
+        RowVec<CPL> v[kLoadBatch];
+#pragma unroll
+        for (int r = 0; r < kLoadBatch; ++r)
+            v[r] = load_row<CPL, ALIGNED>(f, nx, ny, y0 + min(ly0 + r * kWaves, HL - 1), gx0);
+#pragma unroll
+        for (int r = 0; r < kLoadBatch; ++r) {
+            const int ly = min(ly0 + r * kWaves, HL);
+            const bool row_in = (unsigned)(y0 + ly) < (unsigned)ny;
+            V out;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) set_comp(out, k, row_in && col_in[k] ? v[r][k] : 0.0f);
+            *(V*)&dst[ly * W + cx] = out;
+        }
+    }
 }
 
 // LDS view of one species with tile-origin offset; indices are clamped to the tile so a
@@ -504,19 +522,11 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const GlobalPtr<const float> f = gbl((const float*)in[s]);
-        for (int ly0 = wave; ly0 < HL; ly0 += kLoadBatch * kWaves) {
-            V v[kLoadBatch];
-#pragma unroll
-            for (int r = 0; r < kLoadBatch; ++r) {
-                const int ly = ly0 + r * kWaves;
-                if (ly < HL) v[r] = load_row<CPL>(f, a.nx, a.ny, y0 + ly, gx0, col_in, aligned);
-            }
-#pragma unroll
-            for (int r = 0; r < kLoadBatch; ++r) {
-                const int ly = ly0 + r * kWaves;
-                if (ly < HL) *(V*)&lds[s * plane + (ly + 1) * W + cx] = v[r];
-            }
-        }
+        float* const dst = lds + s * plane + W;
+        if (aligned)
+            load_tile<CPL, true>(dst, f, a.nx, a.ny, y0, HL, gx0, cx, wave, col_in);
+        else
+            load_tile<CPL, false>(dst, f, a.nx, a.ny, y0, HL, gx0, cx, wave, col_in);
     }
     // sin and cos of every heading, carried alongside the cone from sub-step to sub-step, and
     // the second half of the current Philox block
@@ -678,8 +688,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
 __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* __restrict__ base,
                             int n_base, int par_in, int par_zero, bool zero, int4* items,
                             int item_cap, LaunchState* ls) {
-    extern __shared__ __align__(16) float lds[];
-    int* scan = reinterpret_cast<int*>(lds);   // kThreads ints of the (idle) dynamic LDS
+    __shared__ int wave_total[kWaves];
     const int per = (n_base + kThreads - 1) / kThreads;
     const int lo = min((int)threadIdx.x * per, n_base), hi = min(lo + per, n_base);
     int mine = 0;
@@ -688,15 +697,24 @@ __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* _
                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         mine += max(1, (c + kPartCones - 1) / kPartCones);
     }
-    scan[threadIdx.x] = mine;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {   // inclusive scan
-        const int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
-        __syncthreads();
-        scan[threadIdx.x] += v;
-        __syncthreads();
+    // exclusive scan of `mine` over the workgroup: within each wavefront by lane shuffles,
+    // then across the wavefronts' totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
     }
-    int at = scan[threadIdx.x] - mine;
+    if (lane == 63) wave_total[wave] = incl;
+    __syncthreads();
+    int at = incl - mine, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int t = wave_total[w];
+        at += w < wave ? t : 0;
+        total += t;
+    }
     for (int k = lo; k < hi; ++k) {
         const TiledArgs2D& a = table[base[k].x];
         const int c = __hip_atomic_load(&a.count[par_in][base[k].y], __ATOMIC_RELAXED,
@@ -706,7 +724,7 @@ __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* _
             if (at < item_cap) items[at] = make_int4(base[k].x, base[k].y, q, 0);
         if (zero) a.count[par_zero][base[k].y] = 0;
     }
-    if (threadIdx.x == kThreads - 1) ls->n_items = min(scan[kThreads - 1], item_cap);
+    if (threadIdx.x == 0) ls->n_items = min(total, item_cap);
 }
 
 // The step kernel.  Work items are (simulation, tile) pairs; without an item list the
@@ -742,15 +760,20 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
         }
     }
     // The last workgroup to finish lists the next launch's work items from the final tile
-    // counts, zeroes this launch's input counts and advances the launch state.
+    // counts, zeroes this launch's input counts and advances the launch state.  The only
+    // data it reads that other workgroups wrote during the launch are those counts, which
+    // are changed by read-modify-write atomics only (performed at the device's coherence
+    // point, all of a workgroup's complete before it counts itself out: their results were
+    // used before the barrier) and read back with agent-scope atomic loads.  So no fence is
+    // needed -- an agent-scope fence would write back and invalidate the whole L2 of the
+    // chiplet once per workgroup.  Everything else it writes is read by the next launch,
+    // after the kernel boundary.
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last_out = atomicAdd(&ls->exited, 1) == (int)gridDim.x - 1;
-    }
+    if (threadIdx.x == 0)
+        last_out = __hip_atomic_fetch_add(&ls->exited, 1, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1;
     __syncthreads();
     if (last_out) {
-        __threadfence();
         build_items(table, base, n_base, par ^ 1, par, true, items, item_cap, ls);
         if (threadIdx.x == 0) {
             ls->exited = 0;
@@ -1051,7 +1074,7 @@ int tiled_item_capacity(int n_tiles, int n_cones) {
 
 hipError_t tiled_build_items(const TiledArgs2D* table, int4* items, const int2* base,
                              int n_base, int item_cap, LaunchState* launch, hipStream_t stream) {
-    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(kThreads), kThreads * sizeof(int), stream,
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(kThreads), 0, stream,
                        table, items, base, n_base, item_cap, launch);
     return hipGetLastError();
 }
