@@ -335,19 +335,28 @@ __global__ __launch_bounds__(kRecThreads) void k_sample_add(
     const int i = blockIdx.x * kRecThreads + threadIdx.x;
     const int t = blockIdx.y;
     if (i >= n || t > last_step(seg, status, event_step, i)) return;
-    const double scale = ldexp(1.0, kFixedBits - fixed_exponent(step_max[t]));
     const size_t rec = (((size_t)t * n + i) * NS) * 12;
+    // the whole record first (16-byte loads, all in flight together), then the additions
+    float4 v[3 * NS];
+    int4 at[3 * NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        unsigned long long* dst = e + ((size_t)t * NS + s) * seg.cells;
+    for (int k = 0; k < 3 * NS; ++k) {
+        v[k] = ((const float4*)(rec_v + rec))[k];
+        at[k] = ((const int4*)(rec_at + rec))[k];
+    }
+    const double scale = ldexp(1.0, kFixedBits - fixed_exponent(step_max[t]));
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const double x = (double)rec_v[rec + s * 12 + k] * scale;
-            // (a non-finite contribution, possible only from non-finite fields, adds nothing
-            // rather than an undefined conversion)
-            const long long q = isfinite(x) ? (long long)rint(x) : 0;
-            if (q != 0) atomicAdd(dst + rec_at[rec + s * 12 + k], (unsigned long long)q);
-        }
+    for (int k = 0; k < 12 * NS; ++k) {
+        unsigned long long* dst = e + ((size_t)t * NS + k / 12) * seg.cells;
+        const float4 vq = v[k / 4];
+        const int4 aq = at[k / 4];
+        const float val = k % 4 == 0 ? vq.x : k % 4 == 1 ? vq.y : k % 4 == 2 ? vq.z : vq.w;
+        const int cell = k % 4 == 0 ? aq.x : k % 4 == 1 ? aq.y : k % 4 == 2 ? aq.z : aq.w;
+        const double x = (double)val * scale;
+        // (a non-finite contribution, possible only from non-finite fields, adds nothing
+        // rather than an undefined conversion)
+        const long long q = isfinite(x) ? (long long)rint(x) : 0;
+        if (q != 0) atomicAdd(dst + cell, (unsigned long long)q);
     }
 }
 
