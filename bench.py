@@ -339,6 +339,15 @@ def bench_volume(args):
     print(json.dumps(out), flush=True)
 
 
+def without_cones(sc):
+    """The same scenario with no cones and no targets (the field update alone)."""
+    bare = copy.copy(sc)
+    bare.cone_pos = sc.cone_pos[:0]
+    bare.cone_dir = sc.cone_dir[:0]
+    bare.target_pos = sc.target_pos[:0]
+    return bare
+
+
 def timed_region(sc, stream, block, warmup, steps):
     """HIP-event milliseconds of `steps` steps of `sc` after `warmup` steps, on `stream`,
     and the tiling used."""
@@ -390,6 +399,11 @@ def main():
     ap.add_argument("--connectivity", action="store_true",
                     help="adjacency list and BFS levels of the headline run's contacts")
     ap.add_argument("--connectivity-steps", type=int, default=4000)
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="the headline grid with no cones and no targets (field update only)")
+    ap.add_argument("--call-steps", type=int, default=0,
+                    help="step the timed region in calls of this many steps, one launch each "
+                         "when it is at most the blocking depth (0 = one call)")
     ap.add_argument("--no-cone-rate", action="store_true",
                     help="skip the stencil-only run behind cone_steps_per_s")
     ap.add_argument("--ratio-batch-steps", type=int, default=400,
@@ -425,6 +439,10 @@ def main():
     block = args.block_steps
     if block == 0:   # blocking depth and tile shape recorded by the autotuner, if any
         block = autotune.apply(sc)
+    if args.stencil_only:   # after the lookup: the tiling stays the headline's
+        sc = without_cones(sc)
+        sc.name += ", stencil only"
+        args.no_cone_rate = True
     print(f"[bench] {sc.name}: {sc.n_cells} cells, {sc.n_cones} cones, "
           f"warmup {args.warmup}, timed {args.steps}, block_steps {block or 'default'}",
           file=sys.stderr, flush=True)
@@ -440,7 +458,11 @@ def main():
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    if args.call_steps > 0:
+        for done in range(0, args.steps, args.call_steps):
+            sim.step(min(args.call_steps, args.steps - done))
+    else:
+        sim.step(args.steps)
     ev1.record(stream)
     sim.synchronize()
     elapsed = time.perf_counter() - t0
@@ -453,10 +475,7 @@ def main():
     # the same field with no cones and no targets, in the same tiling, on HIP event time
     cone_rate = None
     if not args.no_cone_rate:
-        bare = copy.copy(sc)
-        bare.cone_pos = sc.cone_pos[:0]
-        bare.cone_dir = sc.cone_dir[:0]
-        bare.target_pos = sc.target_pos[:0]
+        bare = without_cones(sc)
         bare_ms, bare_tiling = timed_region(bare, stream, block, args.warmup, args.steps)
         extra_ms = gpu_ms - bare_ms
         cone_rate = {

@@ -41,50 +41,75 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
     __shared__ int32_t count[kBins];
     const int tid = threadIdx.x, tile = blockIdx.x;
     count[tid] = 0;
+    // every round's key first (indices clamped, so nothing branches between the loads)
+    uint32_t key[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) key[r] = keys[min(tile * kTile + r * kSortThreads + tid, n - 1)];
     __syncthreads();
-    for (int r = 0; r < kRounds; ++r) {
-        const int i = tile * kTile + r * kSortThreads + tid;
-        if (i < n) atomicAdd(&count[(keys[i] >> shift) & (kBins - 1)], 1);
-    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+        if (tile * kTile + r * kSortThreads + tid < n)
+            atomicAdd(&count[(key[r] >> shift) & (kBins - 1)], 1);
     __syncthreads();
     hist[tid * n_tiles + tile] = count[tid];
 }
 
 // Exclusive scan of a[0..n) in place by one workgroup, kScanPer entries per thread at a
-// time: each thread loads its run of kScanPer consecutive entries into registers (all
-// loads issued before any is used), the run totals are scanned in LDS, and each thread
-// writes its run back; longer arrays take several such rounds, carrying the total.
+// time: each thread loads its run of kScanPer consecutive entries into registers (16-byte
+// loads when the run lies inside the array, else loads at clamped indices; either way all
+// issued before any is used), the run totals are scanned across each wavefront by lane
+// shuffles and across the wavefronts in LDS, and each thread writes its run back; longer
+// arrays take several such rounds, carrying the total.
 constexpr int kScanPer = 32;
+constexpr int kScanWaves = kScanThreads / 64;
 
 __global__ __launch_bounds__(kScanThreads) void k_sort_scan(int32_t* __restrict__ a, int n) {
-    __shared__ int32_t part[kScanThreads];
-    __shared__ int32_t carry_in;
-    if (threadIdx.x == 0) carry_in = 0;
+    __shared__ int32_t wave_total[kScanWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t carry = 0;
     for (int base = 0; base < n; base += kScanThreads * kScanPer) {
         const int lo = base + (int)threadIdx.x * kScanPer;
         int32_t v[kScanPer];
+        if (lo + kScanPer <= n && (lo & 3) == 0) {
 #pragma unroll
-        for (int u = 0; u < kScanPer; ++u) v[u] = lo + u < n ? a[lo + u] : 0;
+            for (int u = 0; u < kScanPer; u += 4) {
+                const int4 q = *(const int4*)(a + lo + u);
+                v[u] = q.x;
+                v[u + 1] = q.y;
+                v[u + 2] = q.z;
+                v[u + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kScanPer; ++u) v[u] = a[min(lo + u, n - 1)];
+#pragma unroll
+            for (int u = 0; u < kScanPer; ++u) v[u] = lo + u < n ? v[u] : 0;
+        }
         int32_t sum = 0;
 #pragma unroll
         for (int u = 0; u < kScanPer; ++u) sum += v[u];
-        part[threadIdx.x] = sum;
-        __syncthreads();
-        for (int off = 1; off < kScanThreads; off <<= 1) {
-            const int32_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
+        int32_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
         }
-        int32_t at = carry_in + part[threadIdx.x] - sum;
+        if (lane == 63) wave_total[wave] = incl;
+        __syncthreads();
+        int32_t at = carry + incl - sum, round_total = 0;
+#pragma unroll
+        for (int w = 0; w < kScanWaves; ++w) {
+            const int32_t t = wave_total[w];
+            at += w < wave ? t : 0;
+            round_total += t;
+        }
 #pragma unroll
         for (int u = 0; u < kScanPer; ++u) {
             if (lo + u < n) a[lo + u] = at;
             at += v[u];
         }
-        __syncthreads();   // every thread has read carry_in and part
-        if (threadIdx.x == kScanThreads - 1) carry_in = at;
-        __syncthreads();
+        carry += round_total;
+        __syncthreads();   // every thread has read wave_total
     }
 }
 
@@ -97,15 +122,21 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, tile = blockIdx.x;
     next[tid] = start[tid * n_tiles + tile];
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // every round's item first (indices clamped, so nothing branches between the loads)
+    uint32_t keys[kRounds];
+    int32_t vals[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int i = min(tile * kTile + r * kSortThreads + tid, n - 1);
+        keys[r] = kin[i];
+        vals[r] = vin[i];
+    }
+#pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int i = tile * kTile + r * kSortThreads + tid;
         const bool valid = i < n;
-        uint32_t key = 0;
-        int32_t val = 0;
-        if (valid) {
-            key = kin[i];
-            val = vin[i];
-        }
+        const uint32_t key = valid ? keys[r] : 0u;
+        const int32_t val = vals[r];
         const int d = (int)((key >> shift) & (kBins - 1));
         // lanes of this wavefront holding a valid item with the same digit
         uint64_t peers = __ballot(valid);
