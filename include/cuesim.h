@@ -214,9 +214,11 @@ const char* sim_last_error(const sim_handle* h);
  * derivative is taken along the run's branch: the exit and contact decisions and the active
  * side of the turn cap are held as the run took them (the cone rules of Sec. 3.4-3.5 are
  * not differentiable at those switches).  Memory: checkpoints of the fields and cone state
- * every checkpoint_every steps, and during the reverse sweep one segment of
- * checkpoint_every + 1 fields per species that is recomputed from its checkpoint; a
- * checkpoint_every of at least n_steps records the whole run and recomputes it once.
+ * every checkpoint_every steps.  When every field state of the run fits within the tape
+ * limit (sim_adjoint_set_tape_limit), the run records them all as it goes and the reverse
+ * sweep re-runs only the cone steps; otherwise the sweep re-runs each segment of
+ * checkpoint_every + 1 fields per species from its checkpoint just before reversing it.
+ * Both ways give the same gradient, bit for bit.
  * ---------------------------------------------------------------------------------------- */
 
 /* Advance n_steps >= 0 steps (as sim_step does), checkpointing every checkpoint_every >= 1
@@ -233,12 +235,13 @@ sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_ev
  * called again for the same record.  Synchronises the stream. */
 sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, double* dL_dk);
 
-/* Device memory (bytes) that sim_adjoint_backward may spend on recorded states so that it
- * re-runs the fields and cone steps of the whole run once (instead of re-running each
- * checkpoint segment from its checkpoint just before reversing it).  0 (the default) means
- * half the device memory free when the sweep starts.  When the whole run's states do not
- * fit within the limit, each segment is re-run from its checkpoint; both ways give the
- * same gradient.  SIM_EINVAL if max_bytes < 0. */
+/* Device memory (bytes) that the gradient may spend on recorded states: every field state
+ * of the run (recorded by sim_adjoint_run as it steps, freed with the record) and every
+ * cone state (re-run once by sim_adjoint_backward), instead of re-running each checkpoint
+ * segment from its checkpoint just before reversing it.  0 (the default) means half the
+ * device memory free when sim_adjoint_run starts.  Set it before sim_adjoint_run.  When
+ * the whole run's states do not fit within the limit, each segment is re-run from its
+ * checkpoint; both ways give the same gradient.  SIM_EINVAL if max_bytes < 0. */
 sim_status sim_adjoint_set_tape_limit(sim_handle* h, int64_t max_bytes);
 
 /* ----------------------------------------------------------------------------------------

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -71,6 +72,10 @@ struct TiledArgs2D {
     int cone_rows;             // stencil rows a wavefront gives up per cone slot it steps
     ConeArrays cones;
     ConeRules rules;
+    float* record;             // non-null: every sub-step's field also goes to
+                               // record + ((step - record_n0) * NS + s) * cells (a tape of
+                               // every state of a run, for the trajectory-loss gradient)
+    uint32_t record_n0;
 };
 
 namespace {
@@ -456,12 +461,48 @@ __device__ __forceinline__ int2 next_tile(const float4& st, int tx, int ty, int 
     return make_int2(ntx, nty);
 }
 
+// The core of a tile from LDS to the fields dst[s] (row-major, the grid's row length),
+// through global-address-space stores.  The tile's rows are strided over the wavefronts.
+template <int NS, int CPL>
+__device__ __forceinline__ void store_core(float* const dst[], const TiledArgs2D& a, int tx,
+                                           int ty, int plane, int cx, int wave, bool aligned) {
+    using V = typename Row<CPL>::T;
+    constexpr int W = 64 * CPL;
+    extern __shared__ __align__(16) float lds[];
+    const int H = a.halo;
+    const int cx0 = tx * a.tx_core, cy0 = ty * a.ty_core;
+    for (int ly = wave; ly < a.ty_core; ly += kWaves) {
+        const int gy = cy0 + ly;
+        if (gy >= a.ny) break;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const V v = *(const V*)&lds[s * plane + (ly + H + 1) * W + cx];
+            const GlobalPtr<float> row = gbl(dst[s]) + (size_t)gy * a.nx + cx0;
+            if (aligned) {
+                const int lx = cx - H;   // the segment is wholly inside or outside the core
+                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx) {
+                    RowVec<CPL> x;
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) x[k] = comp(v, k);
+                    *(GlobalPtr<RowVec<CPL>>)(row + lx) = x;
+                }
+                continue;
+            }
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                const int lx = cx + k - H;   // core column of this lane's k-th cell
+                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx) row[lx] = comp(v, k);
+            }
+        }
+    }
+}
+
 // One work item: part `part` of one tile of one simulation for `steps` sub-steps.  Every
 // part of a tile computes the tile's field; part p steps the tile's cones
 // [p * kPartCones, (p + 1) * kPartCones) and only part 0 writes the field back, so a tile
 // crowded with cones is spread over several workgroups.  par selects the input half of
 // every ping-pong pair (fields and cone buckets); the other half is written.
-template <int NS, int CPL>
+template <int NS, int CPL, bool RECORD>
 __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int part, int steps,
                                           uint32_t first_step, int par) {
     using V = typename Row<CPL>::T;
@@ -608,6 +649,16 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
             }
             __syncthreads();
         }
+        // recording a run: the state after this sub-step goes to the tape (read from LDS
+        // before the next sub-step's in-place update, hence the barrier)
+        if (RECORD && part == 0) {
+            const size_t cells = (size_t)a.nx * a.ny;
+            const size_t at = (size_t)(first_step + (uint32_t)b + 1u - a.record_n0) * NS;
+            float* tape[SIM_MAX_SPECIES] = {a.record + at * cells,
+                                            a.record + (at + (NS - 1)) * cells};
+            store_core<NS, CPL>(tape, a, tx, ty, plane, cx, wave, aligned);
+            __syncthreads();
+        }
         // 4. cones against the updated field.  Every read of the field (the gradients)
         //    happens before the barrier; the cones then finish their step after it,
         //    overlapping the next sub-step's in-place stencil, which they no longer read.
@@ -624,32 +675,8 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
         }
     }
 
-    // 5. write the core back (one part per tile does), through global-address-space stores
-    const int cx0 = tx * a.tx_core, cy0 = ty * a.ty_core;
-    for (int ly = wave; part == 0 && ly < a.ty_core; ly += kWaves) {
-        const int gy = cy0 + ly;
-        if (gy >= a.ny) break;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const V v = *(const V*)&lds[s * plane + (ly + H + 1) * W + cx];
-            const GlobalPtr<float> row = gbl(out[s]) + (size_t)gy * a.nx + cx0;
-            if (aligned) {
-                const int lx = cx - H;   // the segment is wholly inside or outside the core
-                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx) {
-                    RowVec<CPL> x;
-#pragma unroll
-                    for (int k = 0; k < CPL; ++k) x[k] = comp(v, k);
-                    *(GlobalPtr<RowVec<CPL>>)(row + lx) = x;
-                }
-                continue;
-            }
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                const int lx = cx + k - H;   // core column of this lane's k-th cell
-                if (lx >= 0 && lx < a.tx_core && cx0 + lx < a.nx) row[lx] = comp(v, k);
-            }
-        }
-    }
+    // 5. write the core back (one part per tile does)
+    if (part == 0) store_core<NS, CPL>(out, a, tx, ty, plane, cx, wave, aligned);
 
     // 6. re-bucket surviving cones, straight from registers, into the tile that now holds
     //    their tip (one of the 3 x 3 tiles around this one)
@@ -732,7 +759,7 @@ __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* _
 // queue until it runs dry.  The launch state (step counter, ping-pong parity) is read by
 // every workgroup at its start and advanced by the last workgroup to finish, so launches
 // need no host-side bookkeeping and can be captured in a graph and replayed.
-template <int NS, int CPL>
+template <int NS, int CPL, bool RECORD>
 __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restrict__ table,
                                                       int4* items, const int2* __restrict__ base,
                                                       int n_base, int item_cap, int steps,
@@ -747,7 +774,7 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
         // launch state (an entry past n_items is not used)
         const int4 it = items[blockIdx.x];
         if ((int)blockIdx.x < n_items)
-            tile_body<NS, CPL>(table[it.x], it.y, it.z, steps, first_step, par);
+            tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, steps, first_step, par);
     } else {
         for (;;) {
             __syncthreads();   // the previous item is done with LDS and item_idx
@@ -756,7 +783,7 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
             const int i = item_idx;
             if (i >= n_items) break;
             const int4 it = items[i];
-            tile_body<NS, CPL>(table[it.x], it.y, it.z, steps, first_step, par);
+            tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, steps, first_step, par);
         }
     }
     // The last workgroup to finish lists the next launch's work items from the final tile
@@ -821,10 +848,17 @@ __global__ void k_unbucket2d(ConeArrays c, const float4* bucket, const int32_t* 
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-const void* kernel_for(int n_species, int cpl) {
+// The kernel variant for a species count and row width; `record` selects the one that also
+// writes every sub-step's state to the run tape (only a recording run launches it).
+const void* kernel_for(int n_species, int cpl, bool record = false) {
+    if (record) {
+        if (n_species == 1)
+            return cpl == 4 ? (const void*)k_tiled2d<1, 4, true> : (const void*)k_tiled2d<1, 2, true>;
+        return cpl == 4 ? (const void*)k_tiled2d<2, 4, true> : (const void*)k_tiled2d<2, 2, true>;
+    }
     if (n_species == 1)
-        return cpl == 4 ? (const void*)k_tiled2d<1, 4> : (const void*)k_tiled2d<1, 2>;
-    return cpl == 4 ? (const void*)k_tiled2d<2, 4> : (const void*)k_tiled2d<2, 2>;
+        return cpl == 4 ? (const void*)k_tiled2d<1, 4, false> : (const void*)k_tiled2d<1, 2, false>;
+    return cpl == 4 ? (const void*)k_tiled2d<2, 4, false> : (const void*)k_tiled2d<2, 2, false>;
 }
 
 }  // namespace
@@ -1056,8 +1090,27 @@ hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
     const LaunchState ls0 = {0, 0, 0, 0, 0};
     if ((e = hipMemcpy(st.launch, &ls0, sizeof ls0, hipMemcpyHostToDevice)) != hipSuccess) return e;
     st.cur = 0;
-    return hipFuncSetAttribute(kernel_for(plan.n_species, plan.cpl),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
+    for (bool record : {false, true})
+        if ((e = hipFuncSetAttribute(kernel_for(plan.n_species, plan.cpl, record),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)plan.lds_bytes)) != hipSuccess)
+            return e;
+    return hipSuccess;
+}
+
+hipError_t tiled_set_record(TiledState& st, float* tape, uint32_t n0, hipStream_t stream) {
+    struct {
+        float* record;
+        uint32_t record_n0;
+    } rec = {tape, n0};
+    st.recording = tape != nullptr;
+    static_assert(offsetof(TiledArgs2D, record_n0) == offsetof(TiledArgs2D, record) + sizeof(float*),
+                  "record and record_n0 are adjacent");
+    hipError_t e = hipMemcpyAsync((char*)st.table + offsetof(TiledArgs2D, record), &rec,
+                                  sizeof(float*) + sizeof(uint32_t), hipMemcpyHostToDevice,
+                                  stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(stream);
 }
 
 hipError_t tiled_set_launch_state(TiledState& st, uint32_t step, int parity, hipStream_t stream) {
@@ -1144,7 +1197,7 @@ hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStr
     LaunchState* ls = st.launch;
     int persistent = 0;
     void* args[] = {&table, &items, &base, &n_base, &item_cap, &steps, &ls, &persistent};
-    const hipError_t e = hipExtLaunchKernel(kernel_for(plan.n_species, plan.cpl),
+    const hipError_t e = hipExtLaunchKernel(kernel_for(plan.n_species, plan.cpl, st.recording),
                                             dim3(item_cap), dim3(kThreads), args,
                                             plan.lds_bytes, stream, start, stop, 0);
     if (e == hipSuccess) st.cur ^= 1;

@@ -42,6 +42,8 @@ struct AdjointRun {
     float* weight = nullptr;            // [M]
     float* acone = nullptr;             // [M][3]
     double* loss_partial = nullptr;     // [cone workgroups]
+    float* tape = nullptr;              // [n_steps + 1][n_species][n_cells]: every field state
+                                        // of the run, recorded as it ran (null: not recorded)
 };
 
 struct sim_handle {
@@ -102,7 +104,9 @@ struct sim_handle {
     std::vector<int32_t> src_merged_cell[SIM_MAX_SPECIES];   // merged, sorted by cell
     std::vector<float> src_merged_q[SIM_MAX_SPECIES];        // their amounts / dx^dim
     AdjointRun* adj = nullptr;
-    int64_t adj_tape_limit = 0;   // bytes the reverse sweep may record (0: half the free memory)
+    int64_t adj_tape_limit = 0;   // bytes the gradient may record (0: half the free memory)
+    float* record = nullptr;      // recording a run (per-step path): tape of its field states
+    int64_t record_n0 = 0;        // step of the tape's first state
     GraphBuffers graph = {};                                 // last sim_connectivity
     int graph_cones = 0;
 
@@ -177,6 +181,7 @@ void adjoint_release(sim_handle* h) {
     dfree(a->weight);
     dfree(a->acone);
     dfree(a->loss_partial);
+    dfree(a->tape);
     delete a;
     h->adj = nullptr;
 }
@@ -397,6 +402,12 @@ sim_status plain_step(sim_handle* h) {
     else
         HIP_TRY(h, launch_field2d_rows(h->field2d, in, out, h->coef, h->stream, t0, t1));
     for (int s = 0; s < h->n_species; ++s) h->cur[s] ^= 1;
+    if (h->record)   // recording a run: the new state goes to the tape
+        for (int s = 0; s < h->n_species; ++s)
+            HIP_TRY(h, hipMemcpyAsync(h->record + ((size_t)(h->step + 1 - h->record_n0) *
+                                                       h->n_species + s) * h->n_cells,
+                                      h->field[s][h->cur[s]], (size_t)h->n_cells * 4,
+                                      hipMemcpyDeviceToDevice, h->stream));
     const float* f0 = h->field[0][h->cur[0]];
     const float* f1 = h->n_species > 1 ? h->field[1][h->cur[1]] : f0;
     if (h->dim == 2) {
@@ -997,11 +1008,11 @@ const char* sim_last_error(const sim_handle* h) {
 // ------------------------------------------------------------------------------------
 namespace {
 
-int64_t cone_blocks(const sim_handle* h) { return adjoint_cone_blocks(std::max(h->n_cones, 1)); }
+static int64_t cone_blocks(const sim_handle* h) { return adjoint_cone_blocks(std::max(h->n_cones, 1)); }
 
 // Loss seed from the current (final) cone state: a_p = 2 w (p - t), a_theta = 0; the
 // per-workgroup loss partials are left in adj->loss_partial.
-sim_status adjoint_seed(sim_handle* h) {
+static sim_status adjoint_seed(sim_handle* h) {
     sim_status st = unbucket(h);
     if (st != SIM_OK) return st;
     AdjointRun* a = h->adj;
@@ -1009,6 +1020,33 @@ sim_status adjoint_seed(sim_handle* h) {
                                      a->loss_partial, h->n_cones, h->stream));
     return SIM_OK;
 }
+
+// Bytes of every field state of a run of n_steps, of its cone states and of one segment's
+// sample sums: what the gradient needs to re-run the cones of the whole run once.
+static size_t adjoint_whole_bytes(const sim_handle* h, int64_t n_steps, int64_t every) {
+    const size_t ns = (size_t)h->n_species, cells = (size_t)h->n_cells;
+    const int64_t K = std::min<int64_t>(every, std::max<int64_t>(n_steps, 1));
+    return ((size_t)(n_steps + 1) * ns * cells + (size_t)K * ns * cells) * 4 +
+           (size_t)n_steps * std::max<size_t>((size_t)h->n_cones, 1) * 16;
+}
+
+// The handle's tape limit (sim_adjoint_set_tape_limit), or half the free device memory.
+static size_t adjoint_tape_limit(const sim_handle* h) {
+    if (h->adj_tape_limit > 0) return (size_t)h->adj_tape_limit;
+    size_t free_bytes = 0, total_bytes = 0;
+    if (hipMemGetInfo(&free_bytes, &total_bytes) != hipSuccess) free_bytes = 0;
+    return free_bytes / 2;
+}
+
+// Ends the recording of a run's field states (both paths) when it goes out of scope.
+struct RecordGuard {
+    sim_handle* h = nullptr;
+    ~RecordGuard() {
+        if (!h) return;
+        h->record = nullptr;
+        if (h->block_steps > 1) (void)tiled_set_record(h->tiled, nullptr, 0, h->stream);
+    }
+};
 
 }  // namespace
 
@@ -1063,6 +1101,25 @@ sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_ev
         HIP_TRY(h, hipMemcpyAsync(a->tip_target, tips.data(), Ms * 2 * 4, hipMemcpyHostToDevice,
                                   h->stream));
         HIP_TRY(h, hipMemcpyAsync(a->weight, weight, Ms * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    // When the whole run's states fit the tape limit, record every field state as the run
+    // goes (the reverse sweep then re-runs only the cone steps); if the tape cannot be had,
+    // the sweep re-runs the fields from the checkpoints instead.
+    RecordGuard recording;
+    if (a->n_ckpt > 1 && adjoint_whole_bytes(h, n_steps, checkpoint_every) < adjoint_tape_limit(h)) {
+        if (dalloc(&a->tape, (size_t)(n_steps + 1) * ns * cells) != hipSuccess) {
+            (void)hipGetLastError();
+            a->tape = nullptr;
+        } else {
+            for (size_t s = 0; s < ns; ++s)
+                HIP_TRY(h, hipMemcpyAsync(a->tape + s * cells, h->field[s][h->cur[s]], cells * 4,
+                                          hipMemcpyDeviceToDevice, h->stream));
+            recording.h = h;
+            h->record = a->tape;
+            h->record_n0 = h->step;
+            if (h->block_steps > 1)
+                HIP_TRY(h, tiled_set_record(h->tiled, a->tape, (uint32_t)h->step, h->stream));
+        }
     }
     for (int j = 0; j < a->n_ckpt; ++j) {
         sim_status st = unbucket(h);
@@ -1128,14 +1185,12 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     // one thread per (segment, cone), instead of segment after segment.
     const int n_seg = a->n_ckpt;
     const int64_t n_run = a->n_steps;
-    size_t free_bytes = 0, total_bytes = 0;
-    if (hipMemGetInfo(&free_bytes, &total_bytes) != hipSuccess) free_bytes = 0;
-    const size_t whole_bytes = ((size_t)(n_run + 1) * ns * cells + (size_t)K * ns * cells) * 4 +
-                               (size_t)n_run * std::max<size_t>(Ms, 1) * 16;
-    const size_t tape_limit = h->adj_tape_limit > 0 ? (size_t)h->adj_tape_limit : free_bytes / 2;
-    const bool whole = n_seg > 1 && whole_bytes < tape_limit;
+    // the run recorded its field states (sim_adjoint_run): only the cone steps are re-run
+    const bool recorded = a->tape != nullptr;
+    const bool whole = recorded ||
+                       (n_seg > 1 && adjoint_whole_bytes(h, n_run, a->every) < adjoint_tape_limit(h));
     const int64_t window = whole ? n_run : K;
-    float* tape = nullptr;
+    float* tape_own = nullptr;   // the window's field states when the run did not record them
     float4* tape_cones = nullptr;
     long long* scatter = nullptr;   // fixed-point sample adjoints [K][species][cells]
     int32_t* rec_at = nullptr;      // one segment's sample records [K][M][species][12]
@@ -1147,7 +1202,7 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     int32_t* q_start = nullptr;
     int32_t* q_index = nullptr;
     auto free_all = [&]() {
-        dfree(tape);
+        dfree(tape_own);
         dfree(tape_cones);
         dfree(scatter);
         dfree(rec_at);
@@ -1172,7 +1227,7 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     }
     hipError_t e;
     const size_t acc_n = (size_t)2 * ns * fb + (size_t)std::max(nq_all, 1);
-    if ((e = dalloc(&tape, (size_t)(window + 1) * ns * cells)) != hipSuccess ||
+    if ((!recorded && (e = dalloc(&tape_own, (size_t)(window + 1) * ns * cells)) != hipSuccess) ||
         (e = dalloc(&tape_cones, (size_t)window * std::max<size_t>(Ms, 1))) != hipSuccess ||
         (e = dalloc(&scatter, (size_t)K * ns * cells)) != hipSuccess ||
         (e = dalloc(&rec_at, (size_t)K * std::max<size_t>(Ms, 1) * ns * 12)) != hipSuccess ||
@@ -1216,6 +1271,7 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         return st;
     }
     int64_t t_base = 0;   // run step whose field state is at the start of the window
+    float* const tape = recorded ? a->tape : tape_own;
     auto field_at = [&](int64_t t, int s) {
         return tape + ((size_t)(t - t_base) * ns + s) * cells;
     };
@@ -1224,7 +1280,12 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     auto afield_at = [&](int s, int half) { return afield + ((size_t)s * 2 + half) * cells; };
     // re-run the fields of run steps [t0, t0 + len) from the checkpoint of segment j, and
     // the cone steps of segments j .. j + n - 1
+    // (the fields only when the run did not record them)
     auto rerun = [&](int j, int64_t t0, int64_t len, int n) -> hipError_t {
+        if (recorded)
+            return launch_cones_segments2d(h->rules, tape, cells, ns, (int)t_base, j, n,
+                                           a->every, (int)n_run, (uint32_t)a->n0, a->ckpt_pos,
+                                           a->ckpt_dir, a->ckpt_int, M, tape_cones, h->stream);
         hipError_t r = hipMemcpyAsync(field_at(t0, 0), a->ckpt_field + (size_t)j * ns * cells,
                                       (size_t)ns * cells * 4, hipMemcpyDeviceToDevice,
                                       h->stream);

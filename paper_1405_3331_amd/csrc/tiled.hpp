@@ -59,6 +59,8 @@ struct TiledState {
     int2* base = nullptr;                      // (simulation, tile) per tile
     int4* items = nullptr;                     // (simulation, tile, part) of the next launch
     int item_cap = 0;
+    bool recording = false;                    // launches also write every sub-step's state
+                                               // to the run tape (tiled_set_record)
 };
 
 // Choose B and the tile shape; block_steps = 1 in the result means no tiling fits.
@@ -73,6 +75,9 @@ hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
                           ConeArrays cones, hipStream_t stream);
 // Set the device launch state (step counter; parity = input half of the ping-pong pairs).
 hipError_t tiled_set_launch_state(TiledState& st, uint32_t step, int parity, hipStream_t stream);
+// Record mode: while tape is non-null every launch also writes the state after each of its
+// sub-steps to tape + ((step - n0) * n_species + s) * cells (null: off).
+hipError_t tiled_set_record(TiledState& st, float* tape, uint32_t n0, hipStream_t stream);
 void tiled_release(TiledState& st);
 // Move active cones from the caller-order arrays into the tile buckets.
 hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,

@@ -140,8 +140,9 @@ def test_degenerate_cases(block):
 
 @pytest.mark.parametrize("block", BLOCKS)
 def test_crowded_tiles(block):
-    """Thousands of cones per tile: cones held in registers (two slots per thread) and the
-    overflow path that steps further cones from memory, crossing tile borders."""
+    """Thousands of cones per tile: a crowded tile is stepped by several workgroups (parts of
+    512 cones, one per thread, each recomputing the tile's stencil), and cones cross tile
+    borders."""
     sc = S.make_scenario("crowded", 2, (200, 180), 1.0, 0.2, ((1.0, 0.01, 1.0),), 5,
                          (0.5, 2.0), 7000, 30, seed=8)
     _say(f"crowded 200x180, 7000 cones, block_steps={block}")
@@ -227,6 +228,26 @@ def test_headline_size_short_run_elementwise():
     sim, ref, worst = run_pair(sc, 30, block, 15)
     _say(f"worst field {worst['field']:.2e} tip {worst['tip']:.2e}")
     sim.close()
+
+
+def test_headline_size_long_run_tiled_equals_per_step():
+    """At full size over 4000 steps -- long enough for ~16K cones to gather around the
+    sources, so that a handful of tiles are each stepped by several workgroups (512 cones a
+    part) -- the tiled path in bench.py's launch configuration gives bitwise the state of the
+    un-blocked per-step path (separate field and cone kernels, caller-order cones)."""
+    sc = S.headline()
+    block = autotune.apply(sc)
+    _say(f"headline 2048^2, 4000 steps, tiled (block_steps {block}) vs per-step")
+    tiled = B.Simulation(sc, block_steps=block).step(4000)
+    plain = B.Simulation(sc, block_steps=1).step(4000)
+    assert np.array_equal(tiled.field(), plain.field())
+    ct, cp = tiled.cones(), plain.cones()
+    for k in ct:
+        assert np.array_equal(ct[k], cp[k]), k
+    counts = tiled.counts()
+    _say(f"active {counts[0]}, contact {counts[1]}, exited {counts[2]}")
+    tiled.close()
+    plain.close()
 
 
 def test_headline_size_long_run_mass():
