@@ -232,7 +232,9 @@ sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_ev
 /* Reverse sweep of the last sim_adjoint_run (the handle must not have been stepped since;
  * SIM_ESTATE otherwise).  Writes host arrays dL_dq[sum of n_sources] (species 0's sources
  * in the caller's order, then species 1's), dL_dD[n_species] and dL_dk[n_species].  May be
- * called again for the same record.  Synchronises the stream. */
+ * called again for the same record: its device workspace is allocated by the first call and
+ * kept, with the record, until the next sim_adjoint_run or sim_destroy.  Synchronises the
+ * stream. */
 sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, double* dL_dk);
 
 /* Device memory (bytes) that the gradient may spend on recorded states: every field state

@@ -44,7 +44,25 @@ struct AdjointRun {
     double* loss_partial = nullptr;     // [cone workgroups]
     float* tape = nullptr;              // [n_steps + 1][n_species][n_cells]: every field state
                                         // of the run, recorded as it ran (null: not recorded)
+    // The reverse sweep's workspace, allocated by its first call and kept for further calls
+    // on the same record (freed with the record).
+    struct Work {
+        bool ready = false;
+        bool whole = false;             // the window is the whole run (else one segment)
+        float* tape_own = nullptr;      // the window's field states when the run did not record
+        float4* tape_cones = nullptr;   // the cone state at every step of the window
+        long long* scatter = nullptr;   // fixed-point sample adjoints [K][species][cells]
+        int32_t* rec_at = nullptr;      // one segment's sample records [K][M][species][12]
+        float* rec_v = nullptr;
+        uint32_t* step_max = nullptr;   // [K]
+        float* afield = nullptr;        // the field adjoint, ping-pong per species
+        double* acc = nullptr;          // FP64 accumulators
+        int32_t* q_cell = nullptr;      // source cells, and the sources listed per box
+        int32_t* q_start = nullptr;
+        int32_t* q_index = nullptr;
+    } work;
 };
+
 
 struct sim_handle {
     // geometry and coefficients
@@ -170,6 +188,21 @@ void drop_events(sim_handle* h) {
     h->events.clear();
 }
 
+static void adjoint_work_release(AdjointRun::Work& w) {
+    dfree(w.tape_own);
+    dfree(w.tape_cones);
+    dfree(w.scatter);
+    dfree(w.rec_at);
+    dfree(w.rec_v);
+    dfree(w.step_max);
+    dfree(w.afield);
+    dfree(w.acc);
+    dfree(w.q_cell);
+    dfree(w.q_start);
+    dfree(w.q_index);
+    w = AdjointRun::Work();
+}
+
 void adjoint_release(sim_handle* h) {
     AdjointRun* a = h->adj;
     if (!a) return;
@@ -182,6 +215,7 @@ void adjoint_release(sim_handle* h) {
     dfree(a->acone);
     dfree(a->loss_partial);
     dfree(a->tape);
+    adjoint_work_release(a->work);
     delete a;
     h->adj = nullptr;
 }
@@ -1187,33 +1221,26 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     const int64_t n_run = a->n_steps;
     // the run recorded its field states (sim_adjoint_run): only the cone steps are re-run
     const bool recorded = a->tape != nullptr;
-    const bool whole = recorded ||
-                       (n_seg > 1 && adjoint_whole_bytes(h, n_run, a->every) < adjoint_tape_limit(h));
+    AdjointRun::Work& w = a->work;
+    const bool fresh = !w.ready;   // first sweep of this record: allocate the workspace
+    if (fresh)
+        w.whole = recorded || (n_seg > 1 &&
+                               adjoint_whole_bytes(h, n_run, a->every) < adjoint_tape_limit(h));
+    const bool whole = w.whole;
     const int64_t window = whole ? n_run : K;
-    float* tape_own = nullptr;   // the window's field states when the run did not record them
-    float4* tape_cones = nullptr;
-    long long* scatter = nullptr;   // fixed-point sample adjoints [K][species][cells]
-    int32_t* rec_at = nullptr;      // one segment's sample records [K][M][species][12]
-    float* rec_v = nullptr;
-    uint32_t* step_max = nullptr;   // [K]
-    float* afield = nullptr;
-    double* acc = nullptr;
-    int32_t* q_cell = nullptr;
-    int32_t* q_start = nullptr;
-    int32_t* q_index = nullptr;
-    auto free_all = [&]() {
-        dfree(tape_own);
-        dfree(tape_cones);
-        dfree(scatter);
-        dfree(rec_at);
-        dfree(rec_v);
-        dfree(step_max);
-        dfree(afield);
-        dfree(acc);
-        dfree(q_cell);
-        dfree(q_start);
-        dfree(q_index);
-    };
+    float*& tape_own = w.tape_own;
+    float4*& tape_cones = w.tape_cones;
+    long long*& scatter = w.scatter;
+    int32_t*& rec_at = w.rec_at;
+    float*& rec_v = w.rec_v;
+    uint32_t*& step_max = w.step_max;
+    float*& afield = w.afield;
+    double*& acc = w.acc;
+    int32_t*& q_cell = w.q_cell;
+    int32_t*& q_start = w.q_start;
+    int32_t*& q_index = w.q_index;
+    // on a device error the workspace is dropped (the next call allocates it again)
+    auto free_all = [&]() { adjoint_work_release(w); };
     // each species' sources listed by the box of the two-step kernel that holds their cell:
     // q_start[s * (nbp + 1) + box] indexes q_index (source numbers within the species)
     const int nbp = adjoint_pair_blocks(nx, ny);
@@ -1225,9 +1252,10 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
             q_start_h[(size_t)s * (nbp + 1) + b] = st[b] + (int32_t)q_index_h.size();
         q_index_h.insert(q_index_h.end(), ix.begin(), ix.end());
     }
-    hipError_t e;
+    hipError_t e = hipSuccess;
     const size_t acc_n = (size_t)2 * ns * fb + (size_t)std::max(nq_all, 1);
-    if ((!recorded && (e = dalloc(&tape_own, (size_t)(window + 1) * ns * cells)) != hipSuccess) ||
+    if (fresh &&
+        ((!recorded && (e = dalloc(&tape_own, (size_t)(window + 1) * ns * cells)) != hipSuccess) ||
         (e = dalloc(&tape_cones, (size_t)window * std::max<size_t>(Ms, 1))) != hipSuccess ||
         (e = dalloc(&scatter, (size_t)K * ns * cells)) != hipSuccess ||
         (e = dalloc(&rec_at, (size_t)K * std::max<size_t>(Ms, 1) * ns * 12)) != hipSuccess ||
@@ -1237,7 +1265,7 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
         (e = dalloc(&acc, acc_n)) != hipSuccess ||
         (e = dalloc(&q_cell, (size_t)std::max(nq_all, 1))) != hipSuccess ||
         (e = dalloc(&q_start, q_start_h.size())) != hipSuccess ||
-        (e = dalloc(&q_index, std::max<size_t>(q_index_h.size(), 1))) != hipSuccess) {
+        (e = dalloc(&q_index, std::max<size_t>(q_index_h.size(), 1))) != hipSuccess)) {
         free_all();
         if (e == hipErrorOutOfMemory)
             return fail(h, SIM_ENOMEM, "adjoint workspace: out of device memory");
@@ -1251,15 +1279,18 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
             return device_fail(h, e_, #expr);                               \
         }                                                                   \
     } while (0)
-    for (int s = 0; s < ns; ++s)
-        if (n_q[s] > 0)
-            ADJ_TRY(hipMemcpyAsync(q_cell + q_off[s], h->src_caller_cell[s].data(), n_q[s] * 4,
-                                   hipMemcpyHostToDevice, h->stream));
-    ADJ_TRY(hipMemcpyAsync(q_start, q_start_h.data(), q_start_h.size() * 4,
-                           hipMemcpyHostToDevice, h->stream));
-    if (!q_index_h.empty())
-        ADJ_TRY(hipMemcpyAsync(q_index, q_index_h.data(), q_index_h.size() * 4,
+    if (fresh) {
+        for (int s = 0; s < ns; ++s)
+            if (n_q[s] > 0)
+                ADJ_TRY(hipMemcpyAsync(q_cell + q_off[s], h->src_caller_cell[s].data(),
+                                       n_q[s] * 4, hipMemcpyHostToDevice, h->stream));
+        ADJ_TRY(hipMemcpyAsync(q_start, q_start_h.data(), q_start_h.size() * 4,
                                hipMemcpyHostToDevice, h->stream));
+        if (!q_index_h.empty())
+            ADJ_TRY(hipMemcpyAsync(q_index, q_index_h.data(), q_index_h.size() * 4,
+                                   hipMemcpyHostToDevice, h->stream));
+        w.ready = true;
+    }
     ADJ_TRY(hipMemsetAsync(afield, 0, (size_t)2 * ns * cells * sizeof(float), h->stream));
     ADJ_TRY(hipMemsetAsync(acc, 0, acc_n * sizeof(double), h->stream));
     double* acc_D = acc;
@@ -1351,7 +1382,6 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
                            h->stream));
     ADJ_TRY(hipStreamSynchronize(h->stream));
 #undef ADJ_TRY
-    free_all();
     const double dx2 = h->dx * h->dx;
     for (int s = 0; s < ns; ++s) {
         double sD = 0.0, sk = 0.0;
