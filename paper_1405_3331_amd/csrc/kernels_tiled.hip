@@ -47,6 +47,8 @@ constexpr int kConeSlots = 1;               // cones per thread held in register
 constexpr int kPartCones = kConeSlots * kThreads;   // cones one work item steps
 constexpr size_t kStaticLds = kMaxTileTargets * 16 + 3 * 9 * 4 + 16;   // static LDS per tile
 constexpr int kGuardRows = 4;               // one above and three below each species plane
+constexpr int kXcds = 8;                    // dies (XCDs); workgroup b of a launch runs on die
+                                            // b % kXcds
 
 }  // namespace
 
@@ -711,10 +713,15 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
 // Expand the base items (simulation, tile) into work items (simulation, tile, part), one
 // part per kPartCones cones (at least one per tile), from the tile counts of input half
 // par_in; optionally zero the counts of half par_zero for reuse as the next output.  Run by
-// one whole workgroup.
+// one whole workgroup.  With `by_die` (a launch of one workgroup per item) the list is laid
+// out so that each die gets a contiguous run of the n items, in tile order -- neighbouring
+// tiles, whose overlapping halo rows and columns the die's L2 then fetches once: item q goes
+// to slot (q % per) * kXcds + q / per with per = ceil(n / kXcds), so that workgroup b (on die
+// b % kXcds) takes item (b % kXcds) * per + b / kXcds; slots without an item hold
+// simulation -1, and ls->n_items is the number of slots, kXcds * per.
 __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* __restrict__ base,
                             int n_base, int par_in, int par_zero, bool zero, int4* items,
-                            int item_cap, LaunchState* ls) {
+                            int item_cap, LaunchState* ls, bool by_die) {
     __shared__ int wave_total[kWaves];
     const int per = (n_base + kThreads - 1) / kThreads;
     const int lo = min((int)threadIdx.x * per, n_base), hi = min(lo + per, n_base);
@@ -742,16 +749,24 @@ __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* _
         at += w < wave ? t : 0;
         total += t;
     }
+    // (item_cap includes kXcds slots that a list laid out by die may leave empty)
+    const int n = min(total, by_die ? item_cap - kXcds : item_cap);
+    const int per_die = (n + kXcds - 1) / kXcds;
     for (int k = lo; k < hi; ++k) {
         const TiledArgs2D& a = table[base[k].x];
         const int c = __hip_atomic_load(&a.count[par_in][base[k].y], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
         const int parts = max(1, (c + kPartCones - 1) / kPartCones);
         for (int q = 0; q < parts; ++q, ++at)
-            if (at < item_cap) items[at] = make_int4(base[k].x, base[k].y, q, 0);
+            if (at < n)
+                items[by_die ? (at % per_die) * kXcds + at / per_die : at] =
+                    make_int4(base[k].x, base[k].y, q, 0);
         if (zero) a.count[par_zero][base[k].y] = 0;
     }
-    if (threadIdx.x == 0) ls->n_items = min(total, item_cap);
+    if (by_die)   // the slots that hold no item (at most kXcds - 1, below kXcds * per)
+        for (int b = threadIdx.x; b < kXcds * per_die; b += kThreads)
+            if ((b % kXcds) * per_die + b / kXcds >= n) items[b] = make_int4(-1, 0, 0, 0);
+    if (threadIdx.x == 0) ls->n_items = by_die ? kXcds * per_die : n;
 }
 
 // The step kernel.  Work items are (simulation, tile) pairs; without an item list the
@@ -770,10 +785,11 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
     const int par = ls->parity;
     const int n_items = ls->n_items;
     if (!persistent) {
-        // the item list has one entry per workgroup of the grid: fetch it alongside the
-        // launch state (an entry past n_items is not used)
+        // the item list has one slot per workgroup of the grid, laid out by die
+        // (build_items): fetch it alongside the launch state (a slot past n_items, or one
+        // holding simulation -1, is not used)
         const int4 it = items[blockIdx.x];
-        if ((int)blockIdx.x < n_items)
+        if ((int)blockIdx.x < n_items && it.x >= 0)
             tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, steps, first_step, par);
     } else {
         for (;;) {
@@ -801,7 +817,7 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
                                           __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1;
     __syncthreads();
     if (last_out) {
-        build_items(table, base, n_base, par ^ 1, par, true, items, item_cap, ls);
+        build_items(table, base, n_base, par ^ 1, par, true, items, item_cap, ls, !persistent);
         if (threadIdx.x == 0) {
             ls->exited = 0;
             ls->next = 0;
@@ -816,8 +832,8 @@ __global__ __launch_bounds__(kThreads) void k_build_items(const TiledArgs2D* __r
                                                           int4* items,
                                                           const int2* __restrict__ base,
                                                           int n_base, int item_cap,
-                                                          LaunchState* ls) {
-    build_items(table, base, n_base, ls->parity, 0, false, items, item_cap, ls);
+                                                          LaunchState* ls, int by_die) {
+    build_items(table, base, n_base, ls->parity, 0, false, items, item_cap, ls, by_die != 0);
 }
 
 // Initial bucketing from the caller-order arrays (active cones only).
@@ -1122,13 +1138,15 @@ hipError_t tiled_set_launch_state(TiledState& st, uint32_t step, int parity, hip
 }
 
 int tiled_item_capacity(int n_tiles, int n_cones) {
-    return n_tiles + (n_cones + kPartCones - 1) / kPartCones + 1;
+    // the items, plus the slots a list laid out by die may leave empty
+    return n_tiles + (n_cones + kPartCones - 1) / kPartCones + 1 + kXcds;
 }
 
 hipError_t tiled_build_items(const TiledArgs2D* table, int4* items, const int2* base,
-                             int n_base, int item_cap, LaunchState* launch, hipStream_t stream) {
+                             int n_base, int item_cap, LaunchState* launch, hipStream_t stream,
+                             bool by_die) {
     hipLaunchKernelGGL(k_build_items, dim3(1), dim3(kThreads), 0, stream,
-                       table, items, base, n_base, item_cap, launch);
+                       table, items, base, n_base, item_cap, launch, by_die ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1172,7 +1190,7 @@ hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return tiled_build_items(st.table, st.items, st.base, plan.n_tiles, st.item_cap, st.launch,
-                             stream);
+                             stream, true);
 }
 
 hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,

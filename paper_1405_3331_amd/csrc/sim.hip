@@ -1555,7 +1555,7 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
         h->cones_bucketed = true;
     }
     if ((e = tiled_build_items((const TiledArgs2D*)b->table, b->items, b->base, b->n_base,
-                               b->item_cap, b->launch, b->stream)) != hipSuccess)
+                               b->item_cap, b->launch, b->stream, false)) != hipSuccess)
         return bail(batch_fail(b, SIM_EDEVICE, "work item listing failed"));
     // optional graph of `graph_launches` full-depth launches, replayed by sim_batch_step
     if (graph_launches > 0) {
@@ -1598,7 +1598,7 @@ sim_status sim_batch_step(sim_batch* b, int64_t n_steps) {
     }
     if (rebucketed)
         BATCH_TRY(b, tiled_build_items((const TiledArgs2D*)b->table, b->items, b->base,
-                                       b->n_base, b->item_cap, b->launch, b->stream));
+                                       b->n_base, b->item_cap, b->launch, b->stream, false));
     const int64_t per_graph = (int64_t)b->graph_launches * b->block_steps;
     while (per_graph > 0 && n_steps >= per_graph) {
         BATCH_TRY(b, hipGraphLaunch(b->graph_exec, b->stream));

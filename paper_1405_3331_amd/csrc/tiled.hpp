@@ -102,9 +102,12 @@ hipError_t tiled_launch_batch(const TiledArgs2D* table, int4* items, const int2*
                               hipStream_t stream);
 // Upper bound on the work items of n_tiles tiles holding n_cones cones in total.
 int tiled_item_capacity(int n_tiles, int n_cones);
-// List the work items for the current cone counts (after cones were bucketed).
+// List the work items for the current cone counts (after cones were bucketed); by_die lays
+// the list out for a launch of one workgroup per slot (a contiguous run of tiles per die),
+// else in tile order for the persistent batch launch.
 hipError_t tiled_build_items(const TiledArgs2D* table, int4* items, const int2* base,
-                             int n_base, int item_cap, LaunchState* launch, hipStream_t stream);
+                             int n_base, int item_cap, LaunchState* launch, hipStream_t stream,
+                             bool by_die);
 // Number of workgroups of the persistent batch launch for a given dynamic LDS size.
 int tiled_persistent_grid(size_t lds_bytes);
 // Allow the batch kernel variant lds_bytes of dynamic LDS (call before launching or
