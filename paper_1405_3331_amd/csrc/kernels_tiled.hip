@@ -203,22 +203,27 @@ __device__ __forceinline__ float lane_from_right(float v) {
                                                       0xF, 0xF, false));
 }
 
+// How a tile meets the grid's first and last column (the zero-flux rule: a missing
+// neighbour is the cell itself).  kWallAligned: every lane's segment starts at a multiple of
+// CPL and so does nx, so column 0 can only be a segment's first cell and column nx - 1 a
+// segment's last, and only the neighbours taken from the adjacent lanes need the rule.
+enum ColumnWalls { kNoWall = 0, kWallAligned = 1, kWallAny = 2 };
+
 // New value of the CPL cells of one row from the old rows above (s), at (c) and below (n).
-// Horizontal neighbours across lanes come from the adjacent lanes' registers.  WALLS selects
-// the zero-flux rule for tiles that touch the grid boundary.
-template <int CPL, bool WALLS>
-__device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CPL>::T& s_in,
+// Horizontal neighbours across lanes come from the adjacent lanes' registers.  COLS applies
+// the zero-flux rule at the grid's first and last column; at the first and last row the
+// caller passes the row itself as the missing neighbour.
+template <int CPL, int COLS>
+__device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CPL>::T& s,
                                                            const typename Row<CPL>::T& c,
-                                                           const typename Row<CPL>::T& n_in,
-                                                           int gy, int gx0, int nx, int ny,
-                                                           StencilCoef cf) {
+                                                           const typename Row<CPL>::T& n,
+                                                           int gx0, int nx, StencilCoef cf) {
     using V = typename Row<CPL>::T;
-    const float left = lane_from_left(comp(c, CPL - 1));   // column cx - 1
-    const float right = lane_from_right(comp(c, 0));       // column cx + CPL
-    V s = s_in, n = n_in;
-    if (WALLS) {
-        if (gy == 0) s = c;
-        if (gy == ny - 1) n = c;
+    float left = lane_from_left(comp(c, CPL - 1));   // column cx - 1
+    float right = lane_from_right(comp(c, 0));       // column cx + CPL
+    if (COLS == kWallAligned) {
+        if (gx0 == 0) left = comp(c, 0);
+        if (gx0 + CPL == nx) right = comp(c, CPL - 1);
     }
     V nv;
 #pragma unroll
@@ -226,7 +231,7 @@ __device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CP
         const float ck = comp(c, k);
         float w = k == 0 ? left : comp(c, k - 1);
         float e = k == CPL - 1 ? right : comp(c, k + 1);
-        if (WALLS) {
+        if (COLS == kWallAny) {
             if (gx0 + k == 0) w = ck;
             if (gx0 + k == nx - 1) e = ck;
         }
@@ -246,15 +251,17 @@ __device__ __forceinline__ typename Row<CPL>::T row_update(const typename Row<CP
 // prefetched), so rows are prefetched two ahead with no register moves: a prefetched row
 // is either this strip's, still unmodified, or a neighbour's first row, written only after
 // the barrier (or is never used).  The first and last rows are peeled off, so the loop body
-// has no branches and the LDS wait counter can let prefetches stay in flight.
+// has no branches and the LDS wait counter can let prefetches stay in flight.  A strip
+// never reaches outside the grid's rows; `top` (`bottom`) says that its first (last) row is
+// the grid's first (last), whose missing neighbour is the row itself.
 template <int CPL>
 struct StripEdges {
     typename Row<CPL>::T first, last;
 };
 
-template <int CPL, bool WALLS>
+template <int CPL, int COLS>
 __device__ __forceinline__ StripEdges<CPL> strip_update(float* L, int ybeg, int yend, int cx,
-                                                        int gx0, int y0, int nx, int ny,
+                                                        int gx0, int nx, bool top, bool bottom,
                                                         StencilCoef cf) {
     using V = typename Row<CPL>::T;
     constexpr int W = 64 * CPL;
@@ -262,15 +269,18 @@ __device__ __forceinline__ StripEdges<CPL> strip_update(float* L, int ybeg, int 
     float* wr = L + cx;
     auto load = [&](int yy) { return *(const V*)&rd[yy * W]; };
     auto store = [&](int yy, const V& v) { *(V*)&wr[yy * W] = v; };
-    auto upd = [&](const V& s, const V& c, const V& n, int yy) {
-        return row_update<CPL, WALLS>(s, c, n, y0 + yy, gx0, nx, ny, cf);
+    auto upd = [&](const V& s, const V& c, const V& n, int) {
+        return row_update<CPL, COLS>(s, c, n, gx0, nx, cf);
     };
     StripEdges<CPL> out;
     V A = load(ybeg - 1), Bv = load(ybeg), C = load(ybeg + 1), D = load(ybeg + 2);
     // the strip's first row (returned, written after the barrier)
-    out.first = upd(A, Bv, C, ybeg);
-    out.last = out.first;
-    if (yend - ybeg == 1) return out;
+    if (yend - ybeg == 1) {
+        out.first = upd(top ? Bv : A, Bv, bottom ? Bv : C, ybeg);
+        out.last = out.first;
+        return out;
+    }
+    out.first = upd(top ? Bv : A, Bv, C, ybeg);
     A = load(ybeg + 3);
     // interior rows [ybeg + 1, yend - 1), written in place: a branch-free body of four rows,
     // the registers (Bv, C, D, A) holding rows y - 1 .. y + 2 at its top
@@ -293,16 +303,16 @@ __device__ __forceinline__ StripEdges<CPL> strip_update(float* L, int ybeg, int 
     // 0..3 remaining interior rows, then the last row (returned)
     const int r = yin - y;
     if (r == 0) {
-        out.last = upd(Bv, C, D, y);
+        out.last = upd(Bv, C, bottom ? C : D, y);
     } else if (r == 1) {
         store(y, upd(Bv, C, D, y));
-        out.last = upd(C, D, A, y + 1);
+        out.last = upd(C, D, bottom ? D : A, y + 1);
     } else if (r == 2) {
         const V v0 = upd(Bv, C, D, y);
         Bv = load(y + 3);
         store(y, v0);
         store(y + 1, upd(C, D, A, y + 1));
-        out.last = upd(D, A, Bv, y + 2);
+        out.last = upd(D, A, bottom ? A : Bv, y + 2);
     } else {
         const V v0 = upd(Bv, C, D, y);
         Bv = load(y + 3);
@@ -311,7 +321,7 @@ __device__ __forceinline__ StripEdges<CPL> strip_update(float* L, int ybeg, int 
         C = load(y + 4);
         store(y + 1, v1);
         store(y + 2, upd(D, A, Bv, y + 2));
-        out.last = upd(A, Bv, C, y + 3);
+        out.last = upd(A, Bv, bottom ? Bv : C, y + 3);
     }
     return out;
 }
@@ -499,14 +509,20 @@ __device__ __forceinline__ void store_core(float* const dst[], const TiledArgs2D
     }
 }
 
-// One work item: part `part` of one tile of one simulation for `steps` sub-steps.  Every
-// part of a tile computes the tile's field; part p steps the tile's cones
-// [p * kPartCones, (p + 1) * kPartCones) and only part 0 writes the field back, so a tile
-// crowded with cones is spread over several workgroups.  par selects the input half of
+// Parts of a tile holding c cones when a part takes at most p of them (at least one part
+// per tile).  The tile's cones are shared evenly among its parts (build_items).
+__device__ __forceinline__ int tile_parts(int c, int p) { return max(1, (c + p - 1) / p); }
+
+// One work item: one part of one tile of one simulation for `steps` sub-steps.  Every part
+// of a tile computes the tile's field; each part steps its share of the tile's cones,
+// [first_cone, first_cone + n_cones) with n_cones <= kPartCones, and only the part holding
+// the first cone writes the field back, so a tile crowded with cones is spread over several
+// workgroups.  par selects the input half of
 // every ping-pong pair (fields and cone buckets); the other half is written.
 template <int NS, int CPL, bool RECORD>
-__device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int part, int steps,
-                                          uint32_t first_step, int par) {
+__device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int first_cone,
+                                          int n_cones, int steps, uint32_t first_step,
+                                          int par) {
     using V = typename Row<CPL>::T;
     constexpr int W = 64 * CPL;
     extern __shared__ __align__(16) float lds[];
@@ -517,7 +533,6 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     const float* in[SIM_MAX_SPECIES] = {a.field[0][par], a.field[NS > 1 ? 1 : 0][par]};
     float* out[SIM_MAX_SPECIES] = {a.field[0][par ^ 1], a.field[NS > 1 ? 1 : 0][par ^ 1]};
     float4* const bucket_in = a.bucket[par];
-    int32_t* const count_in = a.count[par];
     float4* const bucket_out = a.bucket[par ^ 1];
     int32_t* const count_out = a.count[par ^ 1];
 
@@ -538,8 +553,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     //    overlaps the tile load.  Every cone of the part stays in registers for the whole
     //    launch: cone i sits in thread i % kThreads, slot i / kThreads (a part holds at
     //    most kPartCones = kConeSlots * kThreads cones).
-    const int first_cone = part * kPartCones;
-    const int n_cones = max(0, min(gbl(count_in)[tile] - first_cone, kPartCones));
+    const bool first_part = first_cone == 0;
     const GlobalPtr<const float4> live = gbl(bucket_in) + (size_t)tile * a.capacity + first_cone;
     const int t_lo = gbl(a.tgt_start)[tile], n_tt = gbl(a.tgt_start)[tile + 1] - t_lo;
     const TileContact contact{tile_targets, n_tt, n_tt <= kMaxTileTargets, &a.rules.targets};
@@ -587,10 +601,13 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     }
     __syncthreads();
 
-    // Strips of rows per wavefront, balanced against the cone work: a wavefront stepping
-    // cones in k register slots gives up k * cone_rows rows to the others, so that every
-    // wavefront does about the same work between two barriers.  Boundaries are computed
-    // for every wavefront in scalar registers and kept monotone.
+    // Strips of the tile's rows inside the grid, [r0, r1), per wavefront, balanced against
+    // the cone work: a wavefront stepping cones in k register slots gives up
+    // k * cone_rows rows to the others, so that every wavefront does about the same work
+    // between two barriers.  Boundaries are computed for every wavefront in scalar registers
+    // and kept monotone.  Rows outside the grid are never computed: no cell inside the grid
+    // reads them (at the grid's first and last row the missing neighbour is the row itself).
+    const int r0 = max(0, -y0), r1 = min(HL, a.ny - y0);
     int ybeg = 0, yend = 0;
     {
         int cw[kConeSlots];   // wavefronts holding a cone in slot k
@@ -600,22 +617,22 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
             cw[k] = min(kWaves, (max(n_cones - k * kThreads, 0) + 63) / 64);
             slots += cw[k];
         }
-        const float per = (float)(HL + a.cone_rows * slots) / kWaves;
-        int prev = 0;
+        const float per = (float)(r1 - r0 + a.cone_rows * slots) / kWaves;
+        int prev = r0;
         for (int w = 1; w <= kWaves; ++w) {
             int used = 0;
 #pragma unroll
             for (int k = 0; k < kConeSlots; ++k) used += a.cone_rows * min(w, cw[k]);
-            const int b = w == kWaves ? HL : min(max((int)rintf(w * per) - used, prev), HL);
+            const int b = w == kWaves ? r1 : min(max(r0 + (int)rintf(w * per) - used, prev), r1);
             if (w == wave) ybeg = b;       // wavefront w's strip is [b(w), b(w + 1))
             if (w == wave + 1) yend = b;
             prev = b;
         }
-        if (wave == 0) ybeg = 0;
+        if (wave == 0) ybeg = r0;
     }
     const int src_lo = gbl(a.src_start)[tile], src_hi = gbl(a.src_start)[tile + 1];
     const ConeRules& rules = a.rules;
-    const bool walls = x0 <= 0 || x0 + W >= a.nx || y0 <= 0 || y0 + HL >= a.ny;
+    const int cols = x0 > 0 && x0 + W < a.nx ? kNoWall : aligned ? kWallAligned : kWallAny;
     const LdsField2D f0{lds + W, x0, y0, W, HL};
     const LdsField2D f1{lds + (NS > 1 ? plane : 0) + W, x0, y0, W, HL};
 
@@ -624,16 +641,21 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
         //    [b + 1, HL - b - 1) are still valid (each sub-step loses one row at either
         //    edge of the tile), so rows outside that band are not computed.
         const int lo = max(ybeg, b + 1), hi = min(yend, HL - b - 1);
+        const bool top = lo == -y0, bottom = hi == a.ny - y0;
         StripEdges<CPL> edge[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (lo < hi) {
-                if (walls)
-                    edge[s] = strip_update<CPL, true>(lds + s * plane + W, lo, hi, cx, gx0, y0,
-                                                      a.nx, a.ny, a.coef[s]);
+                float* const L = lds + s * plane + W;
+                if (cols == kNoWall)
+                    edge[s] = strip_update<CPL, kNoWall>(L, lo, hi, cx, gx0, a.nx, top, bottom,
+                                                         a.coef[s]);
+                else if (cols == kWallAligned)
+                    edge[s] = strip_update<CPL, kWallAligned>(L, lo, hi, cx, gx0, a.nx, top,
+                                                              bottom, a.coef[s]);
                 else
-                    edge[s] = strip_update<CPL, false>(lds + s * plane + W, lo, hi, cx, gx0, y0,
-                                                       a.nx, a.ny, a.coef[s]);
+                    edge[s] = strip_update<CPL, kWallAny>(L, lo, hi, cx, gx0, a.nx, top, bottom,
+                                                          a.coef[s]);
             }
         }
         __syncthreads();
@@ -653,7 +675,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
         }
         // recording a run: the state after this sub-step goes to the tape (read from LDS
         // before the next sub-step's in-place update, hence the barrier)
-        if (RECORD && part == 0) {
+        if (RECORD && first_part) {
             const size_t cells = (size_t)a.nx * a.ny;
             const size_t at = (size_t)(first_step + (uint32_t)b + 1u - a.record_n0) * NS;
             float* tape[SIM_MAX_SPECIES] = {a.record + at * cells,
@@ -678,7 +700,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     }
 
     // 5. write the core back (one part per tile does)
-    if (part == 0) store_core<NS, CPL>(out, a, tx, ty, plane, cx, wave, aligned);
+    if (first_part) store_core<NS, CPL>(out, a, tx, ty, plane, cx, wave, aligned);
 
     // 6. re-bucket surviving cones, straight from registers, into the tile that now holds
     //    their tip (one of the 3 x 3 tiles around this one)
@@ -710,30 +732,78 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int pa
     }
 }
 
-// Expand the base items (simulation, tile) into work items (simulation, tile, part), one
-// part per kPartCones cones (at least one per tile), from the tile counts of input half
-// par_in; optionally zero the counts of half par_zero for reuse as the next output.  Run by
-// one whole workgroup.  With `by_die` (a launch of one workgroup per item) the list is laid
+// Candidate part sizes of a list laid out by die, largest first.  Only tiles of more than
+// the smallest candidate's cones can need more than one part under any of them.
+constexpr int kCand = 5;
+__device__ __forceinline__ int candidate_size(int j) {
+    return j == 0 ? kPartCones : j == 1 ? 384 : j == 2 ? 320 : j == 3 ? 256 : 192;
+}
+static_assert(kPartCones == 512, "candidate part sizes assume 512-cone parts");
+
+// Parts of a tile of c cones under candidate j (constant divisors: no integer division).
+__device__ __forceinline__ int candidate_parts(int c, int j) {
+    switch (j) {
+        case 1: return tile_parts(c, 384);
+        case 2: return tile_parts(c, 320);
+        case 3: return tile_parts(c, 256);
+        case 4: return tile_parts(c, 192);
+        default: return tile_parts(c, kPartCones);
+    }
+}
+
+// Expand the base items (simulation, tile) into work items (simulation, tile, first cone,
+// cones), one per part of a tile, from the tile counts of input half par_in; optionally zero
+// the counts of half par_zero for reuse as the next output.  Run by one whole workgroup.
+//
+// BY_DIE (a launch of one workgroup per item): the part size is the smallest candidate whose
+// list still fits ls->slots (the workgroups resident at once), so that the spare slots carry
+// the crowded tiles' cones in more, smaller parts and every item still starts at once.  The
+// extra parts of each candidate are counted in `extra` (kCand ints of LDS that the caller
+// has zeroed before a barrier) by the few threads whose tile is crowded.  The list is laid
 // out so that each die gets a contiguous run of the n items, in tile order -- neighbouring
 // tiles, whose overlapping halo rows and columns the die's L2 then fetches once: item q goes
 // to slot (q % per) * kXcds + q / per with per = ceil(n / kXcds), so that workgroup b (on die
 // b % kXcds) takes item (b % kXcds) * per + b / kXcds; slots without an item hold
-// simulation -1, and ls->n_items is the number of slots, kXcds * per.
+// simulation -1, and ls->n_items is the number of slots, kXcds * per.  Otherwise (a
+// persistent launch, whose queue balances itself) parts take up to kPartCones cones.
+template <bool BY_DIE>
 __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* __restrict__ base,
                             int n_base, int par_in, int par_zero, bool zero, int4* items,
-                            int item_cap, LaunchState* ls, bool by_die) {
+                            int item_cap, LaunchState* ls, int* extra) {
     __shared__ int wave_total[kWaves];
+    const int slots = BY_DIE ? ls->slots : 0;   // issued early, beside the count loads
     const int per = (n_base + kThreads - 1) / kThreads;
     const int lo = min((int)threadIdx.x * per, n_base), hi = min(lo + per, n_base);
-    int mine = 0;
-    for (int k = lo; k < hi; ++k) {
-        const int c = __hip_atomic_load(&table[base[k].x].count[par_in][base[k].y],
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        mine += max(1, (c + kPartCones - 1) / kPartCones);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto count_of = [&](int k) {
+        return __hip_atomic_load(&table[base[k].x].count[par_in][base[k].y], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    };
+    const int c_lo = lo < hi ? count_of(lo) : 0;   // the first count is kept in a register
+    auto count_at = [&](int k) { return k == lo ? c_lo : count_of(k); };
+
+    int chosen = 0;   // candidate part size in use
+    if (BY_DIE) {
+        for (int k = lo; k < hi; ++k) {
+            const int c = count_at(k);
+            if (c > candidate_size(kCand - 1)) {
+#pragma unroll
+                for (int j = 1; j < kCand; ++j) {
+                    const int e = candidate_parts(c, j) - 1;
+                    if (e > 0) atomicAdd(&extra[j], e);
+                }
+            }
+        }
+        __syncthreads();
+        const int room = slots - n_base;
+#pragma unroll
+        for (int j = 1; j < kCand; ++j)   // the counts grow with j: keep the last that fits
+            if (extra[j] <= room) chosen = j;
     }
+    int mine = 0;
+    for (int k = lo; k < hi; ++k) mine += candidate_parts(count_at(k), chosen);
     // exclusive scan of `mine` over the workgroup: within each wavefront by lane shuffles,
     // then across the wavefronts' totals
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int incl = mine;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -749,29 +819,42 @@ __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* _
         at += w < wave ? t : 0;
         total += t;
     }
-    // (item_cap includes kXcds slots that a list laid out by die may leave empty)
-    const int n = min(total, by_die ? item_cap - kXcds : item_cap);
+    // (item_cap includes kXcds slots that a list laid out by die may leave empty; a list of
+    // parts of up to kPartCones cones always fits, and a smaller size is only chosen when its
+    // list fits ls->slots, which the host keeps within the same bound)
+    const int n = min(total, BY_DIE ? item_cap - kXcds : item_cap);
     const int per_die = (n + kXcds - 1) / kXcds;
+    // item `at` goes to slot r * kXcds + d with (d, r) = (at / per_die, at % per_die) when laid
+    // out by die, stepped along without dividing again
+    int d = BY_DIE ? at / max(per_die, 1) : 0, r = BY_DIE ? at - d * per_die : 0;
     for (int k = lo; k < hi; ++k) {
-        const TiledArgs2D& a = table[base[k].x];
-        const int c = __hip_atomic_load(&a.count[par_in][base[k].y], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-        const int parts = max(1, (c + kPartCones - 1) / kPartCones);
-        for (int q = 0; q < parts; ++q, ++at)
+        const int c = count_at(k);
+        const int parts = candidate_parts(c, chosen);
+        // the tile's cones shared evenly: the first c % parts parts take one more
+        const int each = parts == 1 ? c : c / parts, more = c - each * parts;
+        int first = 0;
+        for (int q = 0; q < parts; ++q, ++at) {
+            const int m = each + (q < more ? 1 : 0);
             if (at < n)
-                items[by_die ? (at % per_die) * kXcds + at / per_die : at] =
-                    make_int4(base[k].x, base[k].y, q, 0);
-        if (zero) a.count[par_zero][base[k].y] = 0;
+                items[BY_DIE ? r * kXcds + d : at] = make_int4(base[k].x, base[k].y, first, m);
+            first += m;
+            if (BY_DIE && ++r == per_die) {
+                r = 0;
+                ++d;
+            }
+        }
+        if (zero) table[base[k].x].count[par_zero][base[k].y] = 0;
     }
-    if (by_die)   // the slots that hold no item (at most kXcds - 1, below kXcds * per)
+    if (BY_DIE)   // the slots that hold no item (at most kXcds - 1, below kXcds * per)
         for (int b = threadIdx.x; b < kXcds * per_die; b += kThreads)
             if ((b % kXcds) * per_die + b / kXcds >= n) items[b] = make_int4(-1, 0, 0, 0);
-    if (threadIdx.x == 0) ls->n_items = by_die ? kXcds * per_die : n;
+    if (threadIdx.x == 0) ls->n_items = BY_DIE ? kXcds * per_die : n;
 }
 
-// The step kernel.  Work items are (simulation, tile) pairs; without an item list the
-// item is (0, blockIdx.x).  In persistent mode a fixed grid pulls items from an atomic
-// queue until it runs dry.  The launch state (step counter, ping-pong parity) is read by
+// The step kernel.  Work items (simulation, tile, first cone, cones) come from the list the
+// previous launch (or k_build_items) wrote: one workgroup per slot of a list laid out by
+// die, or, in persistent mode, a fixed grid pulling items from an atomic queue until it
+// runs dry.  The launch state (step counter, ping-pong parity) is read by
 // every workgroup at its start and advanced by the last workgroup to finish, so launches
 // need no host-side bookkeeping and can be captured in a graph and replayed.
 template <int NS, int CPL, bool RECORD>
@@ -781,6 +864,7 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
                                                       LaunchState* ls, int persistent) {
     __shared__ int item_idx;
     __shared__ int last_out;
+    __shared__ int extra_parts[kCand];
     const uint32_t first_step = ls->step;
     const int par = ls->parity;
     const int n_items = ls->n_items;
@@ -790,7 +874,7 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
         // holding simulation -1, is not used)
         const int4 it = items[blockIdx.x];
         if ((int)blockIdx.x < n_items && it.x >= 0)
-            tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, steps, first_step, par);
+            tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, it.w, steps, first_step, par);
     } else {
         for (;;) {
             __syncthreads();   // the previous item is done with LDS and item_idx
@@ -799,7 +883,7 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
             const int i = item_idx;
             if (i >= n_items) break;
             const int4 it = items[i];
-            tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, steps, first_step, par);
+            tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, it.w, steps, first_step, par);
         }
     }
     // The last workgroup to finish lists the next launch's work items from the final tile
@@ -811,13 +895,19 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
     // needed -- an agent-scope fence would write back and invalidate the whole L2 of the
     // chiplet once per workgroup.  Everything else it writes is read by the next launch,
     // after the kernel boundary.
+    if (threadIdx.x < kCand) extra_parts[threadIdx.x] = 0;   // for build_items
     __syncthreads();
     if (threadIdx.x == 0)
         last_out = __hip_atomic_fetch_add(&ls->exited, 1, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1;
     __syncthreads();
     if (last_out) {
-        build_items(table, base, n_base, par ^ 1, par, true, items, item_cap, ls, !persistent);
+        if (persistent)
+            build_items<false>(table, base, n_base, par ^ 1, par, true, items, item_cap, ls,
+                               extra_parts);
+        else
+            build_items<true>(table, base, n_base, par ^ 1, par, true, items, item_cap, ls,
+                              extra_parts);
         if (threadIdx.x == 0) {
             ls->exited = 0;
             ls->next = 0;
@@ -833,7 +923,15 @@ __global__ __launch_bounds__(kThreads) void k_build_items(const TiledArgs2D* __r
                                                           const int2* __restrict__ base,
                                                           int n_base, int item_cap,
                                                           LaunchState* ls, int by_die) {
-    build_items(table, base, n_base, ls->parity, 0, false, items, item_cap, ls, by_die != 0);
+    __shared__ int extra_parts[kCand];
+    if (threadIdx.x < kCand) extra_parts[threadIdx.x] = 0;
+    __syncthreads();
+    if (by_die)
+        build_items<true>(table, base, n_base, ls->parity, 0, false, items, item_cap, ls,
+                          extra_parts);
+    else
+        build_items<false>(table, base, n_base, ls->parity, 0, false, items, item_cap, ls,
+                           extra_parts);
 }
 
 // Initial bucketing from the caller-order arrays (active cones only).
@@ -1093,7 +1191,8 @@ hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
     a.rules = rules;
     if ((e = hipMalloc(&st.table, sizeof(TiledArgs2D))) != hipSuccess) return e;
     if ((e = hipMemcpy(st.table, &a, sizeof a, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    // work items: one per tile plus one per kPartCones further cones in a crowded tile
+    // work items: one per tile plus one per kPartCones further cones in a crowded tile (a
+    // list of smaller parts is used only when it fits the resident workgroups)
     st.item_cap = tiled_item_capacity(plan.n_tiles, n_cones);
     std::vector<int2> base(plan.n_tiles);
     for (int t = 0; t < plan.n_tiles; ++t) base[t] = make_int2(0, t);
@@ -1103,7 +1202,8 @@ hipError_t tiled_allocate(const TiledPlan& plan, TiledState& st, int n_cones,
         return e;
     if ((e = hipMalloc(&st.items, (size_t)st.item_cap * sizeof(int4))) != hipSuccess) return e;
     if ((e = hipMalloc(&st.launch, sizeof(LaunchState))) != hipSuccess) return e;
-    const LaunchState ls0 = {0, 0, 0, 0, 0};
+    const LaunchState ls0 = tiled_launch_state(
+        std::min(tiled_persistent_grid(plan.lds_bytes), st.item_cap - kXcds));
     if ((e = hipMemcpy(st.launch, &ls0, sizeof ls0, hipMemcpyHostToDevice)) != hipSuccess) return e;
     st.cur = 0;
     for (bool record : {false, true})
@@ -1135,6 +1235,12 @@ hipError_t tiled_set_launch_state(TiledState& st, uint32_t step, int parity, hip
     hipError_t e = hipMemcpyAsync(st.launch, head, sizeof head, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(stream);
+}
+
+LaunchState tiled_launch_state(int slots) {
+    LaunchState ls = {};
+    ls.slots = slots;
+    return ls;
 }
 
 int tiled_item_capacity(int n_tiles, int n_cones) {

@@ -1543,7 +1543,7 @@ sim_status sim_batch_create(const sim_params* const* params, int32_t n, void* hi
     if ((e = hipMemcpy(b->base, items.data(), sizeof(int2) * items.size(),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return bail(batch_fail(b, SIM_EDEVICE, "item upload failed"));
-    const LaunchState ls = {0, 0, 0, 0, 0};
+    const LaunchState ls = tiled_launch_state(0);   // a persistent launch lists no slots
     if ((e = hipMemcpy(b->launch, &ls, sizeof ls, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(batch_fail(b, SIM_EDEVICE, "launch state upload failed"));
     if ((e = tiled_prepare_batch(b->n_species, b->cpl, b->lds_bytes)) != hipSuccess)

@@ -39,7 +39,12 @@ struct LaunchState {
     int32_t next;
     int32_t exited;
     int32_t n_items;   // work items of the next launch (listed by the last workgroup)
+    int32_t slots;     // work items a list laid out by die may hold (set by the host)
 };
+
+// Initial launch state; `slots` bounds the work items of a list laid out by die (the
+// workgroups resident at once, and no more than its item capacity allows).
+LaunchState tiled_launch_state(int slots);
 
 struct TiledArgs2D;
 
