@@ -631,6 +631,16 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int fi
         if (wave == 0) ybeg = r0;
     }
     const int src_lo = gbl(a.src_start)[tile], src_hi = gbl(a.src_start)[tile + 1];
+    // the tile's first 64 source entries, one per lane, kept in registers for every sub-step
+    const int n_src = src_hi - src_lo;
+    int src_cell = -1, src_plane = 0;
+    float src_q = 0.0f;
+    if (lane < n_src) {
+        const int2 ent = gload(gbl(a.src_entry) + src_lo + lane);
+        src_cell = ent.x;
+        src_plane = ent.y * plane;
+        src_q = gbl(a.src_amount)[src_lo + lane];
+    }
     const ConeRules& rules = a.rules;
     const int cols = x0 > 0 && x0 + W < a.nx ? kNoWall : aligned ? kWallAligned : kWallAny;
     const LdsField2D f0{lds + W, x0, y0, W, HL};
@@ -664,15 +674,20 @@ __device__ __forceinline__ void tile_body(const TiledArgs2D& a, int tile, int fi
             if (lo < hi) *(V*)&lds[s * plane + (lo + 1) * W + cx] = edge[s].first;
             if (hi - 1 > lo) *(V*)&lds[s * plane + hi * W + cx] = edge[s].last;
         }
-        __syncthreads();
-        // 3. sources inside the tile (entries are unique cells per species)
-        if (src_hi > src_lo) {
-            for (int e = src_lo + threadIdx.x; e < src_hi; e += kThreads) {
+        // 3. sources in this wavefront's rows [lo, hi) (entries are unique cells per
+        //    species; rows no wavefront computes are not valid after this sub-step), added
+        //    after its own edge rows: a wavefront's LDS operations take effect in order, and
+        //    the barrier below publishes them with the rest of the sub-step
+        if (n_src > 0 && lo < hi) {
+            if (src_cell >= 0 && src_cell / W >= lo && src_cell / W < hi)
+                lds[src_plane + W + src_cell] += src_q;
+            for (int e = src_lo + 64 + lane; e < src_hi; e += 64) {
                 const int2 ent = gload(gbl(a.src_entry) + e);
-                lds[ent.y * plane + W + ent.x] += gbl(a.src_amount)[e];
+                const int row = ent.x / W;
+                if (row >= lo && row < hi) lds[ent.y * plane + W + ent.x] += gbl(a.src_amount)[e];
             }
-            __syncthreads();
         }
+        __syncthreads();
         // recording a run: the state after this sub-step goes to the tape (read from LDS
         // before the next sub-step's in-place update, hence the barrier)
         if (RECORD && first_part) {
