@@ -891,14 +891,20 @@ __global__ __launch_bounds__(kThreads) void k_tiled2d(const TiledArgs2D* __restr
         if ((int)blockIdx.x < n_items && it.x >= 0)
             tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, it.w, steps, first_step, par);
     } else {
-        for (;;) {
-            __syncthreads();   // the previous item is done with LDS and item_idx
-            if (threadIdx.x == 0) item_idx = atomicAdd(&ls->next, 1);
-            __syncthreads();
-            const int i = item_idx;
-            if (i >= n_items) break;
+        // the next item is taken from the queue while the current one runs, so the queue's
+        // round trip is hidden behind the item's work
+        if (threadIdx.x == 0) item_idx = atomicAdd(&ls->next, 1);
+        __syncthreads();
+        int i = item_idx;
+        while (i < n_items) {
+            int next = 0;
+            if (threadIdx.x == 0) next = atomicAdd(&ls->next, 1);
             const int4 it = items[i];
             tile_body<NS, CPL, RECORD>(table[it.x], it.y, it.z, it.w, steps, first_step, par);
+            // every thread read item_idx before tile_body's first barrier
+            if (threadIdx.x == 0) item_idx = next;
+            __syncthreads();   // the item is done with LDS; item_idx holds the next index
+            i = item_idx;
         }
     }
     // The last workgroup to finish lists the next launch's work items from the final tile
