@@ -173,15 +173,28 @@ __device__ __forceinline__ float dist2(float dx, float dy, float dz) {
     return dim == 3 ? fmaf(dz, dz, d2) : d2;
 }
 
-// Nearest target in a list (x, y, z, original index as bits), same rule as below.
+// Nearest target in a list (x, y, z, original index as bits), same rule as below.  The
+// smallest squared distance is found first, four targets at a time (the common case: no
+// target within reach, decided with one min per target); only a tip with a target in reach
+// takes the exact pass with the tie rule.  The squared distances are the same expressions in
+// both passes, so the result is that of the exact pass alone.
 template <int dim>
 __device__ __forceinline__ int contact_in_list(const float4* pts, int n, float r2, float x,
                                                float y, float z) {
+    auto d2 = [&](const float4& t) { return dist2<dim>(x - t.x, y - t.y, z - t.z); };
+    float m = r2;
+    int k = 0;
+    for (; k + 4 <= n; k += 4) {
+        const float4 a = pts[k], b = pts[k + 1], c = pts[k + 2], e = pts[k + 3];
+        m = fminf(m, fminf(fminf(d2(a), d2(b)), fminf(d2(c), d2(e))));
+    }
+    for (; k < n; ++k) m = fminf(m, d2(pts[k]));
+    if (!(m < r2)) return -1;
     float best_d2 = r2;
     int best = -1;
-    for (int k = 0; k < n; ++k) {
+    for (k = 0; k < n; ++k) {
         const float4 t = pts[k];
-        closer(dist2<dim>(x - t.x, y - t.y, z - t.z), __float_as_int(t.w), best_d2, best);
+        closer(d2(t), __float_as_int(t.w), best_d2, best);
     }
     return best;
 }
