@@ -779,8 +779,10 @@ __device__ __forceinline__ int candidate_parts(int c, int j) {
 // tiles, whose overlapping halo rows and columns the die's L2 then fetches once: item q goes
 // to slot (q % per) * kXcds + q / per with per = ceil(n / kXcds), so that workgroup b (on die
 // b % kXcds) takes item (b % kXcds) * per + b / kXcds; slots without an item hold
-// simulation -1, and ls->n_items is the number of slots, kXcds * per.  Otherwise (a
-// persistent launch, whose queue balances itself) parts take up to kPartCones cones.
+// simulation -1, and ls->n_items is the number of slots, kXcds * per.  Such a list serves one
+// simulation whose base items are (0, k), so the count arrays are read from table[0] once
+// rather than through base[] and the table for every tile.  Otherwise (a persistent launch,
+// whose queue balances itself) parts take up to kPartCones cones.
 template <bool BY_DIE>
 __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* __restrict__ base,
                             int n_base, int par_in, int par_zero, bool zero, int4* items,
@@ -790,9 +792,11 @@ __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* _
     const int per = (n_base + kThreads - 1) / kThreads;
     const int lo = min((int)threadIdx.x * per, n_base), hi = min(lo + per, n_base);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t* const counts_in = BY_DIE ? table[0].count[par_in] : nullptr;
+    int32_t* const counts_zero = BY_DIE ? table[0].count[par_zero] : nullptr;
     auto count_of = [&](int k) {
-        return __hip_atomic_load(&table[base[k].x].count[par_in][base[k].y], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
+        int32_t* const c = BY_DIE ? counts_in + k : &table[base[k].x].count[par_in][base[k].y];
+        return __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     const int c_lo = lo < hi ? count_of(lo) : 0;   // the first count is kept in a register
     auto count_at = [&](int k) { return k == lo ? c_lo : count_of(k); };
@@ -848,17 +852,22 @@ __device__ void build_items(const TiledArgs2D* __restrict__ table, const int2* _
         // the tile's cones shared evenly: the first c % parts parts take one more
         const int each = parts == 1 ? c : c / parts, more = c - each * parts;
         int first = 0;
+        const int2 bk = BY_DIE ? make_int2(0, k) : base[k];
         for (int q = 0; q < parts; ++q, ++at) {
             const int m = each + (q < more ? 1 : 0);
-            if (at < n)
-                items[BY_DIE ? r * kXcds + d : at] = make_int4(base[k].x, base[k].y, first, m);
+            if (at < n) items[BY_DIE ? r * kXcds + d : at] = make_int4(bk.x, bk.y, first, m);
             first += m;
             if (BY_DIE && ++r == per_die) {
                 r = 0;
                 ++d;
             }
         }
-        if (zero) table[base[k].x].count[par_zero][base[k].y] = 0;
+        if (zero) {
+            if (BY_DIE)
+                counts_zero[k] = 0;
+            else
+                table[bk.x].count[par_zero][bk.y] = 0;
+        }
     }
     if (BY_DIE)   // the slots that hold no item (at most kXcds - 1, below kXcds * per)
         for (int b = threadIdx.x; b < kXcds * per_die; b += kThreads)
