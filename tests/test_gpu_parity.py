@@ -140,14 +140,38 @@ def test_degenerate_cases(block):
 
 @pytest.mark.parametrize("block", BLOCKS)
 def test_crowded_tiles(block):
-    """Thousands of cones per tile: a crowded tile is stepped by several workgroups (parts of
-    512 cones, one per thread, each recomputing the tile's stencil), and cones cross tile
-    borders."""
+    """Thousands of cones per tile: a crowded tile is stepped by several workgroups (its cones
+    shared evenly among parts of at most 512, one cone per thread, each part recomputing the
+    tile's stencil), and cones cross tile borders."""
     sc = S.make_scenario("crowded", 2, (200, 180), 1.0, 0.2, ((1.0, 0.01, 1.0),), 5,
                          (0.5, 2.0), 7000, 30, seed=8)
     _say(f"crowded 200x180, 7000 cones, block_steps={block}")
     sim, ref, _ = run_pair(sc, 120, block, 40)
     sim.close()
+
+
+@pytest.mark.parametrize("block", [3, 12])
+def test_one_crowded_tile_in_small_parts(block):
+    """All 900 cones start within a 24-cell square, so one or two tiles hold them.  The list
+    build then has room for three parts beyond one per tile and shares each crowded tile's
+    cones among parts well under 512 (four of 225 if one tile holds them all, two of 225 each
+    if two do); as the cones spread the part size changes from launch to launch.  The tiled
+    path stays bitwise equal to the un-blocked per-step path."""
+    sc = S.make_scenario("cluster", 2, (512, 448), 1.0, 0.2, ((1.0, 0.01, 1.0),), 6,
+                         (0.5, 2.0), 900, 24, seed=12)
+    rng = np.random.default_rng(12)
+    sc.cone_pos = (np.array([250.0, 230.0]) +
+                   rng.uniform(-12.0, 12.0, size=(900, 2))).astype(sc.cone_pos.dtype)
+    _say(f"one crowded tile, 512x448, 900 cones in a 24-cell square, block_steps={block}")
+    tiled = B.Simulation(sc, block_steps=block).step(150)
+    plain = B.Simulation(sc, block_steps=1).step(150)
+    assert tiled.tiling()["block_steps"] == block
+    assert np.array_equal(tiled.field(), plain.field())
+    ct, cp = tiled.cones(), plain.cones()
+    for k in ct:
+        assert np.array_equal(ct[k], cp[k]), k
+    tiled.close()
+    plain.close()
 
 
 def test_mass_recursion_on_gpu():
@@ -232,8 +256,8 @@ def test_headline_size_short_run_elementwise():
 
 def test_headline_size_long_run_tiled_equals_per_step():
     """At full size over 4000 steps -- long enough for ~16K cones to gather around the
-    sources, so that a handful of tiles are each stepped by several workgroups (512 cones a
-    part) -- the tiled path in bench.py's launch configuration gives bitwise the state of the
+    sources, so that a handful of tiles are each stepped by several workgroups (parts of at
+    most 512 cones) -- the tiled path in bench.py's launch configuration gives bitwise the state of the
     un-blocked per-step path (separate field and cone kernels, caller-order cones)."""
     sc = S.headline()
     block = autotune.apply(sc)
