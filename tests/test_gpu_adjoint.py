@@ -1,5 +1,6 @@
 """Trajectory-loss gradient on the GPU (sim_adjoint_run / sim_adjoint_backward) against
 the FP64 oracle's reverse sweep, checkpoint invariance, error paths and the torch binding."""
+import copy
 import math
 
 import numpy as np
@@ -250,6 +251,21 @@ def test_tiled_forward_and_plain_forward_agree():
     sc = _case(1, seed=9)
     a = _compare(sc, 60, 25, block_steps=1)
     b = _compare(sc, 60, 25, block_steps=8)
+    _same_gradient(a, b, 1e-9)
+
+
+def test_deep_tiled_forward_agrees():
+    """The recording forward run at the depth and tile height the autotuner chose for the
+    gradient workload (16 steps per launch, 110-row tiles), on a grid of several tiles with
+    checkpoints that do not fall on launch boundaries, gives the gradient of the per-step
+    run."""
+    sc = _case(1, n=(300, 260), cones=160, seed=10)
+    deep = copy.copy(sc)
+    deep.tile = (2, 110)
+    with B.Simulation(deep, block_steps=16) as sim:
+        assert sim.tiling()["block_steps"] == 16
+    a = _compare(sc, 70, 30, block_steps=1)
+    b = _compare(deep, 70, 30, block_steps=16)
     _same_gradient(a, b, 1e-9)
 
 
