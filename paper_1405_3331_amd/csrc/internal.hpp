@@ -259,6 +259,17 @@ hipError_t sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t
 
 // Sum of a field in FP64 (deterministic two-pass reduction) into *out (device); when
 // nonfinite is given, a non-finite sum sets *nonfinite = 1 (device).
+// Up to kMaxSpans device-to-device copies of whole 4-byte words in one launch: span k copies
+// word_end[k] - word_end[k - 1] words from src[k] to dst[k] (word_end is cumulative).
+constexpr int kMaxSpans = 8;
+struct CopySpans {
+    const void* src[kMaxSpans];
+    void* dst[kMaxSpans];
+    size_t word_end[kMaxSpans];
+    int n;
+};
+hipError_t launch_copy_spans(const CopySpans& c, hipStream_t stream);
+
 hipError_t launch_mass(const float* field, int64_t n, double* partial, int n_partial,
                        double* out, hipStream_t stream, int32_t* nonfinite = nullptr);
 constexpr int kMassPartials = 1024;

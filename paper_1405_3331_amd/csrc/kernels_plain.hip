@@ -3,6 +3,8 @@
 // FP64 mass of a field.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace cuesim {
@@ -87,7 +89,28 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_final(const double* __res
     }
 }
 
+// Several device-to-device copies in one launch (a checkpoint's field and cone arrays):
+// word w of the concatenated spans, in 4-byte words, by a grid-stride loop.
+__global__ __launch_bounds__(256) void k_copy_spans(CopySpans c) {
+    const size_t total = c.word_end[c.n - 1];
+    for (size_t w = (size_t)blockIdx.x * 256 + threadIdx.x; w < total;
+         w += (size_t)gridDim.x * 256) {
+        int k = 0;
+        while (w >= c.word_end[k]) ++k;
+        const size_t off = w - (k > 0 ? c.word_end[k - 1] : 0);
+        ((uint32_t*)c.dst[k])[off] = ((const uint32_t*)c.src[k])[off];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_copy_spans(const CopySpans& c, hipStream_t stream) {
+    if (c.n <= 0 || c.word_end[c.n - 1] == 0) return hipSuccess;
+    const size_t total = c.word_end[c.n - 1];
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_copy_spans, dim3(blocks), dim3(256), 0, stream, c);
+    return hipGetLastError();
+}
 
 hipError_t launch_cones2d(const ConeRules& rules, const float* f0, const float* f1,
                           ConeArrays cones, uint32_t step, hipStream_t stream) {

@@ -1341,6 +1341,13 @@ hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cone
     return hipSuccess;
 }
 
+hipError_t tiled_sync_cones(const TiledPlan& plan, const TiledState& st, ConeArrays cones,
+                            hipStream_t stream) {
+    hipLaunchKernelGGL(k_unbucket2d, dim3(plan.n_tiles), dim3(256), 0, stream, cones,
+                       st.bucket[st.cur], st.count[st.cur], st.capacity);
+    return hipGetLastError();
+}
+
 hipError_t tiled_launch(const TiledPlan& plan, TiledState& st, int steps, hipStream_t stream,
                         hipEvent_t start, hipEvent_t stop) {
     const TiledArgs2D* table = st.table;

@@ -1156,27 +1156,36 @@ sim_status sim_adjoint_run(sim_handle* h, int64_t n_steps, int32_t checkpoint_ev
         }
     }
     for (int j = 0; j < a->n_ckpt; ++j) {
-        sim_status st = unbucket(h);
-        if (st != SIM_OK) return st;
-        for (size_t s = 0; s < ns; ++s)
-            HIP_TRY(h, hipMemcpyAsync(a->ckpt_field + ((size_t)j * ns + s) * cells,
-                                      h->field[s][h->cur[s]], cells * 4,
-                                      hipMemcpyDeviceToDevice, h->stream));
-        if (M > 0) {
-            HIP_TRY(h, hipMemcpyAsync(a->ckpt_pos + (size_t)j * Ms * 2, h->cones.pos, Ms * 8,
-                                      hipMemcpyDeviceToDevice, h->stream));
-            HIP_TRY(h, hipMemcpyAsync(a->ckpt_dir + (size_t)j * Ms, h->cones.dir, Ms * 4,
-                                      hipMemcpyDeviceToDevice, h->stream));
-            int32_t* ci = a->ckpt_int + (size_t)j * 3 * Ms;
-            HIP_TRY(h, hipMemcpyAsync(ci, h->cones.status, Ms * 4, hipMemcpyDeviceToDevice,
-                                      h->stream));
-            HIP_TRY(h, hipMemcpyAsync(ci + Ms, h->cones.target, Ms * 4, hipMemcpyDeviceToDevice,
-                                      h->stream));
-            HIP_TRY(h, hipMemcpyAsync(ci + 2 * Ms, h->cones.event_step, Ms * 4,
-                                      hipMemcpyDeviceToDevice, h->stream));
+        // the cones' state into the caller-order arrays; tile buckets stay valid, so the run
+        // goes on without bucketing the cones again
+        if (h->cones_bucketed && !h->cones_ordered) {
+            HIP_TRY(h, tiled_sync_cones(h->plan, h->tiled, h->cones, h->stream));
+        } else {
+            sim_status st = unbucket(h);
+            if (st != SIM_OK) return st;
         }
+        // the checkpoint: fields and cone arrays in one copy launch
+        CopySpans cp = {};
+        size_t words = 0;
+        auto span = [&](const void* src, void* dst, size_t bytes) {
+            cp.src[cp.n] = src;
+            cp.dst[cp.n] = dst;
+            words += bytes / 4;
+            cp.word_end[cp.n++] = words;
+        };
+        for (size_t s = 0; s < ns; ++s)
+            span(h->field[s][h->cur[s]], a->ckpt_field + ((size_t)j * ns + s) * cells, cells * 4);
+        if (M > 0) {
+            int32_t* ci = a->ckpt_int + (size_t)j * 3 * Ms;
+            span(h->cones.pos, a->ckpt_pos + (size_t)j * Ms * 2, Ms * 8);
+            span(h->cones.dir, a->ckpt_dir + (size_t)j * Ms, Ms * 4);
+            span(h->cones.status, ci, Ms * 4);
+            span(h->cones.target, ci + Ms, Ms * 4);
+            span(h->cones.event_step, ci + 2 * Ms, Ms * 4);
+        }
+        HIP_TRY(h, launch_copy_spans(cp, h->stream));
         const int64_t len = std::min<int64_t>(checkpoint_every, n_steps - (int64_t)j * checkpoint_every);
-        st = sim_step(h, len);
+        const sim_status st = sim_step(h, len);
         if (st != SIM_OK) return st;
     }
     sim_status st = adjoint_seed(h);

@@ -90,6 +90,10 @@ hipError_t tiled_bucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
 // Move active cones from the tile buckets back into the caller-order arrays.
 hipError_t tiled_unbucket(const TiledPlan& plan, TiledState& st, ConeArrays cones,
                           hipStream_t stream);
+// The same copy of the active cones into the caller-order arrays, leaving the buckets and
+// counts in place, so that stepping continues without bucketing again.
+hipError_t tiled_sync_cones(const TiledPlan& plan, const TiledState& st, ConeArrays cones,
+                            hipStream_t stream);
 // Advance `steps` (<= plan.block_steps) steps in one launch; flips st.cur like the device
 // parity.
 // start/stop (may be null): events the launch records around the kernel (timing).
