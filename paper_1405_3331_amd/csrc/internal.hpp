@@ -178,14 +178,20 @@ hipError_t launch_cones_segments2d(const ConeRules& rules, const float* fields, 
 // Reverse of a segment's cone steps: each cone's gradient samples' adjoints (12 cells per
 // species and step) are written to the segment's records, rec_at / rec_v
 // [len][n][n_species][12]; then the largest |contribution| of every step goes to
-// step_max[len] (cleared by the call) and the records are added into the fixed-point sums
-// e[len][n_species][cells] (cleared by the call) with that step's scale.
+// step_max[len] (cleared by the call).
 hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fields,
                                          size_t cells, int n_species, uint32_t seg0, int len,
                                          int32_t* rec_at, float* rec_v, uint32_t* step_max,
-                                         long long* e, const float4* tape,
-                                         const int32_t* status, const int32_t* event_step,
-                                         float* acone, int n, hipStream_t stream);
+                                         const float4* tape, const int32_t* status,
+                                         const int32_t* event_step, float* acone, int n,
+                                         hipStream_t stream);
+// The records of segment steps t_lo .. t_lo + n_steps - 1 added into their fixed-point sums
+// with each step's scale: step t's sums of species s are e + ((t % ring) * n_species + s) *
+// cells, a ring of `ring` steps whose slots for these steps must hold zeros.
+hipError_t launch_sample_add2d(size_t cells, int n_species, uint32_t seg0, int len, int t_lo,
+                               int n_steps, int ring, const int32_t* rec_at, const float* rec_v,
+                               const uint32_t* step_max, long long* e, const int32_t* status,
+                               const int32_t* event_step, int n, hipStream_t stream);
 // One reverse field step with the sample adjoints of step t: e + (t * n_species) * cells
 // holds the species' fixed-point sums (e points at this species' first step).
 hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const long long* e_in,
@@ -197,7 +203,9 @@ hipError_t launch_field_adjoint2d(int nx, int ny, const float* a_in, const long 
 // fixed-point sums of segment steps t1 / t0),
 // c1/c0 = c^n/c^{n-1}, a_out = a^{n-1}; adjoint_pair_blocks(nx, ny) boxes own acc_D/acc_k
 // slots, and the sources are listed per box (adjoint_pair_sources: q_start[box] ..
-// q_start[box + 1] - 1 index q_index, the source numbers m of q_cell / acc_q).
+// q_start[box + 1] - 1 index q_index, the source numbers m of q_cell / acc_q).  z1 and z0
+// (may be null) are sums of other steps, which the launch sets to zero (each box its own
+// cells); neither may be e1 or e0.
 int adjoint_pair_blocks(int nx, int ny);
 void adjoint_pair_sources(int nx, int ny, const std::vector<int32_t>& cells,
                           std::vector<int32_t>& start, std::vector<int32_t>& index);
@@ -207,7 +215,7 @@ hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const 
                                        StencilCoef coef, double* acc_D, double* acc_k,
                                        const int32_t* q_start, const int32_t* q_index,
                                        const int32_t* q_cell, double* acc_q,
-                                       hipStream_t stream);
+                                       long long* z1, long long* z0, hipStream_t stream);
 hipError_t launch_adjoint_seed2d(const float* pos, const float* tip_target, const float* weight,
                                  float* acone, double* partial, int n, hipStream_t stream);
 

@@ -19,7 +19,11 @@
 //                             64-bit fixed-point sums per step and species, scaled by the
 //                             step's largest contribution: integer additions, so the sums
 //                             (and the whole gradient) do not depend on the order in which
-//                             the cones' contributions arrive;
+//                             the cones' contributions arrive.  The sums are added a few
+//                             steps at a time, just before those steps are reversed, into a
+//                             small ring of per-step buffers that stays in the on-package
+//                             cache (the reverse field launches clear the buffers they are
+//                             done with);
 //   k_field_adjoint2d_rows    (kernels_field2d.hip) one launch per step: with
 //                             b = a^{n+1} + e^{n+1}, a^n = b + r Lap b - k dt b (the
 //                             zero-flux Laplacian is symmetric, so the adjoint stencil is
@@ -325,15 +329,17 @@ __global__ __launch_bounds__(kRecThreads) void k_sample_max(
     if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(&step_max[t], __float_as_uint(m));
 }
 
-// Every (cone, step) record added into the step's fixed-point sums: q = rint(v 2^(40 - e))
-// (the product is an exact power-of-two scaling in FP64), |q| <= 2^40.
+// Every (cone, step) record of steps t_lo .. t_lo + gridDim.y - 1 added into the step's
+// fixed-point sums (slot t % ring of e): q = rint(v 2^(40 - e)) (the product is an exact
+// power-of-two scaling in FP64), |q| <= 2^40.
 template <int NS>
 __global__ __launch_bounds__(kRecThreads) void k_sample_add(
-    Segment2D seg, const int32_t* __restrict__ rec_at, const float* __restrict__ rec_v,
-    const int32_t* __restrict__ status, const int32_t* __restrict__ event_step,
-    const uint32_t* __restrict__ step_max, unsigned long long* __restrict__ e, int n) {
+    Segment2D seg, int t_lo, int ring, const int32_t* __restrict__ rec_at,
+    const float* __restrict__ rec_v, const int32_t* __restrict__ status,
+    const int32_t* __restrict__ event_step, const uint32_t* __restrict__ step_max,
+    unsigned long long* __restrict__ e, int n) {
     const int i = blockIdx.x * kRecThreads + threadIdx.x;
-    const int t = blockIdx.y;
+    const int t = t_lo + blockIdx.y;
     if (i >= n || t > last_step(seg, status, event_step, i)) return;
     const size_t rec = (((size_t)t * n + i) * NS) * 12;
     // the whole record first (16-byte loads, all in flight together), then the additions
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(kRecThreads) void k_sample_add(
     const double scale = ldexp(1.0, kFixedBits - fixed_exponent(step_max[t]));
 #pragma unroll
     for (int k = 0; k < 12 * NS; ++k) {
-        unsigned long long* dst = e + ((size_t)t * NS + k / 12) * seg.cells;
+        unsigned long long* dst = e + ((size_t)(t % ring) * NS + k / 12) * seg.cells;
         const float4 vq = v[k / 4];
         const int4 aq = at[k / 4];
         const float val = k % 4 == 0 ? vq.x : k % 4 == 1 ? vq.y : k % 4 == 2 ? vq.z : vq.w;
@@ -406,35 +412,43 @@ hipError_t launch_cones_segments2d(const ConeRules& rules, const float* fields, 
 hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fields,
                                          size_t cells, int n_species, uint32_t seg0, int len,
                                          int32_t* rec_at, float* rec_v, uint32_t* step_max,
-                                         long long* e, const float4* tape,
-                                         const int32_t* status, const int32_t* event_step,
-                                         float* acone, int n, hipStream_t stream) {
+                                         const float4* tape, const int32_t* status,
+                                         const int32_t* event_step, float* acone, int n,
+                                         hipStream_t stream) {
     if (len == 0) return hipSuccess;
-    hipError_t err = hipMemsetAsync(e, 0, sizeof(long long) * (size_t)len * n_species * cells,
-                                    stream);
+    hipError_t err = hipMemsetAsync(step_max, 0, sizeof(uint32_t) * (size_t)len, stream);
     if (err != hipSuccess || n == 0) return err;
-    if ((err = hipMemsetAsync(step_max, 0, sizeof(uint32_t) * (size_t)len, stream)) !=
-        hipSuccess)
-        return err;
     const Segment2D seg{fields, cells, n_species, seg0, len};
     const dim3 grid((n + kSegThreads - 1) / kSegThreads);
     const dim3 rec_grid((n + kRecThreads - 1) / kRecThreads, len);
-    unsigned long long* eu = (unsigned long long*)e;
     if (n_species > 1) {
         hipLaunchKernelGGL(k_cone_adjoint_segment2d<2>, grid, dim3(kSegThreads), 0, stream,
                            rules, seg, rec_at, rec_v, tape, status, event_step, acone, n);
         hipLaunchKernelGGL(k_sample_max<2>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
                            status, event_step, step_max, n);
-        hipLaunchKernelGGL(k_sample_add<2>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_at,
-                           rec_v, status, event_step, step_max, eu, n);
     } else {
         hipLaunchKernelGGL(k_cone_adjoint_segment2d<1>, grid, dim3(kSegThreads), 0, stream,
                            rules, seg, rec_at, rec_v, tape, status, event_step, acone, n);
         hipLaunchKernelGGL(k_sample_max<1>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
                            status, event_step, step_max, n);
-        hipLaunchKernelGGL(k_sample_add<1>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_at,
-                           rec_v, status, event_step, step_max, eu, n);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_add2d(size_t cells, int n_species, uint32_t seg0, int len, int t_lo,
+                               int n_steps, int ring, const int32_t* rec_at, const float* rec_v,
+                               const uint32_t* step_max, long long* e, const int32_t* status,
+                               const int32_t* event_step, int n, hipStream_t stream) {
+    if (n == 0 || n_steps <= 0) return hipSuccess;
+    const Segment2D seg{nullptr, cells, n_species, seg0, len};
+    const dim3 rec_grid((n + kRecThreads - 1) / kRecThreads, n_steps);
+    unsigned long long* eu = (unsigned long long*)e;
+    if (n_species > 1)
+        hipLaunchKernelGGL(k_sample_add<2>, rec_grid, dim3(kRecThreads), 0, stream, seg, t_lo,
+                           ring, rec_at, rec_v, status, event_step, step_max, eu, n);
+    else
+        hipLaunchKernelGGL(k_sample_add<1>, rec_grid, dim3(kRecThreads), 0, stream, seg, t_lo,
+                           ring, rec_at, rec_v, status, event_step, step_max, eu, n);
     return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@
 //   a box of 256 x 4 cells holds b^{n+1} on the box and a two-cell ring in LDS, takes the
 //   first step on the box and a one-cell ring, adds e^n and takes the second on the box;
 //   per cell and two steps a^{n+1}, e^{n+1}, e^n, c^n, c^{n-1} are read and a^{n-1}
-//   written (12 instead of 16 B per cell and step, and half the launches).
+//   written (12 instead of 16 B per cell and step, and half the launches).  The launch also
+//   clears, on its box, two buffers of sums of steps already reversed, for their reuse.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -330,6 +331,8 @@ struct FieldAdjointPairArgs {
     const int32_t* q_index;   // source numbers m
     const int32_t* q_cell;    // cell of source m
     double* acc_q;
+    long long* z1;            // sums of two other steps set to zero on the box (may be null)
+    long long* z0;
 };
 
 __global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairArgs a) {
@@ -475,6 +478,17 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairAr
         const int ci = cell % nx, cj = cell / nx;
         a.acc_q[m] += (double)b1(ci, cj);
         a.acc_q[m] += (double)b2(ci, cj);
+    }
+    // the box's cells of two finished steps' sums cleared for their next use
+    if (live && a.z1 != nullptr) {
+        const int rows = min(kPY, ny - y0);
+#pragma unroll
+        for (int r = 0; r < kPY; ++r) {
+            if (r >= rows) break;
+            const size_t at = (size_t)(y0 + r) * nx + i;
+            a.z1[at] = 0;
+            a.z0[at] = 0;
+        }
     }
 }
 
@@ -669,7 +683,8 @@ hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const 
                                        StencilCoef coef, double* acc_D, double* acc_k,
                                        const int32_t* q_start, const int32_t* q_index,
                                        const int32_t* q_cell, double* acc_q,
-                                       hipStream_t stream) {
+                                       long long* z1, long long* z0, hipStream_t stream) {
+    if ((z1 == nullptr) != (z0 == nullptr)) return hipErrorInvalidValue;
     const Tiles2D t = tiles_for(nx, ny, kPY);
     FieldAdjointPairArgs a{};
     a.a_in = a_in;
@@ -693,6 +708,8 @@ hipError_t launch_field_adjoint2d_pair(int nx, int ny, const float* a_in, const 
     a.q_index = q_index;
     a.q_cell = q_cell;
     a.acc_q = acc_q;
+    a.z1 = z1;
+    a.z0 = z0;
     hipLaunchKernelGGL(k_field_adjoint2d_pair, dim3(a.per_xcd * kXcds), dim3(kRX), 0, stream,
                        a);
     return hipGetLastError();

@@ -26,6 +26,16 @@ thread_local std::string g_create_error;
 // Steps between refreshes of the spatial order of 3D cones (a cone moves step_len per step;
 // 8, 16, 32 and 64 were measured at 256^3, 32 was fastest).
 constexpr int kOrderRefresh = 32;
+// Gradient sweep: the samples' fixed-point sums are added kSumGroup steps at a time (an even
+// number, so that the two-step reverse launches stay within a group) into a ring of
+// kSumRing = 2 kSumGroup per-step buffers per species; each two-step launch clears the
+// buffers of the group before its own, which the group after it reuses.  At 1024^2 (one
+// species, 100-step segments) groups of 8 steps measured best: 24.1 ms per sweep against
+// 24.9 with 4, 27.0 with 2 and 24.6 with one buffer per step of the segment (800 MiB, cleared
+// per segment); the ring takes 128 MiB.
+constexpr int kSumGroup = 8;
+constexpr int kSumRing = 2 * kSumGroup;
+static_assert(kSumGroup >= 2 && kSumGroup % 2 == 0, "groups of whole step pairs");
 
 }  // namespace
 
@@ -51,7 +61,8 @@ struct AdjointRun {
         bool whole = false;             // the window is the whole run (else one segment)
         float* tape_own = nullptr;      // the window's field states when the run did not record
         float4* tape_cones = nullptr;   // the cone state at every step of the window
-        long long* scatter = nullptr;   // fixed-point sample adjoints [K][species][cells]
+        long long* scatter = nullptr;   // fixed-point sample adjoints, a ring of steps:
+                                        // [kSumRing][species][cells]
         int32_t* rec_at = nullptr;      // one segment's sample records [K][M][species][12]
         float* rec_v = nullptr;
         uint32_t* step_max = nullptr;   // [K]
@@ -1055,12 +1066,12 @@ static sim_status adjoint_seed(sim_handle* h) {
     return SIM_OK;
 }
 
-// Bytes of every field state of a run of n_steps, of its cone states and of one segment's
+// Bytes of every field state of a run of n_steps, of its cone states and of the ring of
 // sample sums: what the gradient needs to re-run the cones of the whole run once.
 static size_t adjoint_whole_bytes(const sim_handle* h, int64_t n_steps, int64_t every) {
+    (void)every;
     const size_t ns = (size_t)h->n_species, cells = (size_t)h->n_cells;
-    const int64_t K = std::min<int64_t>(every, std::max<int64_t>(n_steps, 1));
-    return ((size_t)(n_steps + 1) * ns * cells + (size_t)K * ns * cells) * 4 +
+    return (size_t)(n_steps + 1) * ns * cells * 4 + (size_t)kSumRing * ns * cells * 8 +
            (size_t)n_steps * std::max<size_t>((size_t)h->n_cones, 1) * 16;
 }
 
@@ -1266,7 +1277,7 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     if (fresh &&
         ((!recorded && (e = dalloc(&tape_own, (size_t)(window + 1) * ns * cells)) != hipSuccess) ||
         (e = dalloc(&tape_cones, (size_t)window * std::max<size_t>(Ms, 1))) != hipSuccess ||
-        (e = dalloc(&scatter, (size_t)K * ns * cells)) != hipSuccess ||
+        (e = dalloc(&scatter, (size_t)kSumRing * ns * cells)) != hipSuccess ||
         (e = dalloc(&rec_at, (size_t)K * std::max<size_t>(Ms, 1) * ns * 12)) != hipSuccess ||
         (e = dalloc(&rec_v, (size_t)K * std::max<size_t>(Ms, 1) * ns * 12)) != hipSuccess ||
         (e = dalloc(&step_max, (size_t)K)) != hipSuccess ||
@@ -1315,7 +1326,9 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
     auto field_at = [&](int64_t t, int s) {
         return tape + ((size_t)(t - t_base) * ns + s) * cells;
     };
-    auto scatter_at = [&](int t, int s) { return scatter + ((size_t)t * ns + s) * cells; };
+    auto scatter_at = [&](int t, int s) {
+        return scatter + ((size_t)(t % kSumRing) * ns + s) * cells;
+    };
     int cur = 0;
     auto afield_at = [&](int s, int half) { return afield + ((size_t)s * 2 + half) * cells; };
     // re-run the fields of run steps [t0, t0 + len) from the checkpoint of segment j, and
@@ -1356,34 +1369,48 @@ sim_status sim_adjoint_backward(sim_handle* h, double* dL_dq, double* dL_dD, dou
             t_base = t0;
             ADJ_TRY(rerun(j, t0, len, 1));
         }
-        // the segment's cone adjoints, their samples' adjoints summed per step and cell
+        // the segment's cone adjoints (their samples' adjoints recorded per step)
         ADJ_TRY(launch_cone_adjoint_segment2d(h->rules, field_at(t0, 0), cells, ns,
                                               (uint32_t)(a->n0 + t0), len, rec_at, rec_v,
-                                              step_max, scatter,
+                                              step_max,
                                               tape_cones + (size_t)(t0 - t_base) * Ms,
                                               h->cones.status, h->cones.event_step, a->acone,
                                               M, h->stream));
-        // reverse the segment's field steps, two per launch while two remain
+        ADJ_TRY(hipMemsetAsync(scatter, 0, (size_t)kSumRing * ns * cells * sizeof(long long),
+                               h->stream));
+        // reverse the segment's field steps, two per launch while two remain, in groups of
+        // kSumGroup steps from the last one down: the group's sample sums first
         int t = len - 1;
-        for (; t >= 1; t -= 2) {
-            for (int s = 0; s < ns; ++s)
-                ADJ_TRY(launch_field_adjoint2d_pair(
-                    nx, ny, afield_at(s, cur), scatter_at(t, s), scatter_at(t - 1, s), step_max,
-                    t, t - 1, field_at(t0 + t, s), field_at(t0 + t - 1, s), afield_at(s, cur ^ 1),
-                    h->coef[s], acc_D + (size_t)s * fb, acc_k + (size_t)s * fb,
-                    q_start + (size_t)s * (nbp + 1), q_index, q_cell + q_off[s],
-                    acc_q + q_off[s], h->stream));
-            cur ^= 1;
-        }
-        if (t == 0) {
-            for (int s = 0; s < ns; ++s)
-                ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), scatter_at(t, s),
-                                               step_max, t, field_at(t0 + t, s),
-                                               afield_at(s, cur ^ 1),
-                                               h->coef[s], acc_D + (size_t)s * fb,
-                                               acc_k + (size_t)s * fb, q_cell + q_off[s],
-                                               n_q[s], acc_q + q_off[s], h->stream));
-            cur ^= 1;
+        while (t >= 0) {
+            const int g_lo = std::max(t - kSumGroup + 1, 0);
+            ADJ_TRY(launch_sample_add2d(cells, ns, (uint32_t)(a->n0 + t0), len, g_lo,
+                                        t - g_lo + 1, kSumRing, rec_at, rec_v, step_max,
+                                        scatter, h->cones.status, h->cones.event_step, M,
+                                        h->stream));
+            for (; t >= g_lo + 1; t -= 2) {
+                // the sums of steps t + kSumGroup and t + kSumGroup - 1 (the group before,
+                // already reversed) are cleared for the group after this one
+                for (int s = 0; s < ns; ++s)
+                    ADJ_TRY(launch_field_adjoint2d_pair(
+                        nx, ny, afield_at(s, cur), scatter_at(t, s), scatter_at(t - 1, s),
+                        step_max, t, t - 1, field_at(t0 + t, s), field_at(t0 + t - 1, s),
+                        afield_at(s, cur ^ 1), h->coef[s], acc_D + (size_t)s * fb,
+                        acc_k + (size_t)s * fb, q_start + (size_t)s * (nbp + 1), q_index,
+                        q_cell + q_off[s], acc_q + q_off[s], scatter_at(t + kSumGroup, s),
+                        scatter_at(t + kSumGroup - 1, s), h->stream));
+                cur ^= 1;
+            }
+            if (t == g_lo) {   // the segment's first step, when its length is odd
+                for (int s = 0; s < ns; ++s)
+                    ADJ_TRY(launch_field_adjoint2d(nx, ny, afield_at(s, cur), scatter_at(t, s),
+                                                   step_max, t, field_at(t0 + t, s),
+                                                   afield_at(s, cur ^ 1), h->coef[s],
+                                                   acc_D + (size_t)s * fb,
+                                                   acc_k + (size_t)s * fb, q_cell + q_off[s],
+                                                   n_q[s], acc_q + q_off[s], h->stream));
+                cur ^= 1;
+                --t;
+            }
         }
     }
     std::vector<double> host(acc_n);
