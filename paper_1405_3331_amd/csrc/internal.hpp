@@ -115,7 +115,9 @@ struct ConeOrder3D {
     int32_t* scratch = nullptr;   // counting-sort histograms (sort_pairs)
     int cur = 0;
     int n = 0;
-    int shift = 2;
+    int shift = 3;   // 8-cell Morton cells: 118.2 us per 256^3 step, against 119.1 with 4-cell
+                     // and 118.3 / 119.5 with 16- / 32-cell ones (fewer sort passes, same order
+                     // at the scale of a workgroup's block)
     uint32_t inactive = 0;
     int end_bit = 1;
 };
