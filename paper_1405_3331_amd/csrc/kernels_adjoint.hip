@@ -21,10 +21,10 @@
 //                             (and the whole gradient) do not depend on the order in which
 //                             the cones' contributions arrive.  The sums are added a few
 //                             steps at a time, just before those steps are reversed, into a
-//                             small ring of per-step buffers that stays in the on-package
-//                             cache (the reverse field launches clear the buffers they are
-//                             done with);
-//   k_field_adjoint2d_rows    (kernels_field2d.hip) one launch per step: with
+//                             small ring of per-step buffers (the reverse field launches
+//                             clear the buffers they are done with);
+//   k_field_adjoint2d_pair    (kernels_field2d.hip) two reverse steps per launch, and
+//   k_field_adjoint2d_rows    one for the first step of a segment of odd length: with
 //                             b = a^{n+1} + e^{n+1}, a^n = b + r Lap b - k dt b (the
 //                             zero-flux Laplacian is symmetric, so the adjoint stencil is
 //                             the stencil), and
