@@ -268,7 +268,9 @@ __device__ __forceinline__ int last_step(const Segment2D& seg, const int32_t* st
 
 // Reverse of one segment's cone steps, one thread per cone from the last step to the first;
 // the adjoints of step t's gradient samples are recorded (write_record) for k_sample_add.
-// The state of the step before is loaded one step ahead.
+// The forward states come from the run's cone tape, so the gathers of the step before do
+// not wait for this step's adjoint: its footprints are loaded one step ahead and its state
+// two.
 template <int NS>
 __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
     ConeRules r, Segment2D seg, int32_t* __restrict__ rec_at, float* __restrict__ rec_v,
@@ -280,13 +282,22 @@ __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
     const int t_hi = last_step(seg, status, event_step, i);
     if (t_hi >= 0) {
         float4 st = tape[(size_t)t_hi * n + i];
+        float4 next = tape[(size_t)max(t_hi - 1, 0) * n + i];
+        Footprint2D p0 = footprint_2d(Field2D{seg.field(t_hi + 1, 0), r.nx}, r, st.x, st.y);
+        Footprint2D p1 =
+            NS > 1 ? footprint_2d(Field2D{seg.field(t_hi + 1, NS - 1), r.nx}, r, st.x, st.y)
+                   : p0;
         for (int t = t_hi; t >= 0; --t) {
-            const float4 next = tape[(size_t)max(t - 1, 0) * n + i];
-            const Footprint2D p0 =
-                footprint_2d(Field2D{seg.field(t + 1, 0), r.nx}, r, st.x, st.y);
-            const Footprint2D p1 =
-                NS > 1 ? footprint_2d(Field2D{seg.field(t + 1, NS - 1), r.nx}, r, st.x, st.y)
-                       : p0;
+            // the step before: its state two steps ahead and its footprints one step ahead,
+            // requested before this step's arithmetic (the samples do not depend on it)
+            const float4 next2 = tape[(size_t)max(t - 2, 0) * n + i];
+            Footprint2D q0 = p0, q1 = p1;
+            if (t > 0) {
+                q0 = footprint_2d(Field2D{seg.field(t, 0), r.nx}, r, next.x, next.y);
+                q1 = NS > 1 ? footprint_2d(Field2D{seg.field(t, NS - 1), r.nx}, r, next.x,
+                                           next.y)
+                            : q0;
+            }
             CornerGradients2D g0, g1;
             float gx, gy;
             sample_2d<NS>(r, p0, p1, g0, g1, gx, gy);
@@ -298,6 +309,9 @@ __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
             for (int s = 0; s < NS; ++s) write_record(rec_at + rec + s * 12, rec_v + rec + s * 12,
                                                       out[s]);
             st = next;
+            next = next2;
+            p0 = q0;
+            p1 = q1;
         }
     }
     acone[3 * i] = apx;
