@@ -321,26 +321,40 @@ __global__ __launch_bounds__(kSegThreads) void k_cone_adjoint_segment2d(
 
 constexpr int kRecThreads = 256;
 
-// Largest |contribution| of every step of the segment: one thread per (cone, step), a
-// wavefront maximum, then one atomic maximum on the step's FP32 bits (non-negative floats
-// order like their bits) per wavefront.
+// Largest |contribution| of every step of the segment: a workgroup takes kMaxCones cones of
+// one step (kMaxCones / kRecThreads per thread), reduces their maximum through the wavefronts
+// and LDS, and applies one atomic maximum on the step's FP32 bits (non-negative floats order
+// like their bits).  Few atomics meet on each step's word: with one per wavefront (128 per
+// step at 8192 cones) they queued on those words, and a gradient's reverse sweep at 1024^2
+// took 23.5 instead of 22.5 ms.
+constexpr int kMaxCones = 8 * kRecThreads;
+
 template <int NS>
 __global__ __launch_bounds__(kRecThreads) void k_sample_max(
     Segment2D seg, const float* __restrict__ rec_v, const int32_t* __restrict__ status,
     const int32_t* __restrict__ event_step, uint32_t* __restrict__ step_max, int n) {
-    const int i = blockIdx.x * kRecThreads + threadIdx.x;
     const int t = blockIdx.y;
     float m = 0.0f;
-    if (i < n && t <= last_step(seg, status, event_step, i)) {
-        const float4* v = (const float4*)(rec_v + (((size_t)t * n + i) * NS) * 12);
 #pragma unroll
-        for (int k = 0; k < 3 * NS; ++k) {
-            const float4 q = v[k];
-            m = fmaxf(m, fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w))));
+    for (int k = 0; k < kMaxCones / kRecThreads; ++k) {
+        const int i = blockIdx.x * kMaxCones + k * kRecThreads + threadIdx.x;
+        if (i < n && t <= last_step(seg, status, event_step, i)) {
+            const float4* v = (const float4*)(rec_v + (((size_t)t * n + i) * NS) * 12);
+#pragma unroll
+            for (int q = 0; q < 3 * NS; ++q) {
+                const float4 x = v[q];
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(&step_max[t], __float_as_uint(m));
+    __shared__ float wave_max[kRecThreads / 64];
+    if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kRecThreads / 64; ++w) m = fmaxf(m, wave_max[w]);
+        if (m > 0.0f) atomicMax(&step_max[t], __float_as_uint(m));
+    }
 }
 
 // Every (cone, step) record of steps t_lo .. t_lo + gridDim.y - 1 added into the step's
@@ -434,16 +448,16 @@ hipError_t launch_cone_adjoint_segment2d(const ConeRules& rules, const float* fi
     if (err != hipSuccess || n == 0) return err;
     const Segment2D seg{fields, cells, n_species, seg0, len};
     const dim3 grid((n + kSegThreads - 1) / kSegThreads);
-    const dim3 rec_grid((n + kRecThreads - 1) / kRecThreads, len);
+    const dim3 max_grid((n + kMaxCones - 1) / kMaxCones, len);
     if (n_species > 1) {
         hipLaunchKernelGGL(k_cone_adjoint_segment2d<2>, grid, dim3(kSegThreads), 0, stream,
                            rules, seg, rec_at, rec_v, tape, status, event_step, acone, n);
-        hipLaunchKernelGGL(k_sample_max<2>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
+        hipLaunchKernelGGL(k_sample_max<2>, max_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
                            status, event_step, step_max, n);
     } else {
         hipLaunchKernelGGL(k_cone_adjoint_segment2d<1>, grid, dim3(kSegThreads), 0, stream,
                            rules, seg, rec_at, rec_v, tape, status, event_step, acone, n);
-        hipLaunchKernelGGL(k_sample_max<1>, rec_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
+        hipLaunchKernelGGL(k_sample_max<1>, max_grid, dim3(kRecThreads), 0, stream, seg, rec_v,
                            status, event_step, step_max, n);
     }
     return hipGetLastError();
